@@ -1,0 +1,89 @@
+"""Pins of the oracle's implicit adjoint (gradient of the frequency-shift stack
+with respect to atom positions, charges, R_i and e_i).
+
+The adjoint is not in the paper; it differentiates the equilibrium condition of
+Eq. 1 and the quadrature of Eq. 3.  It is pinned here against central finite
+differences of the whole oracle pipeline (force-field grid -> relaxed scan ->
+frequency shift) and against the translation identity: moving the sample, the
+grid and the tip lattice together changes nothing, so the position gradients
+sum to minus the gradient with respect to a common shift of grid and tips.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2401_14564_amd import workloads as W
+
+
+def _problem():
+    rng = np.random.default_rng(77)
+    atoms = W.random_atoms(rng, 4, [0.8, 0.8, -0.2], [2.2, 2.2, 0.2], q_max=0.3)
+    grid = W.Grid((0.0, 0.0, -1.0), (0.1, 0.1, 0.1), (30, 30, 70))
+    scan = W.Scan(1.23, 1.31, 0.17, 0.19, 3, 3, 8.2, 0.1, 14)
+    fire = W.parity_fire(W.Fire(), f_conv=1e-9, max_iter=50000)
+    dfp = W.DfParams()
+    m = orc.df_m(dfp.A, scan.dz)
+    gdf = np.random.default_rng(5).normal(size=(scan.nz - 2 * m, scan.nx * scan.ny))
+    return atoms, grid, scan, fire, dfp, gdf
+
+
+def _loss(atoms, grid, scan, fire, dfp, gdf, probe=W.Probe()):
+    ff = orc.build_ff(grid, probe, atoms)
+    res = orc.relaxed_scan(grid, ff, probe, fire, scan, polish_tol=1e-13)
+    df = orc.df(res["fz"].T, scan.dz, dfp)           # [nz-2m][ncol]
+    return float(np.sum(gdf * df)), ff, res
+
+
+def test_adjoint_matches_central_differences():
+    atoms, grid, scan, fire, dfp, gdf = _problem()
+    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf)
+    assert np.all(res["gnorm"] < 1e-12)
+    g = orc.scan_backward(grid, ff, W.Probe(), scan, res["cols"], res["r"], gdf, dfp, atoms)
+
+    def fd(mod, h):
+        ap, am = atoms.copy(), atoms.copy()
+        mod(ap, +h)
+        mod(am, -h)
+        Lp = _loss(ap, grid, scan, fire, dfp, gdf)[0]
+        Lm = _loss(am, grid, scan, fire, dfp, gdf)[0]
+        return (Lp - Lm) / (2 * h)
+
+    scale = max(np.abs(g["pos"]).max(), 1e-12)
+    for i in range(atoms.n):
+        for k in range(3):
+            def mod(a, h, i=i, k=k):
+                a.pos[i, k] += h
+            assert g["pos"][i, k] == pytest.approx(fd(mod, 1e-4), rel=2e-4, abs=2e-5 * scale)
+        def modq(a, h, i=i):
+            a.q[i] += h
+        assert g["q"][i] == pytest.approx(fd(modq, 1e-4), rel=2e-4, abs=1e-6)
+        def modR(a, h, i=i):
+            a.R[i] += h
+        assert g["R"][i] == pytest.approx(fd(modR, 1e-4), rel=2e-4, abs=1e-6)
+        he = 1e-3 * atoms.eps[i]
+        def mode(a, h, i=i):
+            a.eps[i] += h
+        assert g["eps"][i] == pytest.approx(fd(mode, he), rel=2e-4, abs=1e-3)
+
+
+def test_adjoint_translation_identity():
+    """sum_i dL/dr_i = -dL/d(delta) with delta a common shift of the grid origin
+    and the tip lattice (the sample-probe system is translation invariant)."""
+    atoms, grid, scan, fire, dfp, gdf = _problem()
+    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf)
+    g = orc.scan_backward(grid, ff, W.Probe(), scan, res["cols"], res["r"], gdf, dfp, atoms)
+    tot = g["pos"].sum(axis=0)
+    # small step: the interpolated field is only continuous across cell faces,
+    # and a common shift of all atoms by 1e-4 A already crosses one here
+    h = 1e-5
+    for k in range(3):
+        vals = []
+        for sgn in (+1, -1):
+            e = np.zeros(3)
+            e[k] = sgn * h
+            g2 = W.Grid(tuple(np.array(grid.origin) + e), grid.step, grid.n)
+            s2 = W.Scan(scan.x0 + e[0], scan.y0 + e[1], scan.dx, scan.dy, scan.nx, scan.ny,
+                        scan.z_top + e[2], scan.dz, scan.nz)
+            vals.append(_loss(atoms, g2, s2, fire, dfp, gdf)[0])
+        dshift = (vals[0] - vals[1]) / (2 * h)
+        assert tot[k] == pytest.approx(-dshift, rel=1e-5, abs=1e-7 * np.abs(g["pos"]).max())
