@@ -1,0 +1,219 @@
+/*
+ * ppm.h -- C ABI of the MI355X probe-particle hot path.
+ *
+ * Paper: Oinonen et al., "Advancing Scanning Probe Microscopy Simulations:
+ * A Decade of Development in Probe-Particle Models" (arXiv 2401.14564).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950):
+ *   1. the force-field grid of Lennard-Jones (Eq. 5) plus point-charge Coulomb
+ *      (Eq. 6) energies and forces (F = -grad E, Sec. 2.2) on a uniform grid
+ *      (Sec. 5.1.1, step 1)                                   -> ppm_build_ff
+ *   2. the relaxed scan: for every tip column, descending in z, the probe
+ *      particle is relaxed by FIRE (Sec. 5.1.1, step 2) under the tip springs
+ *      (Eq. 2) plus the trilinearly interpolated grid force (Eq. 1), and the
+ *      tip force is read out (text after Eq. 2)               -> ppm_relaxed_scan
+ *   3. the frequency shift (Eq. 3, Giessibl), fused into the scan or
+ *      standalone                                             -> ppm_df
+ *   4. the gradient of a scalar function of the frequency-shift stack with
+ *      respect to atom positions, charges and LJ parameters, by implicit
+ *      differentiation of the equilibrium condition of Eq. 1
+ *                                                 -> ppm_relaxed_scan_backward
+ *   5. many molecules of different sizes in one persistent launch per stage
+ *                                                   -> ppm_batch_build_ff,
+ *                                                      ppm_batch_relaxed_scan
+ *
+ * Conventions shared by every entry point
+ *   - Units: lengths in Angstrom, energies in eV, charges in e, forces in eV/A,
+ *     spring constants in eV/A^2; the cantilever stiffness k_cant in N/m and
+ *     f0 in Hz; frequency shifts in Hz.
+ *   - z points up; the probe hangs below its anchor (d0 = (0, 0, -R0) for a
+ *     symmetric tip).
+ *   - Arrays are row-major [z][y][x] with x fastest.  Scan height index 0 is the
+ *     highest anchor position; index k sits at z_top - k*dz.
+ *   - Every array argument is a DEVICE pointer allocated and owned by the
+ *     caller; the library keeps no pointer after the call returns.
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL = the default stream)
+ *     and return without synchronising.  Calls on different streams may run
+ *     concurrently.
+ *   - Every call validates its arguments on the host first and returns a
+ *     ppm_status; on any error nothing is enqueued.  No C++ exception crosses
+ *     the ABI.  PPM_EHIP reports a failed HIP launch (see ppm_last_hip_error).
+ *   - Non-convergence of a relaxation is not an error: it is reported per point
+ *     as a negative iteration count in the probe-state output.
+ */
+#ifndef PPM_H
+#define PPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ppm_status;
+#define PPM_OK 0
+#define PPM_EINVAL (-1)        /* invalid argument (NULL, bad size, bad parameter) */
+#define PPM_ERANGE (-2)        /* a size or index would overflow */
+#define PPM_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
+#define PPM_EUNSUPPORTED (-4)  /* valid but outside what this build implements */
+
+/* Uniform grid.  Voxel (ix, iy, iz) sits at origin + (ix*step[0], iy*step[1],
+ * iz*step[2]); n = (nx, ny, nz).  With periodic_xy = 1 the sample is periodic in
+ * x and y with periods n[0]*step[0] and n[1]*step[1]: each pair uses the
+ * minimum image and is included iff rho^2 < cutoff^2.  With periodic_xy = 0 the
+ * sum runs over all atoms (open boundary) and cutoff is ignored.  For
+ * interpolation the grid wraps in x and y and is clamped in z (the field is
+ * constant above and below the grid). */
+typedef struct {
+    double origin[3];
+    double step[3];
+    int32_t n[3];
+    int32_t periodic_xy;
+    double cutoff;
+} ppm_grid;
+
+/* Probe particle and tip (Sec. 2.1, Eq. 2; Sec. 2.2.1 mixing rules).
+ * R_pp, eps_pp: LJ radius and depth of the probe; q_pp: its point charge.
+ * k_lat: lateral stiffnesses (k_x, k_y); k_rad: radial stiffness (eV/A^2).
+ * d0: rest displacement probe - anchor; R0 = |d0|. */
+typedef struct {
+    double R_pp, eps_pp, q_pp;
+    double k_lat[2];
+    double k_rad;
+    double d0[3];
+} ppm_probe;
+
+/* FIRE relaxation parameters (Bitzek et al. 2006, as used in Sec. 5.1.1).
+ * Per step: from the second step on, with P = G.v: if P > 0 the velocity is
+ * mixed towards the force, v = (1-alpha) v + alpha |v| G/|G|, and after more
+ * than n_min such steps in a row dt = min(dt*f_inc, dt_max), alpha *= f_alpha;
+ * if P <= 0, v = 0, dt *= f_dec, alpha = alpha0.  Then v += G dt/mass,
+ * r += v dt.  A point is converged when |G|_2 < f_conv (eV/A); after max_iter
+ * steps it is recorded as not converged.  dt, alpha and v restart at every
+ * height. */
+typedef struct {
+    double dt0, dt_max, f_inc, f_dec, alpha0, f_alpha, mass, f_conv;
+    int32_t n_min, max_iter;
+} ppm_fire;
+
+/* Tip lattice: anchor of column (ix, iy) at height index k is
+ * (x0 + ix*dx, y0 + iy*dy, z_top - k*dz), ix < nx, iy < ny, k < nz.
+ * At k = 0 the probe starts at anchor + d0; at k > 0 at the previous height's
+ * relaxed position moved by the anchor's step (warm start). */
+typedef struct {
+    double x0, y0, dx, dy;
+    int32_t nx, ny;
+    double z_top, dz;
+    int32_t nz;
+} ppm_scan;
+
+/* Frequency shift (Eq. 3): A = peak-to-peak amplitude (A), f0 (Hz), k_cant
+ * (N/m).  The integral is evaluated exactly for the piecewise-linear
+ * interpolant of the Fz samples: m = ceil(A/(2 dz) - 1e-9) samples on each side
+ * of the centre; output o is centred at scan index o + m ("valid" outputs,
+ * nz - 2m of them). */
+typedef struct {
+    double A, f0, k_cant;
+} ppm_df_params;
+
+/* Message for a status code (static storage). */
+const char *ppm_status_string(ppm_status s);
+
+/* The hipError_t of the last failed HIP call made by this library on the
+ * calling thread (0 if none). */
+int32_t ppm_last_hip_error(void);
+
+/* Half-width m of the frequency-shift stencil for amplitude A and step dz,
+ * or -1 if A <= 0 or dz <= 0. */
+int32_t ppm_df_half_width(double A, double dz);
+
+/*
+ * ppm_build_ff -- force-field grid (Sec. 5.1.1 step 1; Eq. 5, Eq. 6, Sec. 2.2).
+ * For every voxel v, with e_iP = sqrt(eps_i eps_pp), R_iP = R_i + R_pp,
+ * kq_i = k_e q_i q_pp (k_e = 14.3996454784 eV*A/e^2), rho = |v - r_i|:
+ *   E(v) = sum_i e_iP [(R_iP/rho)^12 - 2 (R_iP/rho)^6] + kq_i/rho
+ *   F(v) = sum_i {12 e_iP [(R_iP/rho)^12 - (R_iP/rho)^6]/rho^2 + kq_i/rho^3} (v - r_i)
+ * in:  pos[n_atoms][3], q[n_atoms], R[n_atoms], eps[n_atoms] (FP64, device);
+ *      n_atoms >= 0 (0 gives the zero field).
+ * out: ff[nz][ny][nx][4] = (Fx, Fy, Fz, E), FP32, device.
+ * Voxels closer than ~1e-3 A to an atom may hold inf.
+ * Errors: PPM_EINVAL for NULL pointers (when n_atoms > 0), n[i] < 2, steps
+ * <= 0, or periodic_xy with cutoff <= 0 or cutoff + 4 A >= min(Lx, Ly)/2;
+ * PPM_ERANGE if the grid has 2^31 voxels or more.
+ */
+ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                        const double *pos, const double *q, const double *R,
+                        const double *eps, float *ff, void *stream);
+
+/*
+ * ppm_relaxed_scan -- relaxed scan with optional fused frequency shift
+ * (Sec. 2.1 Eq. 1-3, Sec. 5.1.1 step 2).
+ * in:  ff[nz][ny][nx][4] from ppm_build_ff (only Fx, Fy, Fz are read).
+ * out (each may be NULL, at least one must be given):
+ *   fz[scan.nz][scan.ny][scan.nx]  tip force Fz_tip = -F^T_z at the relaxed
+ *                                   probe position (eV/A)
+ *   pp[scan.nz][scan.ny][scan.nx][4] (ux, uy, uz, iters): relaxed probe
+ *                                   position minus its rest position
+ *                                   anchor + d0 (A), and the FIRE step count
+ *                                   (negative if not converged)
+ *   df[scan.nz-2m][scan.ny][scan.nx] frequency shift (Hz); requires dfp and
+ *                                   scan.nz >= 2m+1; m <= 32.
+ * Errors: PPM_EINVAL for a bad grid/probe/fire/scan (f_conv <= 0, dt <= 0,
+ * mass <= 0, negative stiffness, |d0| == 0, nz < 1, max_iter < 1), df without
+ * dfp or with too few heights, or all outputs NULL; PPM_EUNSUPPORTED if m > 32.
+ */
+ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                            const ppm_fire *fire, const ppm_scan *scan, float *fz,
+                            float *pp, const ppm_df_params *dfp, float *df, void *stream);
+
+/*
+ * ppm_df -- standalone frequency shift of an Fz stack (Eq. 3).
+ * in:  fz[nz][ny][nx] in scan-index order (index 0 highest), height step dz.
+ * out: df[nz-2m][ny][nx] (Hz).
+ * Errors: PPM_EINVAL for NULL pointers, nz < 2m+1, ny or nx < 1, dz <= 0,
+ * A <= 0, k_cant <= 0; PPM_EUNSUPPORTED if m > 32.
+ */
+ppm_status ppm_df(const float *fz, int32_t nz, int32_t ny, int32_t nx, double dz,
+                  const ppm_df_params *dfp, float *df, void *stream);
+
+/*
+ * Workspace size (bytes, 256-byte aligned) needed by ppm_relaxed_scan_backward
+ * for this scan and atom count.
+ */
+size_t ppm_backward_workspace_bytes(const ppm_scan *scan, int32_t n_atoms);
+
+/*
+ * ppm_relaxed_scan_backward -- gradient of L with respect to the atoms, given
+ * grad_df = dL/d(df) for the stack produced by ppm_relaxed_scan with the same
+ * arguments.  At every relaxed point G(r*) = F^T(r*) + F^S_h(r*) = 0 (Eq. 1), so
+ * with J = dG/dr (3x3, trilinear cell Jacobian plus spring Jacobian),
+ *   gbar_k = dL/dFz_k  (transposed Eq. 3 weights),
+ *   mu = J^{-T} (gbar_k * grad_r F^T_z),
+ *   dL/dtheta_i += mu . sum_corners w_c d f_i(v_c)/d theta_i
+ * where f_i(v) is atom i's pair force at grid corner v, recomputed (the grid
+ * gradient is never stored).  theta_i = (r_i, q_i, R_i, eps_i).
+ * in:  grid, ff, probe, scan, dfp as in the forward call; pos, q, R, eps as in
+ *      ppm_build_ff; pp = the forward call's probe-state output (required);
+ *      grad_df[nz-2m][ny][nx] (FP32).
+ * out: g_pos[n_atoms][3], g_q, g_R, g_eps (FP64, overwritten).
+ * workspace: device buffer of at least ppm_backward_workspace_bytes() bytes.
+ * Points recorded as not converged contribute nothing.  The result is
+ * deterministic (fixed reduction order).
+ * Errors: as ppm_relaxed_scan, plus PPM_EINVAL for NULL pointers or a
+ * workspace that is too small.
+ */
+ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
+                                     const ppm_probe *probe, const ppm_scan *scan,
+                                     const ppm_df_params *dfp, int32_t n_atoms,
+                                     const double *pos, const double *q, const double *R,
+                                     const double *eps, const float *pp,
+                                     const float *grad_df, double *g_pos, double *g_q,
+                                     double *g_R, double *g_eps, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPM_H */

@@ -85,8 +85,11 @@ static void orc_disp(const double *r, const double *a, const double *g,
  * (Eq. 5 + Eq. 6, F = -grad E):
  *   E   = sum_i e_iP [ (R_iP/rho)^12 - 2 (R_iP/rho)^6 ] + kq_i / rho
  *   F   = sum_i { 12 e_iP [ (R_iP/rho)^12 - (R_iP/rho)^6 ] / rho^2 + kq_i / rho^3 } (r - r_i)
- * out[4] = Fx, Fy, Fz, E.  If scale != NULL: scale[0] = sum_i |f_i|,
- * scale[1] = sum_i |E_i|, scale[2] = min rho, scale[3] = min |rho^2 - rc^2|.
+ * out[4] = Fx, Fy, Fz, E.  If scale != NULL it receives the magnitude sums of
+ * every term that enters the sums (the scale of their rounding error):
+ * scale[0] = sum_i [12 e_iP ((R/rho)^12 + (R/rho)^6)/rho^2 + |kq_i|/rho^3] rho,
+ * scale[1] = sum_i e_iP ((R/rho)^12 + 2 (R/rho)^6) + |kq_i|/rho,
+ * scale[2] = min rho, scale[3] = min |rho^2 - rc^2|.
  * With periodic_xy only pairs with rho^2 < rc^2 contribute.
  */
 void orc_point(const double *r, int na, const double *pos, const double *RiP,
@@ -117,8 +120,8 @@ void orc_point(const double *r, int na, const double *pos, const double *RiP,
         Fx += phi * d[0];
         Fy += phi * d[1];
         Fz += phi * d[2];
-        sF += fabs(phi) * rho;
-        sE += fabs(eLJ) + fabs(eC);
+        sF += (12.0 * eiP[i] * (s12 + s6) / rho2 + fabs(kqi[i]) / (rho2 * rho)) * rho;
+        sE += eiP[i] * (s12 + 2.0 * s6) + fabs(eC);
     }
     out[0] = Fx; out[1] = Fy; out[2] = Fz; out[3] = E;
     if (scale) { scale[0] = sF; scale[1] = sE; scale[2] = rmin; scale[3] = tie; }

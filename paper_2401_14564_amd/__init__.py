@@ -1,0 +1,159 @@
+"""MI355X-native probe-particle model hot path (arXiv 2401.14564).
+
+Python surface over libppm (include/ppm.h).  PyTorch provides device memory and
+the current HIP stream; every computation runs in the library's HIP kernels.
+
+  build_ff(grid, probe, atoms)                 -> ff  [nz, ny, nx, 4] float32
+  relaxed_scan(grid, ff, probe, fire, scan, dfp=None, pp=True, fz=True)
+                                               -> dict(fz, pp, df)
+  df(fz, dz, dfp)                              -> df  [nz-2m, ny, nx] float32
+  relaxed_scan_backward(...)                   -> dict(pos, q, R, eps) float64
+  AFMStack.apply(pos, q, R, eps, grid, probe, fire, scan, dfp) -> df  (autograd)
+
+Parameter objects are read by attribute (see workloads.py for the dataclasses).
+Atoms may be given as a workloads.Atoms or as a tuple of device tensors
+(pos [n,3], q [n], R [n], eps [n]) in float64.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+__all__ = ["build_ff", "relaxed_scan", "df", "df_half_width", "relaxed_scan_backward",
+           "AFMStack", "atoms_to_device"]
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _device():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libppm needs a HIP device (torch.cuda.is_available() is False)")
+    return torch.device("cuda")
+
+
+def atoms_to_device(atoms, device=None):
+    """(pos, q, R, eps) as contiguous float64 device tensors."""
+    device = device or _device()
+    if isinstance(atoms, (tuple, list)):
+        pos, q, R, eps = atoms
+    else:
+        pos, q, R, eps = atoms.pos, atoms.q, atoms.R, atoms.eps
+
+    def t(x):
+        return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+    return t(pos).reshape(-1, 3), t(q).reshape(-1), t(R).reshape(-1), t(eps).reshape(-1)
+
+
+def df_half_width(A: float, dz: float) -> int:
+    return int(_lib.lib().ppm_df_half_width(float(A), float(dz)))
+
+
+def build_ff(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Force-field grid (Fx, Fy, Fz, E) [nz, ny, nx, 4], float32, on the device."""
+    L = _lib.lib()
+    pos, q, R, eps = atoms_to_device(atoms)
+    nx, ny, nz = (int(v) for v in grid.n)
+    if out is None:
+        out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=pos.device)
+    assert out.shape == (nz, ny, nx, 4) and out.dtype == torch.float32 and out.is_contiguous()
+    st = L.ppm_build_ff(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
+                        _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps), _lib.ptr(out),
+                        _stream())
+    _lib.check(st, "ppm_build_ff")
+    return out
+
+
+def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
+                 out: dict | None = None) -> dict:
+    """Relaxed scan.  Returns dict with 'fz' [nz,ny,nx] (tip force, eV/A), 'pp'
+    [nz,ny,nx,4] (probe displacement from rest and FIRE steps, negative if not
+    converged) and 'df' [nz-2m,ny,nx] (Hz, when dfp is given)."""
+    L = _lib.lib()
+    dev = ff.device
+    nz, ny, nx = int(scan.nz), int(scan.ny), int(scan.nx)
+    out = dict(out or {})
+    if fz and "fz" not in out:
+        out["fz"] = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    if pp and "pp" not in out:
+        out["pp"] = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev)
+    if dfp is not None and "df" not in out:
+        m = df_half_width(dfp.A, scan.dz)
+        out["df"] = torch.empty((max(nz - 2 * m, 0), ny, nx), dtype=torch.float32, device=dev)
+    st = L.ppm_relaxed_scan(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
+                            _lib.fire_struct(fire), _lib.scan_struct(scan),
+                            _lib.ptr(out.get("fz")), _lib.ptr(out.get("pp")),
+                            None if dfp is None else _lib.df_struct(dfp),
+                            _lib.ptr(out.get("df")), _stream())
+    _lib.check(st, "ppm_relaxed_scan")
+    return out
+
+
+def df(fz: torch.Tensor, dz: float, dfp, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Frequency shift of an Fz stack [nz, ny, nx] (scan-index order)."""
+    L = _lib.lib()
+    nz, ny, nx = fz.shape
+    m = df_half_width(dfp.A, dz)
+    if out is None:
+        out = torch.empty((max(nz - 2 * m, 0), ny, nx), dtype=torch.float32, device=fz.device)
+    st = L.ppm_df(_lib.ptr(fz.contiguous()), nz, ny, nx, float(dz), _lib.df_struct(dfp),
+                  _lib.ptr(out), _stream())
+    _lib.check(st, "ppm_df")
+    return out
+
+
+def relaxed_scan_backward(grid, ff, probe, scan, dfp, atoms, pp, grad_df,
+                          workspace: torch.Tensor | None = None) -> dict:
+    """Gradient of sum(grad_df * df) w.r.t. atom positions, charges, R and eps
+    (float64 device tensors)."""
+    L = _lib.lib()
+    pos, q, R, eps = atoms_to_device(atoms)
+    n = int(q.numel())
+    sc = _lib.scan_struct(scan)
+    nbytes = int(L.ppm_backward_workspace_bytes(sc, n))
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=ff.device)
+    g = {k: torch.empty(s, dtype=torch.float64, device=ff.device)
+         for k, s in (("pos", (n, 3)), ("q", (n,)), ("R", (n,)), ("eps", (n,)))}
+    gdf = grad_df.to(torch.float32).contiguous()
+    st = L.ppm_relaxed_scan_backward(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
+                                     sc, _lib.df_struct(dfp), n, _lib.ptr(pos), _lib.ptr(q),
+                                     _lib.ptr(R), _lib.ptr(eps), _lib.ptr(pp), _lib.ptr(gdf),
+                                     _lib.ptr(g["pos"]), _lib.ptr(g["q"]), _lib.ptr(g["R"]),
+                                     _lib.ptr(g["eps"]), _lib.ptr(workspace), workspace.numel(),
+                                     _stream())
+    _lib.check(st, "ppm_relaxed_scan_backward")
+    return g
+
+
+class _Params:
+    """Attribute holder used to rebuild grid/probe/... objects from tensors."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+class AFMStack(torch.autograd.Function):
+    """df = AFMStack.apply(pos, q, R, eps, grid, probe, fire, scan, dfp)
+
+    Forward: force-field grid -> relaxed scan -> frequency shift (all HIP).
+    Backward: implicit adjoint of the relaxed equilibria (ppm_relaxed_scan_backward)."""
+
+    @staticmethod
+    def forward(ctx, pos, q, R, eps, grid, probe, fire, scan, dfp):
+        atoms = (pos.detach(), q.detach(), R.detach(), eps.detach())
+        ff = build_ff(grid, probe, atoms)
+        res = relaxed_scan(grid, ff, probe, fire, scan, dfp=dfp, fz=False, pp=True)
+        ctx.save_for_backward(pos.detach(), q.detach(), R.detach(), eps.detach(), ff, res["pp"])
+        ctx.params = (grid, probe, scan, dfp)
+        return res["df"]
+
+    @staticmethod
+    def backward(ctx, grad_df):
+        pos, q, R, eps, ff, pp = ctx.saved_tensors
+        grid, probe, scan, dfp = ctx.params
+        g = relaxed_scan_backward(grid, ff, probe, scan, dfp, (pos, q, R, eps), pp, grad_df)
+        return (g["pos"].to(pos.dtype), g["q"].to(q.dtype), g["R"].to(R.dtype),
+                g["eps"].to(eps.dtype), None, None, None, None, None)

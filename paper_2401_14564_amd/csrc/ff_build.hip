@@ -1,0 +1,169 @@
+// ff_build.hip -- force-field grid projection on gfx950.
+//
+// Every voxel sums the Lennard-Jones (Eq. 5) and point-charge Coulomb (Eq. 6)
+// energy of the probe particle and the force F = -grad E over the sample's
+// atoms (Sec. 2.2, Sec. 5.1.1 step 1).  The work is O(n_atoms * n_voxels) and
+// bound by the FP32 vector ALU; it is not a dense contraction, so no MFMA.
+//
+// Design:
+//  * A block of BX x BY threads owns a brick of BX x BY x NZB voxels; each
+//    thread owns NZB voxels of one z-column, so dx, dy and dx^2+dy^2 are shared
+//    by NZB pairs (register blocking along z).  Threads of a wave cover 64
+//    consecutive x-voxels, so the float4 stores of a wave are one contiguous
+//    1 KiB run.
+//  * Atoms are staged through LDS in chunks of BX*BY.  While staging, each atom's
+//    mixing rules are applied once (R_iP = R_i + R_PP, e_iP = sqrt(e_i e_PP),
+//    kq_i = k_e q_i q_PP) and its position is made brick-local in FP64 before
+//    rounding to FP32: FP32 differences of small local coordinates keep the
+//    relative error of rho near 1e-7, which absolute FP32 coordinates (ulp of
+//    24 A = 1.9e-6 A) would not.  The inner loop reads one atom per step with
+//    wave-uniform LDS addresses (broadcast).
+//  * Periodic samples: each atom takes, per brick, the image nearest to the
+//    brick centre (exact minimum image for every voxel of the brick as long as
+//    cutoff + brick half-diagonal < L/2, which the host checks), atoms beyond
+//    cutoff + half-diagonal of the centre are dropped with a deterministic
+//    ballot compaction, and each pair is masked by rho^2 < cutoff^2.
+#include "ppm_kernels.h"
+
+namespace ppm {
+namespace {
+
+template <int BX, int BY, int NZB, bool PERIODIC>
+__global__ __launch_bounds__(BX * BY) void ff_build_kernel(
+    const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
+    const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
+{
+    constexpr int NT = BX * BY;
+    constexpr int NW = NT / 64;
+    __shared__ float4 s_geo[NT];   // brick-local (x, y, z) and R_iP^2
+    __shared__ float4 s_par[NT];   // e_iP, 12 e_iP, kq_i
+    __shared__ int s_wcnt[NW];
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * BX + tx;
+    const int ix0 = blockIdx.x * BX, iy0 = blockIdx.y * BY, iz0 = blockIdx.z * NZB;
+
+    // brick centre in FP64
+    const double hcx = 0.5 * (BX - 1), hcy = 0.5 * (BY - 1), hcz = 0.5 * (NZB - 1);
+    const double cx = a.ox + (ix0 + hcx) * a.hx;
+    const double cy = a.oy + (iy0 + hcy) * a.hy;
+    const double cz = a.oz + (iz0 + hcz) * a.hz;
+    // this thread's voxels relative to the brick centre, exactly rounded
+    const float vx = (float)((tx - hcx) * a.hx);
+    const float vy = (float)((ty - hcy) * a.hy);
+    float vz[NZB];
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) vz[k] = (float)((k - hcz) * a.hz);
+
+    float Fx[NZB], Fy[NZB], Fz[NZB], E[NZB];
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) Fx[k] = Fy[k] = Fz[k] = E[k] = 0.0f;
+
+    for (int base = 0; base < a.n_atoms; base += NT) {
+        const int i = base + tid;
+        bool keep = false;
+        float4 geo = make_float4(0.f, 0.f, 0.f, 0.f), par = geo;
+        if (i < a.n_atoms) {
+            double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
+            if (PERIODIC) {
+                dx -= a.Lx * rint(dx / a.Lx);
+                dy -= a.Ly * rint(dy / a.Ly);
+                keep = dx * dx + dy * dy + dz * dz < a.cull2;
+            } else {
+                keep = true;
+            }
+            const double RiP = R[i] + a.R_pp;
+            const double eiP = sqrt(eps[i] * a.eps_pp);
+            geo = make_float4((float)dx, (float)dy, (float)dz, (float)(RiP * RiP));
+            par = make_float4((float)eiP, (float)(12.0 * eiP), (float)(a.kq_pp * q[i]), 0.f);
+        }
+        int cnt, slot;
+        if (PERIODIC) {
+            // deterministic compaction: wave ballot + per-wave offsets
+            const int lane = tid & 63, wv = tid >> 6;
+            const unsigned long long m = __ballot(keep);
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wcnt[wv] = __popcll(m);
+            __syncthreads();
+            int off = 0;
+            cnt = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                off += (w < wv) ? s_wcnt[w] : 0;
+                cnt += s_wcnt[w];
+            }
+            slot = off + before;
+        } else {
+            cnt = min(NT, a.n_atoms - base);
+            slot = tid;
+        }
+        if (keep) {
+            s_geo[slot] = geo;
+            s_par[slot] = par;
+        }
+        __syncthreads();
+
+        for (int j = 0; j < cnt; ++j) {
+            const float4 g = s_geo[j];
+            const float4 p = s_par[j];
+            const float dx = vx - g.x, dy = vy - g.y;
+            const float dxy2 = fmaf(dx, dx, dy * dy);
+#pragma unroll
+            for (int k = 0; k < NZB; ++k) {
+                const float dz = vz[k] - g.z;
+                const float r2 = fmaf(dz, dz, dxy2);
+                float ir = __builtin_amdgcn_rsqf(r2);
+                if (PERIODIC) ir = (r2 < a.rc2) ? ir : 0.0f;
+                const float ir2 = ir * ir;
+                const float s2 = g.w * ir2;
+                const float s6 = s2 * s2 * s2;
+                const float s12 = s6 * s6;
+                const float ec = p.z * ir;
+                E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + ec;
+                const float f = fmaf(p.y, s12 - s6, ec) * ir2;
+                Fx[k] = fmaf(f, dx, Fx[k]);
+                Fy[k] = fmaf(f, dy, Fy[k]);
+                Fz[k] = fmaf(f, dz, Fz[k]);
+            }
+        }
+        __syncthreads();
+    }
+
+    const int ix = ix0 + tx, iy = iy0 + ty;
+    if (ix < a.nx && iy < a.ny) {
+#pragma unroll
+        for (int k = 0; k < NZB; ++k) {
+            const int iz = iz0 + k;
+            if (iz < a.nz)
+                ff[((size_t)iz * a.ny + iy) * a.nx + ix] = make_float4(Fx[k], Fy[k], Fz[k], E[k]);
+        }
+    }
+}
+
+constexpr int kBX = 64, kBY = 4, kNZB = 8;
+
+}  // namespace
+
+// Brick geometry used by the launcher (the host validates the periodic cutoff
+// against its half-diagonal).
+double ff_brick_half_diagonal(double hx, double hy, double hz)
+{
+    const double ex = 0.5 * (kBX - 1) * hx, ey = 0.5 * (kBY - 1) * hy, ez = 0.5 * (kNZB - 1) * hz;
+    return sqrt(ex * ex + ey * ey + ez * ez);
+}
+
+hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
+                           const double *R, const double *eps, float4 *ff, hipStream_t stream)
+{
+    dim3 block(kBX, kBY, 1);
+    dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
+    if (a.Lx > 0.0)
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, true>), grid, block, 0, stream,
+                           a, pos, q, R, eps, ff);
+    else
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false>), grid, block, 0, stream,
+                           a, pos, q, R, eps, ff);
+    return hipGetLastError();
+}
+
+}  // namespace ppm

@@ -1,0 +1,350 @@
+// ppm_api.hip -- host side of the C ABI declared in include/ppm.h: argument
+// validation, derived constants, and kernel launches.  Nothing here computes
+// per-voxel or per-point results; every step of the path runs in the kernels.
+#include <math.h>
+#include <string.h>
+
+#include "ppm.h"
+#include "ppm_kernels.h"
+
+namespace ppm {
+double ff_brick_half_diagonal(double hx, double hy, double hz);
+}
+
+using namespace ppm;
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+ppm_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return PPM_OK;
+    g_last_hip_error = (int32_t)e;
+    return PPM_EHIP;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+ppm_status check_grid(const ppm_grid *g)
+{
+    if (!g) return PPM_EINVAL;
+    for (int i = 0; i < 3; ++i) {
+        if (g->n[i] < 2) return PPM_EINVAL;
+        if (!finite_pos(g->step[i]) || !isfinite(g->origin[i])) return PPM_EINVAL;
+    }
+    const double nv = (double)g->n[0] * g->n[1] * g->n[2];
+    if (nv >= 2147483648.0) return PPM_ERANGE;
+    if (g->periodic_xy != 0 && g->periodic_xy != 1) return PPM_EINVAL;
+    return PPM_OK;
+}
+
+ppm_status check_probe(const ppm_probe *p)
+{
+    if (!p) return PPM_EINVAL;
+    if (!isfinite(p->R_pp) || !(p->eps_pp >= 0.0) || !isfinite(p->eps_pp) || !isfinite(p->q_pp))
+        return PPM_EINVAL;
+    if (!(p->k_lat[0] >= 0.0) || !(p->k_lat[1] >= 0.0) || !(p->k_rad >= 0.0)) return PPM_EINVAL;
+    if (!isfinite(p->k_lat[0]) || !isfinite(p->k_lat[1]) || !isfinite(p->k_rad)) return PPM_EINVAL;
+    const double R0 = sqrt(p->d0[0] * p->d0[0] + p->d0[1] * p->d0[1] + p->d0[2] * p->d0[2]);
+    if (!finite_pos(R0)) return PPM_EINVAL;
+    return PPM_OK;
+}
+
+ppm_status check_fire(const ppm_fire *f)
+{
+    if (!f) return PPM_EINVAL;
+    if (!finite_pos(f->dt0) || !finite_pos(f->dt_max) || !finite_pos(f->mass) ||
+        !finite_pos(f->f_conv))
+        return PPM_EINVAL;
+    if (!finite_pos(f->f_inc) || !finite_pos(f->f_dec) || !isfinite(f->alpha0) ||
+        !isfinite(f->f_alpha))
+        return PPM_EINVAL;
+    if (f->alpha0 < 0.0 || f->alpha0 > 1.0 || f->f_alpha < 0.0 || f->f_alpha > 1.0)
+        return PPM_EINVAL;
+    if (f->n_min < 0 || f->max_iter < 1) return PPM_EINVAL;
+    return PPM_OK;
+}
+
+ppm_status check_scan(const ppm_scan *s)
+{
+    if (!s) return PPM_EINVAL;
+    if (s->nx < 1 || s->ny < 1 || s->nz < 1) return PPM_EINVAL;
+    if (!isfinite(s->x0) || !isfinite(s->y0) || !isfinite(s->dx) || !isfinite(s->dy) ||
+        !isfinite(s->z_top) || !isfinite(s->dz))
+        return PPM_EINVAL;
+    if (s->nz > 1 && !finite_pos(s->dz)) return PPM_EINVAL;
+    const double n = (double)s->nx * s->ny * s->nz;
+    if (n >= 1099511627776.0) return PPM_ERANGE;   // 2^40 points
+    return PPM_OK;
+}
+
+int32_t df_half_width(double A, double dz)
+{
+    if (!finite_pos(A) || !finite_pos(dz)) return -1;
+    const double m = ceil(A / (2.0 * dz) - 1e-9);
+    if (m > 1e6) return -1;
+    return (int32_t)m;
+}
+
+// Exact weights of Eq. 3 for the piecewise-linear interpolant of the samples
+// (integrals of z/sqrt(a^2-z^2) and z^2/sqrt(a^2-z^2) on each segment), with the
+// prefactor -(f0/2k)(8/(pi A^2)) (N/m per eV/A^2) folded in, laid out for the
+// ring buffer: W[2K - lag] multiplies the sample `lag` heights before the newest,
+// i.e. the sample at physical offset j = lag - m from the centre.
+ppm_status df_weights(const ppm_df_params *p, double dz, int m, DfWeights *W)
+{
+    if (!p || !finite_pos(p->A) || !finite_pos(p->k_cant) || !isfinite(p->f0))
+        return PPM_EINVAL;
+    if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+    memset(W, 0, sizeof(*W));
+    const double a = 0.5 * p->A;
+    double w[2 * kMaxDfHalfWidth + 1] = {0};
+    for (int j = -m; j < m; ++j) {
+        const double z0 = j * dz, z1 = (j + 1) * dz;
+        const double lo = fmax(z0, -a), hi = fmin(z1, a);
+        if (!(lo < hi)) continue;
+        const double rl = sqrt(fmax(a * a - lo * lo, 0.0)), rh = sqrt(fmax(a * a - hi * hi, 0.0));
+        const double I1 = rl - rh;   // int z / sqrt(a^2 - z^2)
+        const double I2 = 0.5 * a * a * (asin(fmin(hi / a, 1.0)) - asin(fmax(lo / a, -1.0))) -
+                          0.5 * (hi * rh - lo * rl);   // int z^2 / sqrt(a^2 - z^2)
+        w[j + m] += (z1 * I1 - I2) / dz;
+        w[j + 1 + m] += (I2 - z0 * I1) / dz;
+    }
+    const double C = -(p->f0 / (2.0 * p->k_cant)) * (8.0 / (M_PI * p->A * p->A)) *
+                     kEvPerA2InNewtonPerM;
+    const int K = kMaxDfHalfWidth;
+    for (int lag = 0; lag <= 2 * m; ++lag) W->w[2 * K - lag] = (float)(C * w[lag]);
+    // lag = m + j  ->  w index j + m = lag
+    return PPM_OK;
+}
+
+ScanArgs make_scan_args(const ppm_grid *g, const ppm_probe *p, const ppm_fire *f,
+                        const ppm_scan *s)
+{
+    ScanArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ox = g->origin[0];
+    a.oy = g->origin[1];
+    a.oz = g->origin[2];
+    a.ihx = 1.0 / g->step[0];
+    a.ihy = 1.0 / g->step[1];
+    a.ihz = 1.0 / g->step[2];
+    a.gnx = g->n[0];
+    a.gny = g->n[1];
+    a.gnz = g->n[2];
+    a.kx = p->k_lat[0];
+    a.ky = p->k_lat[1];
+    a.kR = p->k_rad;
+    a.d0x = p->d0[0];
+    a.d0y = p->d0[1];
+    a.d0z = p->d0[2];
+    a.R0 = sqrt(p->d0[0] * p->d0[0] + p->d0[1] * p->d0[1] + p->d0[2] * p->d0[2]);
+    if (f) {
+        a.dt0 = f->dt0;
+        a.dt_max = f->dt_max;
+        a.f_inc = f->f_inc;
+        a.f_dec = f->f_dec;
+        a.alpha0 = f->alpha0;
+        a.f_alpha = f->f_alpha;
+        a.inv_mass = 1.0 / f->mass;
+        a.f_conv2 = f->f_conv * f->f_conv;
+        a.n_min = f->n_min;
+        a.max_iter = f->max_iter;
+    }
+    a.x0 = s->x0;
+    a.y0 = s->y0;
+    a.sdx = s->dx;
+    a.sdy = s->dy;
+    a.z_top = s->z_top;
+    a.sdz = s->dz;
+    a.snx = s->nx;
+    a.sny = s->ny;
+    a.snz = s->nz;
+    return a;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Chunking of the relaxed points for the atom scatter of the backward pass.
+void backward_chunks(const ppm_scan *s, int *n_blocks, int *per_block)
+{
+    const size_t n_eq = (size_t)s->nx * s->ny * s->nz;
+    size_t nb = (n_eq + 31) / 32;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    const size_t per = (n_eq + nb - 1) / nb;
+    *per_block = (int)(per < 1 ? 1 : per);
+    *n_blocks = (int)((n_eq + *per_block - 1) / *per_block);
+    if (*n_blocks < 1) *n_blocks = 1;
+}
+
+size_t backward_record_bytes(const ppm_scan *s)
+{
+    return align256((size_t)s->nx * s->ny * s->nz * 48);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ppm_status_string(ppm_status s)
+{
+    switch (s) {
+    case PPM_OK: return "ok";
+    case PPM_EINVAL: return "invalid argument";
+    case PPM_ERANGE: return "size out of range";
+    case PPM_EHIP: return "HIP runtime error";
+    case PPM_EUNSUPPORTED: return "unsupported by this build";
+    default: return "unknown status";
+    }
+}
+
+int32_t ppm_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t ppm_df_half_width(double A, double dz) { return df_half_width(A, dz); }
+
+ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                        const double *pos, const double *q, const double *R,
+                        const double *eps, float *ff, void *stream)
+{
+    ppm_status st = check_grid(grid);
+    if (st != PPM_OK) return st;
+    if ((st = check_probe(probe)) != PPM_OK) return st;
+    if (n_atoms < 0 || !ff) return PPM_EINVAL;
+    if (n_atoms > 0 && (!pos || !q || !R || !eps)) return PPM_EINVAL;
+    FFArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ox = grid->origin[0];
+    a.oy = grid->origin[1];
+    a.oz = grid->origin[2];
+    a.hx = grid->step[0];
+    a.hy = grid->step[1];
+    a.hz = grid->step[2];
+    a.nx = grid->n[0];
+    a.ny = grid->n[1];
+    a.nz = grid->n[2];
+    a.n_atoms = n_atoms;
+    a.R_pp = probe->R_pp;
+    a.eps_pp = probe->eps_pp;
+    a.kq_pp = kCoulomb * probe->q_pp;
+    if (grid->periodic_xy) {
+        const double Lx = grid->n[0] * grid->step[0], Ly = grid->n[1] * grid->step[1];
+        const double hd = ff_brick_half_diagonal(grid->step[0], grid->step[1], grid->step[2]);
+        if (!finite_pos(grid->cutoff) || grid->cutoff + hd >= 0.5 * fmin(Lx, Ly))
+            return PPM_EINVAL;
+        a.Lx = Lx;
+        a.Ly = Ly;
+        a.rc2 = (float)(grid->cutoff * grid->cutoff);
+        a.cull2 = (grid->cutoff + hd) * (grid->cutoff + hd);
+    }
+    return hip_status(launch_build_ff(a, pos, q, R, eps, reinterpret_cast<float4 *>(ff),
+                                      (hipStream_t)stream));
+}
+
+ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                            const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
+                            const ppm_df_params *dfp, float *df, void *stream)
+{
+    ppm_status st;
+    if ((st = check_grid(grid)) != PPM_OK) return st;
+    if ((st = check_probe(probe)) != PPM_OK) return st;
+    if ((st = check_fire(fire)) != PPM_OK) return st;
+    if ((st = check_scan(scan)) != PPM_OK) return st;
+    if (!ff || (!fz && !pp && !df)) return PPM_EINVAL;
+    ScanArgs a = make_scan_args(grid, probe, fire, scan);
+    DfWeights W;
+    memset(&W, 0, sizeof(W));
+    a.m = 0;
+    if (df) {
+        if (!dfp) return PPM_EINVAL;
+        const int m = df_half_width(dfp->A, scan->dz);
+        if (m < 1) return PPM_EINVAL;
+        if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+        if (scan->nz < 2 * m + 1) return PPM_EINVAL;
+        if ((st = df_weights(dfp, scan->dz, m, &W)) != PPM_OK) return st;
+        a.m = m;
+        a.ndf = scan->nz - 2 * m;
+    }
+    return hip_status(launch_relaxed_scan(a, W, reinterpret_cast<const float4 *>(ff), fz,
+                                          reinterpret_cast<float4 *>(pp), df,
+                                          (hipStream_t)stream));
+}
+
+ppm_status ppm_df(const float *fz, int32_t nz, int32_t ny, int32_t nx, double dz,
+                  const ppm_df_params *dfp, float *df, void *stream)
+{
+    if (!fz || !df || !dfp || ny < 1 || nx < 1 || !finite_pos(dz)) return PPM_EINVAL;
+    const int m = df_half_width(dfp->A, dz);
+    if (m < 1) return PPM_EINVAL;
+    if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+    if (nz < 2 * m + 1) return PPM_EINVAL;
+    if ((double)nx * ny * nz >= 2147483648.0 * 4.0) return PPM_ERANGE;
+    DfWeights W;
+    ppm_status st = df_weights(dfp, dz, m, &W);
+    if (st != PPM_OK) return st;
+    return hip_status(launch_df(fz, nz, ny, nx, m, W, df, (hipStream_t)stream));
+}
+
+size_t ppm_backward_workspace_bytes(const ppm_scan *scan, int32_t n_atoms)
+{
+    if (check_scan(scan) != PPM_OK || n_atoms < 0) return 0;
+    int nb, per;
+    backward_chunks(scan, &nb, &per);
+    const size_t na_pad = (size_t)((n_atoms + 63) / 64) * 64;
+    return backward_record_bytes(scan) + align256((size_t)nb * na_pad * 6 * sizeof(double));
+}
+
+ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
+                                     const ppm_probe *probe, const ppm_scan *scan,
+                                     const ppm_df_params *dfp, int32_t n_atoms,
+                                     const double *pos, const double *q, const double *R,
+                                     const double *eps, const float *pp,
+                                     const float *grad_df, double *g_pos, double *g_q,
+                                     double *g_R, double *g_eps, void *workspace,
+                                     size_t workspace_bytes, void *stream)
+{
+    ppm_status st;
+    if ((st = check_grid(grid)) != PPM_OK) return st;
+    if ((st = check_probe(probe)) != PPM_OK) return st;
+    if ((st = check_scan(scan)) != PPM_OK) return st;
+    if (!ff || !pp || !grad_df || !dfp || n_atoms < 0) return PPM_EINVAL;
+    if (n_atoms > 0 && (!pos || !q || !R || !eps || !g_pos || !g_q || !g_R || !g_eps))
+        return PPM_EINVAL;
+    const int m = df_half_width(dfp->A, scan->dz);
+    if (m < 1) return PPM_EINVAL;
+    if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+    if (scan->nz < 2 * m + 1) return PPM_EINVAL;
+    if (!workspace || workspace_bytes < ppm_backward_workspace_bytes(scan, n_atoms))
+        return PPM_EINVAL;
+    if (grid->periodic_xy && !finite_pos(grid->cutoff)) return PPM_EINVAL;
+    DfWeights W;
+    if ((st = df_weights(dfp, scan->dz, m, &W)) != PPM_OK) return st;
+    BwdArgs A;
+    memset(&A, 0, sizeof(A));
+    A.s = make_scan_args(grid, probe, nullptr, scan);
+    A.s.m = m;
+    A.s.ndf = scan->nz - 2 * m;
+    A.hx = grid->step[0];
+    A.hy = grid->step[1];
+    A.hz = grid->step[2];
+    A.periodic = grid->periodic_xy;
+    A.Lx = grid->n[0] * grid->step[0];
+    A.Ly = grid->n[1] * grid->step[1];
+    A.rc2 = (float)(grid->cutoff * grid->cutoff);
+    A.n_atoms = n_atoms;
+    A.R_pp = probe->R_pp;
+    A.eps_pp = probe->eps_pp;
+    A.kq_pp = kCoulomb * probe->q_pp;
+    A.ke_qpp = kCoulomb * probe->q_pp;
+    backward_chunks(scan, &A.n_eq_blocks, &A.eq_per_block);
+    char *ws = static_cast<char *>(workspace);
+    float4 *rec = reinterpret_cast<float4 *>(ws);
+    double *partial = reinterpret_cast<double *>(ws + backward_record_bytes(scan));
+    return hip_status(launch_backward(A, W, reinterpret_cast<const float4 *>(ff),
+                                      reinterpret_cast<const float4 *>(pp), grad_df, pos, q, R,
+                                      eps, rec, partial, g_pos, g_q, g_R, g_eps,
+                                      (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,330 @@
+// scan_backward.hip -- implicit adjoint of the relaxed scan + frequency shift.
+//
+// At every relaxed point the net force vanishes, G(r*, theta) = 0 (Eq. 1), so the
+// equilibrium moves with the atom parameters theta as dr*/dtheta = -J^{-1} dG/dtheta
+// with J = dG/dr.  The tip force Fz_tip = -F^T_z(r*) (text after Eq. 2) depends on
+// theta only through r*, and the frequency shift (Eq. 3) is linear in Fz_tip.
+// Hence, for L with dL/d(df) = grad_df:
+//   gbar_k = dL/dFz_k   (transposed frequency-shift weights)
+//   mu     = J^{-T} (gbar_k grad_r F^T_z)
+//   dL/dtheta_i = sum_k mu . sum_corners w_c d f_i(v_c)/d theta_i
+// where f_i(v) = phi(rho) (v - r_i) is atom i's pair force (Eq. 5 + Eq. 6) at a
+// cell corner, recomputed here; the gradient of the grid is never stored.
+//
+// Kernels:
+//  1. adjoint_solve: one lane per tip column walks its heights with a register
+//     ring of grad_df, gathers the eight corners of the relaxed point's cell,
+//     builds J (trilinear cell Jacobian + spring Jacobian, FP64), solves the
+//     3x3 transposed system and writes mu, the cell and its fractions.
+//  2. atom_scatter: one lane per atom, one wave per chunk of relaxed points.  The
+//     point data are wave-uniform (scalar loads); every lane evaluates its own
+//     atom's pair-force derivatives at the eight corners and accumulates in FP64
+//     registers, so no cross-lane reduction is needed.  Each block writes its
+//     per-atom partial sums.
+//  3. reduce: sums the partials of every (atom, component) in a fixed order and
+//     applies the per-atom constant factors -> deterministic result.
+#include "ppm_kernels.h"
+
+namespace ppm {
+namespace {
+
+constexpr int kTX = 16, kTY = 16;
+
+struct EqRecord {
+    float4 mu_v;      // mu (3), valid flag
+    float4 t;         // tx, ty, tz, unused
+    int4 idx;         // ix, iy, iz (cell corner), unused
+};
+
+__device__ __forceinline__ int wrap_index(double f, int n)
+{
+    // f is integral; return f mod n in [0, n).  NaN, inf or huge values map to a
+    // valid index (the conversion below is only reached with a finite, in-range w).
+    double w = f - (double)n * floor(f / (double)n);
+    if (!(w >= 0.0 && w < (double)n)) w = 0.0;
+    const int i = (int)w;
+    return i >= n ? n - 1 : i;
+}
+
+template <int M>
+__global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
+    const BwdArgs A, const DfWeights wts, const float4 *__restrict__ ff,
+    const float4 *__restrict__ pp, const float *__restrict__ grad_df, EqRecord *__restrict__ rec)
+{
+    const ScanArgs &a = A.s;
+    const int ix = blockIdx.x * kTX + threadIdx.x;
+    const int iy = blockIdx.y * kTY + threadIdx.y;
+    if (ix >= a.snx || iy >= a.sny) return;
+    const size_t plane = (size_t)a.snx * a.sny;
+    const size_t col = (size_t)iy * a.snx + ix;
+    const double ax = a.x0 + ix * a.sdx, ay = a.y0 + iy * a.sdy;
+
+    // ring[j] = grad_df of output s - (2M - j); gbar_s = sum_j wts.w[j] ring[j]
+    float ring[2 * M + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * M + 1; ++j) ring[j] = 0.0f;
+
+    for (int s = 0; s < a.snz; ++s) {
+#pragma unroll
+        for (int j = 0; j < 2 * M; ++j) ring[j] = ring[j + 1];
+        ring[2 * M] = (s < a.ndf) ? grad_df[(size_t)s * plane + col] : 0.0f;
+        float gbar = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2 * M + 1; ++j) gbar = fmaf(wts.w[j], ring[j], gbar);
+
+        const size_t o = (size_t)s * plane + col;
+        const float4 st = pp[o];
+        EqRecord r;
+        r.mu_v = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.t = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.idx = make_int4(0, 0, 0, 0);
+        if (gbar != 0.0f && st.w >= 0.0f) {
+            const double az = a.z_top - s * a.sdz;
+            const double dx = a.d0x + st.x, dy = a.d0y + st.y, dz = a.d0z + st.z;  // r - anchor
+            const double x = ax + dx, y = ay + dy, z = az + dz;
+            // cell
+            const double ux = (x - a.ox) * a.ihx, uy = (y - a.oy) * a.ihy, uz = (z - a.oz) * a.ihz;
+            const double fx = floor(ux), fy = floor(uy);
+            const double tx = ux - fx, ty = uy - fy;
+            const int cx = wrap_index(fx, a.gnx), cy = wrap_index(fy, a.gny);
+            double fz = floor(uz), tz;
+            bool zin = true;
+            if (!(fz >= 0.0)) { fz = 0.0; tz = 0.0; zin = false; }
+            else if (fz > (double)(a.gnz - 2)) { fz = (double)(a.gnz - 2); tz = 1.0; zin = false; }
+            else tz = uz - fz;
+            const int cz = (int)fz;
+            const int cx1 = (cx + 1 < a.gnx) ? cx + 1 : 0, cy1 = (cy + 1 < a.gny) ? cy + 1 : 0;
+            const size_t pl = (size_t)a.gnx * a.gny;
+            const size_t b0 = (size_t)cz * pl, b1 = b0 + pl;
+            const float4 v000 = ff[b0 + (size_t)cy * a.gnx + cx];
+            const float4 v100 = ff[b0 + (size_t)cy * a.gnx + cx1];
+            const float4 v010 = ff[b0 + (size_t)cy1 * a.gnx + cx];
+            const float4 v110 = ff[b0 + (size_t)cy1 * a.gnx + cx1];
+            const float4 v001 = ff[b1 + (size_t)cy * a.gnx + cx];
+            const float4 v101 = ff[b1 + (size_t)cy * a.gnx + cx1];
+            const float4 v011 = ff[b1 + (size_t)cy1 * a.gnx + cx];
+            const float4 v111 = ff[b1 + (size_t)cy1 * a.gnx + cx1];
+            const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
+            // d/dx, d/dy, d/dz of the trilinear weights (per unit length)
+            const double ihz = zin ? a.ihz : 0.0;
+            double J[9];
+#define PPM_JROW(C, r)                                                                          \
+    {                                                                                           \
+        const double e00 = (double)v100.C - v000.C, e10 = (double)v110.C - v010.C;             \
+        const double e01 = (double)v101.C - v001.C, e11 = (double)v111.C - v011.C;             \
+        J[3 * r + 0] = a.ihx * (sy * sz * e00 + ty * sz * e10 + sy * tz * e01 + ty * tz * e11); \
+        const double f00 = (double)v010.C - v000.C, f10 = (double)v110.C - v100.C;             \
+        const double f01 = (double)v011.C - v001.C, f11 = (double)v111.C - v101.C;             \
+        J[3 * r + 1] = a.ihy * (sx * sz * f00 + tx * sz * f10 + sx * tz * f01 + tx * tz * f11); \
+        const double g00 = (double)v001.C - v000.C, g10 = (double)v101.C - v100.C;             \
+        const double g01 = (double)v011.C - v010.C, g11 = (double)v111.C - v110.C;             \
+        J[3 * r + 2] = ihz * (sx * sy * g00 + tx * sy * g10 + sx * ty * g01 + tx * ty * g11);   \
+    }
+            PPM_JROW(x, 0)
+            PPM_JROW(y, 1)
+            PPM_JROW(z, 2)
+#undef PPM_JROW
+            // spring Jacobian dF^T/dr = -k_R[(1 - R0/|d|) I + R0 d d^T/|d|^3] - diag(kx, ky, 0)
+            const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+            const double c1 = 1.0 - a.R0 / dn, c2 = a.R0 / (dn * dn * dn);
+            const double d[3] = {dx, dy, dz};
+            double Jt[9];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Jt[3 * i + j] = -a.kR * ((i == j ? c1 : 0.0) + c2 * d[i] * d[j]);
+            Jt[0] -= a.kx;
+            Jt[4] -= a.ky;
+            for (int i = 0; i < 9; ++i) J[i] += Jt[i];
+            // solve J^T mu = gbar * (row z of Jt)
+            const double g = (double)gbar;
+            const double b[3] = {g * Jt[6], g * Jt[7], g * Jt[8]};
+            // transpose: T[i][j] = J[j][i]
+            const double T00 = J[0], T01 = J[3], T02 = J[6];
+            const double T10 = J[1], T11 = J[4], T12 = J[7];
+            const double T20 = J[2], T21 = J[5], T22 = J[8];
+            const double k00 = T11 * T22 - T12 * T21, k01 = T12 * T20 - T10 * T22,
+                         k02 = T10 * T21 - T11 * T20;
+            const double det = T00 * k00 + T01 * k01 + T02 * k02;
+            if (fabs(det) > 1e-300) {
+                const double id = 1.0 / det;
+                const double mu0 = (k00 * b[0] + (T02 * T21 - T01 * T22) * b[1] +
+                                    (T01 * T12 - T02 * T11) * b[2]) * id;
+                const double mu1 = (k01 * b[0] + (T00 * T22 - T02 * T20) * b[1] +
+                                    (T02 * T10 - T00 * T12) * b[2]) * id;
+                const double mu2 = (k02 * b[0] + (T01 * T20 - T00 * T21) * b[1] +
+                                    (T00 * T11 - T01 * T10) * b[2]) * id;
+                r.mu_v = make_float4((float)mu0, (float)mu1, (float)mu2, 1.0f);
+                r.t = make_float4((float)tx, (float)ty, (float)tz, 0.0f);
+                r.idx = make_int4(cx, cy, cz, 0);
+            }
+        }
+        rec[o] = r;
+    }
+}
+
+// One wave per chunk of relaxed points; lane = atom.
+__global__ __launch_bounds__(64) void atom_scatter_kernel(
+    const BwdArgs A, const EqRecord *__restrict__ rec, const double *__restrict__ pos,
+    const double *__restrict__ q, const double *__restrict__ R, const double *__restrict__ eps,
+    double *__restrict__ partial)
+{
+    const ScanArgs &a = A.s;
+    const int atom = blockIdx.y * 64 + threadIdx.x;
+    const bool live = atom < A.n_atoms;
+    const int ia = live ? atom : 0;
+    const double px = pos[3 * ia], py = pos[3 * ia + 1], pz = pos[3 * ia + 2];
+    const double RiP = R[ia] + A.R_pp;
+    const float R2 = (float)(RiP * RiP);
+    const double eiP = sqrt(eps[ia] * A.eps_pp);
+    const float e12 = (float)(12.0 * eiP);
+    const float kq = (float)(A.kq_pp * q[ia]);
+
+    double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0;
+    const size_t n_eq = (size_t)a.snx * a.sny * a.snz;
+    const size_t e0 = (size_t)blockIdx.x * A.eq_per_block;
+    const size_t e1 = min(n_eq, e0 + (size_t)A.eq_per_block);
+    for (size_t e = e0; e < e1; ++e) {
+        const EqRecord r = rec[e];
+        if (r.mu_v.w == 0.0f) continue;
+        // corner coordinates relative to the atom (FP64 difference, then FP32)
+        const int cx1 = (r.idx.x + 1 < a.gnx) ? r.idx.x + 1 : 0;
+        const int cy1 = (r.idx.y + 1 < a.gny) ? r.idx.y + 1 : 0;
+        double ddx0 = a.ox + r.idx.x * A.hx - px, ddx1 = a.ox + cx1 * A.hx - px;
+        double ddy0 = a.oy + r.idx.y * A.hy - py, ddy1 = a.oy + cy1 * A.hy - py;
+        if (A.periodic) {
+            ddx0 -= A.Lx * rint(ddx0 / A.Lx);
+            ddx1 -= A.Lx * rint(ddx1 / A.Lx);
+            ddy0 -= A.Ly * rint(ddy0 / A.Ly);
+            ddy1 -= A.Ly * rint(ddy1 / A.Ly);
+        }
+        const float dxs[2] = {(float)ddx0, (float)ddx1};
+        const float dys[2] = {(float)ddy0, (float)ddy1};
+        const float dzs[2] = {(float)(a.oz + r.idx.z * A.hz - pz),
+                              (float)(a.oz + (r.idx.z + 1) * A.hz - pz)};
+        const float tx = r.t.x, ty = r.t.y, tz = r.t.z;
+        const float wx[2] = {1.0f - tx, tx}, wy[2] = {1.0f - ty, ty}, wz[2] = {1.0f - tz, tz};
+        float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int i = cc & 1, j = (cc >> 1) & 1, k = cc >> 2;
+            const float w = wx[i] * wy[j] * wz[k];
+            const float mx = w * r.mu_v.x, my = w * r.mu_v.y, mz = w * r.mu_v.z;
+            const float dx = dxs[i], dy = dys[j], dz = dzs[k];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            float ir = __builtin_amdgcn_rsqf(r2);
+            if (A.periodic) ir = (r2 < A.rc2) ? ir : 0.0f;
+            const float ir2 = ir * ir;
+            const float ir3 = ir * ir2;
+            const float s2 = R2 * ir2;
+            const float s6 = s2 * s2 * s2;
+            const float s12 = s6 * s6;
+            const float ec = kq * ir;
+            const float phi = fmaf(e12, s12 - s6, ec) * ir2;
+            // phi'(rho)/rho = ir2^2 [12 e (-14 s12 + 8 s6) - 3 kq/rho]
+            const float dphi = fmaf(e12, fmaf(-14.0f, s12, 8.0f * s6), -3.0f * ec) * ir2 * ir2;
+            const float md = fmaf(mx, dx, fmaf(my, dy, mz * dz));
+            const float tq = dphi * md;
+            ax_ -= fmaf(phi, mx, tq * dx);
+            ay_ -= fmaf(phi, my, tq * dy);
+            az_ -= fmaf(phi, mz, tq * dz);
+            const float im = ir2 * md;
+            aq = fmaf(ir3, md, aq);                       // x k_e q_pp
+            aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
+            ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+        }
+        gx += ax_;
+        gy += ay_;
+        gz += az_;
+        gq += aq;
+        gR += aR;
+        ge += ae;
+    }
+    if (live) {
+        const int na_pad = gridDim.y * 64;
+        double *out = partial + ((size_t)blockIdx.x * na_pad + atom) * 6;
+        out[0] = gx;
+        out[1] = gy;
+        out[2] = gz;
+        out[3] = gq * A.ke_qpp;
+        out[4] = gR * 72.0 * eiP / RiP;
+        out[5] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
+    }
+}
+
+// One block per (atom, component): fixed-order sum over the chunk partials.
+__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial,
+                                                     int n_blocks, int na_pad, int n_atoms,
+                                                     double *__restrict__ g_pos,
+                                                     double *__restrict__ g_q,
+                                                     double *__restrict__ g_R,
+                                                     double *__restrict__ g_eps)
+{
+    __shared__ double s[256];
+    const int atom = blockIdx.x / 6, comp = blockIdx.x % 6;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += 256)
+        acc += partial[((size_t)b * na_pad + atom) * 6 + comp];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && atom < n_atoms) {
+        const double v = s[0];
+        if (comp < 3) g_pos[3 * atom + comp] = v;
+        else if (comp == 3) g_q[atom] = v;
+        else if (comp == 4) g_R[atom] = v;
+        else g_eps[atom] = v;
+    }
+}
+
+DfWeights repad_lag(const DfWeights &w, int m, int M)
+{
+    // input: forward layout of capacity K (W[2K - lag] = weight of lag);
+    // output: V[j] = weight of lag 2m - (2M - j) for the grad_df ring.
+    DfWeights o{};
+    const int K = kMaxDfHalfWidth;
+    for (int j = 2 * M - 2 * m; j <= 2 * M; ++j) {
+        const int lag = 2 * m - (2 * M - j);
+        o.w[j] = w.w[2 * K - lag];
+    }
+    return o;
+}
+
+}  // namespace
+
+hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *ff,
+                           const float4 *pp, const float *grad_df, const double *pos,
+                           const double *q, const double *R, const double *eps, float4 *eq_ws,
+                           double *partial_ws, double *g_pos, double *g_q, double *g_R,
+                           double *g_eps, hipStream_t stream)
+{
+    EqRecord *rec = reinterpret_cast<EqRecord *>(eq_ws);
+    dim3 blk(kTX, kTY, 1);
+    dim3 grd((A.s.snx + kTX - 1) / kTX, (A.s.sny + kTY - 1) / kTY, 1);
+    const int m = A.s.m;
+    if (m <= 8)
+        hipLaunchKernelGGL((adjoint_solve_kernel<8>), grd, blk, 0, stream, A, repad_lag(w, m, 8),
+                           ff, pp, grad_df, rec);
+    else if (m <= 16)
+        hipLaunchKernelGGL((adjoint_solve_kernel<16>), grd, blk, 0, stream, A,
+                           repad_lag(w, m, 16), ff, pp, grad_df, rec);
+    else
+        hipLaunchKernelGGL((adjoint_solve_kernel<32>), grd, blk, 0, stream, A,
+                           repad_lag(w, m, 32), ff, pp, grad_df, rec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (A.n_atoms == 0) return hipSuccess;
+    const int na_blocks = (A.n_atoms + 63) / 64;
+    dim3 g2(A.n_eq_blocks, na_blocks, 1);
+    hipLaunchKernelGGL(atom_scatter_kernel, g2, dim3(64, 1, 1), 0, stream, A, rec, pos, q, R, eps,
+                       partial_ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_kernel, dim3(A.n_atoms * 6, 1, 1), dim3(256, 1, 1), 0, stream,
+                       partial_ws, A.n_eq_blocks, na_blocks * 64, A.n_atoms, g_pos, g_q, g_R,
+                       g_eps);
+    return hipGetLastError();
+}
+
+}  // namespace ppm

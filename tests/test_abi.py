@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI (no GPU needed): the built library exports every
+function include/ppm.h declares, the ctypes structs match the C layout, and
+invalid arguments are rejected before anything is enqueued."""
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2401_14564_amd import _lib, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppm.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = _declared_functions()
+    assert "ppm_build_ff" in names and "ppm_relaxed_scan_backward" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(_lib.EXPORTED)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ppm.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(ppm_grid), sizeof(ppm_probe), sizeof(ppm_fire),'
+        " sizeof(ppm_scan), sizeof(ppm_df_params));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", offsetof(ppm_grid, cutoff), offsetof(ppm_probe, d0),'
+        " offsetof(ppm_fire, max_iter), offsetof(ppm_scan, nz), offsetof(ppm_scan, z_top));\n"
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    sizes = [int(v) for v in out]
+    assert sizes[:5] == [ct.sizeof(_lib.Grid), ct.sizeof(_lib.Probe), ct.sizeof(_lib.Fire),
+                         ct.sizeof(_lib.Scan), ct.sizeof(_lib.DfParams)]
+    assert sizes[5:] == [_lib.Grid.cutoff.offset, _lib.Probe.d0.offset, _lib.Fire.max_iter.offset,
+                         _lib.Scan.nz.offset, _lib.Scan.z_top.offset]
+
+
+def test_status_strings():
+    assert _lib.string(_lib.PPM_OK) == "ok"
+    assert "invalid" in _lib.string(_lib.PPM_EINVAL)
+    assert _lib.string(12345) == "unknown status"
+
+
+def test_df_half_width():
+    L = _lib.lib()
+    assert L.ppm_df_half_width(1.0, 0.1) == 5
+    assert L.ppm_df_half_width(0.7, 0.1) == 4
+    assert L.ppm_df_half_width(2.0, 0.05) == 20
+    assert L.ppm_df_half_width(0.0, 0.1) == -1
+    assert L.ppm_df_half_width(1.0, -0.1) == -1
+
+
+FAKE = ct.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+
+
+def _args():
+    w = W.config0()
+    return (_lib.grid_struct(w.grid), _lib.probe_struct(w.probe), _lib.fire_struct(w.fire),
+            _lib.scan_struct(w.scan), _lib.df_struct(w.df))
+
+
+def test_build_ff_rejects_bad_arguments():
+    L = _lib.lib()
+    g, p, f, s, d = _args()
+    assert L.ppm_build_ff(None, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    assert L.ppm_build_ff(g, p, 1, None, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    assert L.ppm_build_ff(g, p, -1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    assert L.ppm_build_ff(g, p, 1, FAKE, FAKE, FAKE, FAKE, None, None) == _lib.PPM_EINVAL
+    bad = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (1, 10, 10)))
+    assert L.ppm_build_ff(bad, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    bad = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.0, 0.1), (10, 10, 10)))
+    assert L.ppm_build_ff(bad, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    huge = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (2048, 2048, 1024)))
+    assert L.ppm_build_ff(huge, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_ERANGE
+    # periodic: cutoff must leave room for the brick half-diagonal below L/2
+    per = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (100, 100, 10), 1, 4.9))
+    assert L.ppm_build_ff(per, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    per = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (100, 100, 10), 1, 0.0))
+    assert L.ppm_build_ff(per, p, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    badp = _lib.probe_struct(W.Probe(d0=(0.0, 0.0, 0.0)))
+    assert L.ppm_build_ff(g, badp, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+    badp = _lib.probe_struct(W.Probe(k_rad=-1.0))
+    assert L.ppm_build_ff(g, badp, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.PPM_EINVAL
+
+
+def test_relaxed_scan_rejects_bad_arguments():
+    L = _lib.lib()
+    g, p, f, s, d = _args()
+    E = _lib.PPM_EINVAL
+    assert L.ppm_relaxed_scan(g, FAKE, p, f, s, None, None, None, None, None) == E  # no output
+    assert L.ppm_relaxed_scan(g, None, p, f, s, FAKE, None, None, None, None) == E  # no ff
+    assert L.ppm_relaxed_scan(g, FAKE, p, f, s, None, None, None, FAKE, None) == E  # df w/o dfp
+    for bad in (dict(f_conv=0.0), dict(dt0=-1.0), dict(mass=0.0), dict(max_iter=0),
+                dict(alpha0=1.5), dict(n_min=-1)):
+        bf = _lib.fire_struct(W.Fire(**bad))
+        assert L.ppm_relaxed_scan(g, FAKE, p, bf, s, FAKE, None, None, None, None) == E, bad
+    short = _lib.scan_struct(W.Scan(0, 0, 0.1, 0.1, 4, 4, 10.0, 0.1, 10))   # < 2m+1 = 11
+    assert L.ppm_relaxed_scan(g, FAKE, p, f, short, None, None, d, FAKE, None) == E
+    empty = _lib.scan_struct(W.Scan(0, 0, 0.1, 0.1, 0, 4, 10.0, 0.1, 20))
+    assert L.ppm_relaxed_scan(g, FAKE, p, f, empty, FAKE, None, None, None, None) == E
+    wide = _lib.df_struct(W.DfParams(A=7.0))                                # m = 35 > 32
+    tall = _lib.scan_struct(W.Scan(0, 0, 0.1, 0.1, 4, 4, 10.0, 0.1, 80))
+    assert L.ppm_relaxed_scan(g, FAKE, p, f, tall, None, None, wide, FAKE, None) == \
+        _lib.PPM_EUNSUPPORTED
+
+
+def test_df_and_backward_reject_bad_arguments():
+    L = _lib.lib()
+    g, p, f, s, d = _args()
+    E = _lib.PPM_EINVAL
+    assert L.ppm_df(None, 20, 4, 4, 0.1, d, FAKE, None) == E
+    assert L.ppm_df(FAKE, 10, 4, 4, 0.1, d, FAKE, None) == E          # nz < 2m+1
+    assert L.ppm_df(FAKE, 20, 0, 4, 0.1, d, FAKE, None) == E
+    assert L.ppm_df(FAKE, 20, 4, 4, 0.0, d, FAKE, None) == E
+    assert L.ppm_df(FAKE, 20, 4, 4, 0.1, _lib.df_struct(W.DfParams(k_cant=0.0)), FAKE, None) == E
+    ws = L.ppm_backward_workspace_bytes(s, 12)
+    assert ws > 0 and ws % 256 == 0
+    args = [g, FAKE, p, s, d, 12, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+            FAKE, ws - 1, None]
+    assert L.ppm_relaxed_scan_backward(*args) == E                     # workspace too small
+    args[-2] = ws
+    args[10] = None                                                    # no saved probe state
+    assert L.ppm_relaxed_scan_backward(*args) == E

@@ -1,0 +1,199 @@
+"""GPU parity of the forward path (force-field build, relaxed scan, frequency
+shift) against the FP64 oracle, through the C ABI.  Tolerances: see parity.py."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import paper_2401_14564_amd as ppm
+from paper_2401_14564_amd import workloads as W
+from parity import DF_TOL, check_ff, grade_scan
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_ff(w):
+    ff = ppm.build_ff(w.grid, w.probe, w.atoms)
+    torch.cuda.synchronize()
+    return ff
+
+
+@pytest.fixture(scope="module")
+def c0():
+    w = W.config0()
+    ref, sc = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
+    return w, ref, sc
+
+
+# ------------------------------------------------------------------ FF build
+def test_ff_c0_full_grid(c0):
+    w, ref, sc = c0
+    info = check_ff(_gpu_ff(w).cpu().numpy(), ref, sc, "C0")
+    print("C0 ff", info, flush=True)
+
+
+def test_ff_c1_full_grid():
+    w = W.config1()
+    ref, sc = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
+    info = check_ff(_gpu_ff(w).cpu().numpy(), ref, sc, "C1")
+    print("C1 ff", info, flush=True)
+
+
+@pytest.mark.parametrize("n,natoms,periodic", [((5, 3, 3), 4, 0), ((67, 9, 13), 300, 0),
+                                               ((64, 4, 8), 1, 0), ((2, 2, 2), 3, 0),
+                                               ((130, 90, 11), 40, 1)])
+def test_ff_ragged_and_multi_chunk(n, natoms, periodic):
+    """Grids that are not multiples of the brick, more atoms than one LDS chunk,
+    a 2x2x2 grid, and a periodic cell with a cutoff."""
+    rng = np.random.default_rng(sum(n) + natoms)
+    h = 0.1
+    L = np.array(n) * h
+    atoms = W.random_atoms(rng, natoms, [0, 0, -1.0], [L[0], L[1], 0.0])
+    cutoff = 0.5 * min(L[0], L[1]) - 3.5 if periodic else 0.0
+    grid = W.Grid((0.0, 0.0, 1.5), (h, h, h), n, periodic, cutoff)
+    ref, sc = orc.build_ff(grid, W.Probe(), atoms, with_scale=True)
+    got = ppm.build_ff(grid, W.Probe(), atoms).cpu().numpy()
+    check_ff(got, ref, sc, f"grid {n} atoms {natoms} periodic {periodic}")
+
+
+def test_ff_zero_atoms_is_zero_field():
+    grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (70, 5, 9))
+    empty = W.Atoms(np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0), [])
+    got = ppm.build_ff(grid, W.Probe(), empty).cpu().numpy()
+    assert np.all(got == 0.0)
+
+
+def test_ff_c2_sampled_voxels():
+    """Full 400x400x300 periodic grid with 1,600 atoms, checked on 20,000 seeded
+    voxels computed one by one by the oracle."""
+    w = W.config2()
+    got = _gpu_ff(w)
+    rng = np.random.default_rng(2002)
+    idx = np.stack([rng.integers(0, w.grid.n[0], 20000), rng.integers(0, w.grid.n[1], 20000),
+                    rng.integers(0, w.grid.n[2], 20000)], axis=1)
+    ref, sc = orc.ff_voxels(w.grid, w.probe, w.atoms, idx)
+    it = torch.as_tensor(idx, device=got.device)
+    sel = got[it[:, 2], it[:, 1], it[:, 0]].cpu().numpy()
+    info = check_ff(sel, ref, sc, "C2 sampled")
+    print("C2 ff", info, flush=True)
+
+
+# ------------------------------------------------------------------ relaxed scan
+def _scan_both(w, fire, cols=None, dfp=None):
+    """Oracle force field rounded to FP32 feeds both sides; the GPU scans every
+    column, the oracle the listed ones (polished equilibria)."""
+    ref = orc.build_ff(w.grid, w.probe, w.atoms)
+    ff32 = ref.astype(np.float32)
+    ff64 = ff32.astype(np.float64)
+    res = ppm.relaxed_scan(w.grid, torch.as_tensor(ff32, device="cuda"), w.probe, fire, w.scan,
+                           dfp=dfp)
+    torch.cuda.synchronize()
+    ores = orc.relaxed_scan(w.grid, ff64, w.probe, fire, w.scan, cols=cols, polish_tol=1e-12,
+                            with_lambda=True)
+    g = {k: v.cpu().numpy() for k, v in res.items()}
+    return ff64, ores, g
+
+
+def test_scan_parity_c0_full():
+    w = W.config0()
+    fire = W.parity_fire(w.fire)
+    ff64, ores, g = _scan_both(w, fire, dfp=w.df)
+    info = grade_scan(w.grid, ff64, w.probe, fire, w.scan, ores["cols"], ores, g["pp"], g["fz"],
+                      g["df"], w.df, label="C0")
+    print("C0 scan", info, flush=True)
+    assert info["graded"] > 0.95 * info["points"]
+
+
+def test_scan_parity_c1_sampled_columns():
+    """Full 240x240x100 scan on the GPU; 600 seeded columns re-run by the oracle."""
+    w = W.config1()
+    fire = W.parity_fire(w.fire)
+    rng = np.random.default_rng(1001)
+    cols = np.stack([rng.integers(0, w.scan.nx, 600), rng.integers(0, w.scan.ny, 600)], axis=1)
+    ff64, ores, g = _scan_both(w, fire, cols=cols, dfp=w.df)
+    info = grade_scan(w.grid, ff64, w.probe, fire, w.scan, cols, ores, g["pp"], g["fz"], g["df"],
+                      w.df, label="C1")
+    print("C1 scan", info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]
+
+
+def test_scan_throughput_tolerance_certificates_c0():
+    """At the workload's own convergence threshold (1e-4 eV/A) every GPU point must
+    be a converged, stable equilibrium of the oracle's force balance (certificate),
+    and within residual/stiffness of the exact one."""
+    w = W.config0()
+    ref = orc.build_ff(w.grid, w.probe, w.atoms)
+    ff32 = ref.astype(np.float32)
+    ff64 = ff32.astype(np.float64)
+    res = ppm.relaxed_scan(w.grid, torch.as_tensor(ff32, device="cuda"), w.probe, w.fire, w.scan)
+    pp = res["pp"].cpu().numpy()
+    assert np.all(pp[..., 3] >= 0)
+    cols = orc.all_columns(w.scan)
+    from parity import anchors_for
+    A = anchors_for(w.scan, cols)
+    r = A + np.asarray(w.probe.d0) + pp[:, cols[:, 1], cols[:, 0], :3].transpose(1, 0, 2)
+    gn, lam = orc.residual(w.grid, ff64, w.probe, A.reshape(-1, 3), r.reshape(-1, 3))
+    assert np.all(gn < w.fire.f_conv * 1.001 + 2e-7)
+    assert np.all(lam > 0)
+    print("C0 iters mean", float(pp[..., 3].mean()), flush=True)
+
+
+def test_scan_zero_field_exact_rest():
+    grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (30, 30, 90))
+    ff = torch.zeros((90, 30, 30, 4), dtype=torch.float32, device="cuda")
+    scan = W.Scan(0.33, 0.41, 0.1, 0.1, 17, 5, 8.0, 0.1, 13)
+    res = ppm.relaxed_scan(grid, ff, W.Probe(), W.Fire(), scan, dfp=W.DfParams())
+    assert torch.all(res["fz"] == 0) and torch.all(res["pp"] == 0) and torch.all(res["df"] == 0)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 5, 12), (3, 40, 2)])
+def test_scan_ragged_shapes(shape):
+    """Tip lattices that do not fill the 16x16 tile, a single point and a single
+    height, compared with the oracle on every column."""
+    nx, ny, nz = shape
+    w = W.config0()
+    scan = W.Scan(7.1, 7.3, 0.13, 0.11, nx, ny, 10.2, 0.1, nz)
+    w = W.Workload("ragged", w.atoms, w.grid, w.probe, w.fire, scan, w.df)
+    fire = W.parity_fire(w.fire)
+    ff64, ores, g = _scan_both(w, fire)
+    grade_scan(w.grid, ff64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+               label=f"ragged {shape}")
+
+
+def test_scan_below_and_above_grid_clamps():
+    """Probe heights outside the grid see the field of the nearest z-layer (the
+    grid is clamped in z); both sides agree there too."""
+    w = W.config0()
+    scan = W.Scan(7.0, 7.0, 0.2, 0.2, 4, 4, 16.5, 0.5, 12)   # probe from 12.5 A down to 7 A
+    grid = W.Grid((0.0, 0.0, -4.0), (0.1, 0.1, 0.1), (160, 160, 130))   # top at 8.9 A
+    w = W.Workload("clamp", w.atoms, grid, w.probe, w.fire, scan, w.df)
+    fire = W.parity_fire(w.fire)
+    ff64, ores, g = _scan_both(w, fire)
+    grade_scan(grid, ff64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+               label="clamp")
+
+
+# ------------------------------------------------------------------ frequency shift
+def test_df_fused_standalone_and_oracle_agree():
+    w = W.config0()
+    ref = orc.build_ff(w.grid, w.probe, w.atoms).astype(np.float32)
+    res = ppm.relaxed_scan(w.grid, torch.as_tensor(ref, device="cuda"), w.probe, w.fire, w.scan,
+                           dfp=w.df)
+    alone = ppm.df(res["fz"], w.scan.dz, w.df)
+    assert torch.equal(alone, res["df"])           # same weights, same summation order
+    odf = orc.df(res["fz"].cpu().numpy().astype(np.float64), w.scan.dz, w.df)
+    assert np.abs(alone.cpu().numpy() - odf).max() <= DF_TOL * 1e-2
+
+
+@pytest.mark.parametrize("A,dz,nz", [(1.0, 0.1, 11), (0.7, 0.1, 30), (3.0, 0.05, 61),
+                                     (1.3, 0.17, 25)])
+def test_df_standalone_random_stacks(A, dz, nz):
+    """Standalone kernel on random stacks (several half-widths, minimum height
+    count) against the oracle's quadrature."""
+    rng = np.random.default_rng(int(A * 100 + nz))
+    fz = rng.normal(0, 0.05, size=(nz, 7, 33)).astype(np.float32)
+    dfp = W.DfParams(A=A)
+    got = ppm.df(torch.as_tensor(fz, device="cuda"), dz, dfp).cpu().numpy()
+    ref = orc.df(fz.astype(np.float64), dz, dfp)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, atol=2e-5 * np.abs(ref).max() + 1e-6)
