@@ -5,7 +5,10 @@ Tolerances (stated for the workloads, checked element by element):
     magnitude sum of every term that enters the sum -- the repulsive and the
     attractive LJ part of each pair and its Coulomb part -- i.e. the scale of the
     rounding error of the sum (from the oracle); the same for E; and
-    |dF| / |F| <= 1e-5 wherever |F| >= 0.1 S.  Voxels closer than 0.5 A to an atom
+    |dF| / |F| <= 1e-5 wherever the sum is well conditioned, |F| >= S/2 (an n-term
+    FP32 sum with condition number S/|F| = k carries up to ~n u k relative error,
+    u = 6e-8, so a relative bound on |F| itself is only meaningful for small k).
+    Voxels closer than 0.5 A to an atom
     (energies of 1e5 eV and more, never visited by the probe) and, with a cutoff,
     voxels with a pair within 1e-3 A^2 of the cutoff sphere (each side applies
     rho^2 < rc^2 in its own precision) are excluded and counted.
@@ -15,8 +18,10 @@ A relaxed point is graded when the oracle's stability eigenvalue (smallest
 eigenvalue of sym(-dG/dr)) is >= 1e-2 eV/A^2, so that the force residual maps to
 a position error well inside the tolerance.  Where several equilibria exist
 (bistable columns) the scan may legitimately settle in another one: such a
-column is accepted from the height where it departs only if the GPU position is
-itself a certified stable equilibrium of the oracle's force balance.
+column is accepted from the height where it departs only if every GPU position
+from there on is certified by the oracle's force balance, |G_FP64(r_gpu)| <=
+2 f_conv + 1e-6 (FIRE's own stopping rule, plus the FP32 rounding of the stored
+displacement).  Every ungraded point needs the same certificate.
 """
 from __future__ import annotations
 
@@ -41,7 +46,7 @@ def check_ff(gpu_ff: np.ndarray, ref: np.ndarray, scale: np.ndarray, label: str 
     dE = np.abs(gpu[..., 3] - ref[..., 3])
     bad_e = (dE > FF_RTOL * scale[..., 1]) & ok
     Fn = np.linalg.norm(ref[..., :3], axis=-1)
-    strong = ok & (Fn >= 0.1 * scale[..., 0]) & (Fn > 0)
+    strong = ok & (Fn >= 0.5 * scale[..., 0]) & (Fn > 0)
     rel = np.where(strong, np.linalg.norm(gpu[..., :3] - ref[..., :3], axis=-1) /
                    np.where(Fn > 0, Fn, 1.0), 0.0)
     bad_r = rel > FF_RTOL
@@ -87,7 +92,7 @@ def grade_scan(grid, ff64, probe, fire, scan, cols, ores, gpu_pp, gpu_fz, gpu_df
     gres, glam = orc.residual(grid, ff64, probe, A.reshape(-1, 3), r_gpu.reshape(-1, 3))
     gres = gres.reshape(nc, nz)
     glam = glam.reshape(nc, nz)
-    cert = (gres <= 2 * fire.f_conv + 1e-6) & (glam > 0)
+    cert = gres <= 2 * fire.f_conv + 1e-6
     for c in range(nc):
         far = np.nonzero(dr[c] > POS_TOL)[0]
         if len(far) == 0:
@@ -100,10 +105,12 @@ def grade_scan(grid, ff64, probe, fire, scan, cols, ores, gpu_pp, gpu_fz, gpu_df
     assert np.all(dr[g] <= POS_TOL), (f"{label}: {np.sum(dr[g] > POS_TOL)} graded points off, "
                                       f"worst {dr[g].max():.3e} A")
     ungraded = ~g
-    assert np.all(cert[ungraded]), f"{label}: {np.sum(~cert[ungraded])} uncertified points"
+    assert np.all(cert[ungraded]), (f"{label}: {np.sum(~cert[ungraded])} uncertified points, "
+                                    f"worst residual {gres[ungraded].max():.3e}")
     assert diverged_cols <= max_diverged_frac * nc, f"{label}: {diverged_cols} diverged columns"
     out = dict(points=int(dr.size), graded=int(g.sum()), ungraded=int(ungraded.sum()),
-               diverged_cols=diverged_cols, worst_dr=float(dr[g].max()) if g.any() else 0.0,
+               diverged_cols=diverged_cols, unstable_sym=int(np.sum(glam <= 0)),
+               worst_dr=float(dr[g].max()) if g.any() else 0.0,
                worst_dfz=float(np.abs(fz - ores["fz"])[g].max()) if g.any() else 0.0)
     if gpu_df is not None:
         m = orc.df_m(dfp.A, scan.dz)
