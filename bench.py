@@ -4,7 +4,9 @@ One step = one pass of the forward hot path over the paper-scale workload
 (60-atom molecule, 240^3 force-field grid, 240x240 tip columns x 100 heights):
 force-field build -> relaxed scan with the fused frequency shift.  Inputs are
 resident in device memory before timing starts.  The reported value is relaxed
-probe positions (pixel x height) per second of the whole step.
+probe positions (pixel x height) per second of the whole job: consecutive
+steps are pipelined over two streams (the force field of step i+1 is built
+while step i scans), as a production loop over many samples would run.
 
 Also reported, each timed separately after the main loop:
   * per-kernel durations (HIP events on the launch stream) and the roofline of
@@ -25,6 +27,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -41,7 +45,86 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the backward measurement")
+    ap.add_argument("--kernels-once", action="store_true",
+                    help="for rocprofv3 --pmc: a 1 GiB copy (counter calibration), then one "
+                         "launch of each hot kernel on the paper-scale workload")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) "
+                         "into profiles/traffic.json")
     return ap.parse_args()
+
+
+TRAFFIC_KERNELS = {
+    # key: (kernel-name fragment, source files whose hash the figures belong to)
+    "ff_build_c1": ("ff_build_kernel", ["paper_2401_14564_amd/csrc/ff_build.hip",
+                                        "paper_2401_14564_amd/csrc/ppm_kernels.h"]),
+    "relaxed_scan_c1": ("relaxed_scan_kernel", ["paper_2401_14564_amd/csrc/relaxed_scan.hip",
+                                                "paper_2401_14564_amd/csrc/ppm_kernels.h",
+                                                "paper_2401_14564_amd/csrc/ppm_device.h"]),
+}
+CALIB_BYTES = 1 << 30
+
+
+def kernels_once():
+    import torch
+    import paper_2401_14564_amd as ppm
+    from paper_2401_14564_amd import workloads as W
+    dev = torch.device("cuda:0")
+    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)                        # reads and writes CALIB_BYTES
+    torch.cuda.synchronize()
+    del a, b
+    w = W.config1()
+    ff = ppm.build_ff(w.grid, w.probe, w.atoms)
+    torch.cuda.synchronize()
+    ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False)
+    torch.cuda.synchronize()
+    print("kernels-once done", flush=True)
+
+
+def _read_pmc(folder, counter):
+    """{kernel name: [values per dispatch]} from a rocprofv3 counter-collection csv."""
+    import csv
+    import glob
+    rows = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    out = {"calibration": f"torch copy of {CALIB_BYTES} bytes (reads and writes that many)",
+           "units": "bytes per launch, counter KiB x 1024 x (known copy bytes / copy reading)"}
+    for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _read_pmc(folder, counter)
+        copy = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        calib_kib = max(max(v) for v in copy) if copy else None
+        factor = (CALIB_BYTES / 1024.0) / calib_kib if calib_kib else 1.0
+        out[f"{counter}_copy_reading_kib"] = calib_kib
+        out[f"{counter}_scale"] = factor
+        for key, (frag, src) in TRAFFIC_KERNELS.items():
+            vals = [v for k, vs in rows.items() if frag in k for v in vs]
+            if not vals:
+                continue
+            e = out.setdefault(key, {"source_sha": _sha(src)})
+            e[counter.lower() + "_bytes"] = float(np.mean(vals)) * 1024.0 * factor
+    for key in TRAFFIC_KERNELS:
+        e = out.get(key)
+        if e and "fetch_size_bytes" in e and "write_size_bytes" in e:
+            e["hbm_bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def _sha(paths):
@@ -68,11 +151,16 @@ def _traffic(kernel_key, src, launches_bytes_key):
 
 def main():
     a = _args()
+    if a.summarize_pmc:
+        summarize_pmc(*a.summarize_pmc)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if a.kernels_once:
+        kernels_once()
+        return
     import torch
 
     import paper_2401_14564_amd as ppm
@@ -83,37 +171,55 @@ def main():
     w = W.config1()
     atoms = ppm.atoms_to_device(w.atoms)
     nx, ny, nz = w.grid.n
-    ff = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev)
     m = ppm.df_half_width(w.df.A, w.scan.dz)
-    out = dict(fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32, device=dev),
-               df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
-                              device=dev))
-    stream = torch.cuda.current_stream()
+    # Two buffers so that the force field of step i+1 can be built (stream s_ff)
+    # while step i is still scanning (stream s_scan): the scan's cost is the
+    # serial FIRE chain of its hardest columns and leaves most CUs idle.
+    ffs = [torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev) for _ in range(2)]
+    outs = [dict(fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32,
+                                device=dev),
+                 df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
+                                device=dev)) for _ in range(2)]
+    s_ff, s_scan = torch.cuda.Stream(), torch.cuda.Stream()
+    ff_done = [torch.cuda.Event() for _ in range(2)]
+    scan_done = [torch.cuda.Event() for _ in range(2)]
+    for e in scan_done:
+        e.record(s_scan)
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        ppm.build_ff(w.grid, w.probe, atoms, out=ff)
-        if ev is not None:
-            ev[1].record(stream)
-        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False,
-                         out=out)
-        if ev is not None:
-            ev[2].record(stream)
+    def step(i, ev=None):
+        b = i % 2
+        with torch.cuda.stream(s_ff):
+            s_ff.wait_event(scan_done[b])          # buffer b is free again
+            if ev is not None:
+                ev[0].record(s_ff)
+            ppm.build_ff(w.grid, w.probe, atoms, out=ffs[b])
+            if ev is not None:
+                ev[1].record(s_ff)
+            ff_done[b].record(s_ff)
+        with torch.cuda.stream(s_scan):
+            s_scan.wait_event(ff_done[b])
+            if ev is not None:
+                ev[2].record(s_scan)
+            ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+                             pp=False, out=outs[b])
+            if ev is not None:
+                ev[3].record(s_scan)
+            scan_done[b].record(s_scan)
 
-    for _ in range(a.warmup):
-        step()
+    for i in range(a.warmup):
+        step(i)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        step(evs[i])
+        step(i, evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
     ff_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    scan_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    scan_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ff = ffs[0]
 
     # FIRE evaluations per launch (deterministic: same inputs, same iterations)
     res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=True, pp=True)
@@ -125,8 +231,8 @@ def main():
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
     pairs = w.grid.nvox * w.atoms.n
     ff_tflops = pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12
-    scan_src = ["paper_2401_14564_amd/csrc/relaxed_scan.hip", "paper_2401_14564_amd/csrc/ppm_kernels.h"]
-    ff_src = ["paper_2401_14564_amd/csrc/ff_build.hip", "paper_2401_14564_amd/csrc/ppm_kernels.h"]
+    scan_src = TRAFFIC_KERNELS["relaxed_scan_c1"][1]
+    ff_src = TRAFFIC_KERNELS["ff_build_c1"][1]
     dominant = "relaxed_scan" if scan_ms >= ff_ms else "ff_build"
     if dominant == "relaxed_scan":
         roof = {"kernel": "relaxed_scan_kernel", "bound": "hbm", "achieved": round(scan_gbs, 1),
@@ -154,6 +260,8 @@ def main():
         "config": {"workload": "paper-scale plain method: 60 atoms, grid 240^3 at 0.1 A, "
                                "scan 240x240 tips x 100 heights, FIRE f_conv 1e-4 eV/A, "
                                "df A=1 A f0=30300 Hz k=1800 N/m",
+                   "pipelining": "step i+1's force-field build overlaps step i's scan on a "
+                                 "second stream (double-buffered grid)",
                    "relaxations_per_step": n_eq, "voxels": w.grid.nvox, "atoms": w.atoms.n},
         "roofline": roof,
         "kernels": {
@@ -170,6 +278,7 @@ def main():
 
     if not a.no_extra:
         result["backward"] = _bench_backward(ppm, W, torch)
+        result["batched"] = _bench_batch(ppm, W, torch)
 
     if not a.no_cpu:
         result["cpu_baseline"] = _cpu_baseline(w, n_eq)
@@ -216,7 +325,6 @@ def _bench_backward(ppm, W, torch):
         torch.cuda.synchronize()
         tf.append(e[0].elapsed_time(e[1]))
         tb.append(e[1].elapsed_time(e[2]))
-    import numpy as np
     fwd_ms, bwd_ms = float(np.median(tf)), float(np.median(tb))
     return {"workload": "differentiation: 60 atoms, grid 240^3, scan 128x128 x 30 heights "
                         "(20 df outputs), loss ||df - df_target||^2",
@@ -224,11 +332,94 @@ def _bench_backward(ppm, W, torch):
             "bwd_over_fwd": round(bwd_ms / fwd_ms, 4)}
 
 
+def _bench_batch(ppm, W, torch, n_mol=256):
+    """Frequency-shift stacks per second for 256 molecules x 3 lateral
+    stiffnesses: one captured HIP graph (batched force-field launch + batched
+    scan launch) against a plain per-molecule loop of build_ff + 3 scans on one
+    stream (no per-molecule synchronisation)."""
+    import dataclasses
+    dev = torch.device("cuda:0")
+    ws = W.config3(n_mol)
+    mols = [(w.atoms, w.grid) for w in ws]
+    jobs = []
+    for i, w in enumerate(ws):
+        for k in W.C3_K_LAT_N_PER_M:
+            jobs.append((i, dataclasses.replace(w.probe, k_lat=(k * W.N_PER_M, k * W.N_PER_M)),
+                         w.scan))
+    bp = ppm.BatchPipeline(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df)
+    # eager stage times
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    bp.run()
+    torch.cuda.synchronize()
+    e[0].record()
+    bp.build_ff()
+    e[1].record()
+    bp.scan()
+    e[2].record()
+    torch.cuda.synchronize()
+    ff_ms, scan_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    bp.capture()
+    tb = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        e[0].record()
+        bp.replay()
+        e[1].record()
+        torch.cuda.synchronize()
+        tb.append(e[0].elapsed_time(e[1]))
+    batched_ms = float(np.median(tb))
+    # plain loop
+    maxvox = max(w.grid.nvox for w in ws)
+    ffbuf = torch.empty(maxvox * 4, dtype=torch.float32, device=dev)
+    atoms_dev = [ppm.atoms_to_device(w.atoms) for w in ws]
+    m = ppm.df_half_width(ws[0].df.A, ws[0].scan.dz)
+    outs = [torch.empty((sc.nz - 2 * m, sc.ny, sc.nx), dtype=torch.float32, device=dev)
+            for (_, _, sc) in jobs]
+
+    def plain():
+        j = 0
+        for i, w in enumerate(ws):
+            nx, ny, nz = w.grid.n
+            ff = ffbuf[:w.grid.nvox * 4].view(nz, ny, nx, 4)
+            ppm.build_ff(w.grid, w.probe, atoms_dev[i], out=ff)
+            for _ in W.C3_K_LAT_N_PER_M:
+                _, pr, sc = jobs[j]
+                ppm.relaxed_scan(w.grid, ff, pr, w.fire, sc, dfp=w.df, fz=False, pp=False,
+                                 out={"df": outs[j]})
+                j += 1
+
+    plain()
+    tp = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        e[0].record()
+        plain()
+        e[1].record()
+        torch.cuda.synchronize()
+        tp.append(e[0].elapsed_time(e[1]))
+    plain_ms = float(np.median(tp))
+    same = all(torch.equal(bp.df_stack(j), outs[j]) for j in range(len(jobs)))
+    voxels = sum(w.grid.nvox for w in ws)
+    pairs = sum(w.grid.nvox * w.atoms.n for w in ws)
+    return {"workload": f"{n_mol} seeded molecules, 10-120 atoms, cells with 5 A margins at "
+                        "0.1 A, 128x128 tips x 20 heights, 3 lateral stiffnesses "
+                        "(0.15, 0.25, 0.5 N/m)",
+            "voxels": voxels, "pairs": pairs, "jobs": len(jobs),
+            "batched_ms": round(batched_ms, 3), "plain_ms": round(plain_ms, 3),
+            "batched_stacks_per_s": round(len(jobs) / (batched_ms * 1e-3), 1),
+            "plain_stacks_per_s": round(len(jobs) / (plain_ms * 1e-3), 1),
+            "batched_molecules_per_s": round(n_mol / (batched_ms * 1e-3), 1),
+            "plain_molecules_per_s": round(n_mol / (plain_ms * 1e-3), 1),
+            "speedup": round(plain_ms / batched_ms, 3),
+            "batched_stage_ms": {"ff_build": round(ff_ms, 3), "scan": round(scan_ms, 3)},
+            "batched_ff_tflops": round(pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12, 2),
+            "outputs_identical": bool(same)}
+
+
 def _cpu_baseline(w, n_eq):
     """The FP64 oracle, as it stands, on the host cores: the same step (full
     force-field grid, then a sampled set of tip columns at the same FIRE
     settings, no Newton polish), scaled to relaxations/s of the whole step."""
-    import numpy as np
     import oracle as orc
     threads = orc.num_threads()
     t0 = time.perf_counter()

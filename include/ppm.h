@@ -158,10 +158,12 @@ ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_
  *                                   anchor + d0 (A), and the FIRE step count
  *                                   (negative if not converged)
  *   df[scan.nz-2m][scan.ny][scan.nx] frequency shift (Hz); requires dfp and
- *                                   scan.nz >= 2m+1; m <= 32.
+ *                                   scan.nz >= 2m+1; m <= 32; with more than
+ *                                   256 heights fz must be given as well.
  * Errors: PPM_EINVAL for a bad grid/probe/fire/scan (f_conv <= 0, dt <= 0,
  * mass <= 0, negative stiffness, |d0| == 0, nz < 1, max_iter < 1), df without
- * dfp or with too few heights, or all outputs NULL; PPM_EUNSUPPORTED if m > 32.
+ * dfp or with too few heights, or all outputs NULL; PPM_EUNSUPPORTED if m > 32
+ * or if df is requested for more than 256 heights without fz.
  */
 ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
                             const ppm_fire *fire, const ppm_scan *scan, float *fz,
@@ -211,6 +213,77 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
                                      const float *grad_df, double *g_pos, double *g_q,
                                      double *g_R, double *g_eps, void *workspace,
                                      size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched pipeline: many molecules of different sizes, each scanned with one
+ * or more probes, in one launch per stage.  Host tables describe the work; the
+ * same tables copied to device memory are read by the kernels.  Force fields,
+ * tip forces and frequency shifts live in arenas (one device buffer each) at
+ * the offsets ppm_batch_plan assigns.  The calls allocate nothing, so a
+ * build + scan pair can be captured in a HIP graph and replayed.
+ * ------------------------------------------------------------------------ */
+
+/* One molecule.  atom_begin/n_atoms index the concatenated atom arrays
+ * (positions [.][3], q, R, eps) shared by the whole batch. */
+typedef struct {
+    ppm_grid grid;
+    int32_t atom_begin;
+    int32_t n_atoms;
+    int64_t ff_offset;     /* set by ppm_batch_plan: first voxel in the FF arena */
+    int64_t brick_begin;   /* set by ppm_batch_plan: first FF work item */
+} ppm_batch_mol;
+
+/* One scan job: molecule `mol` scanned with `probe` over `scan`.  The probe's
+ * R_pp, eps_pp and q_pp must equal those the batch's force fields were built
+ * with; its springs and d0 may differ per job.  Outputs are stacks
+ * [scan.nz][scan.ny][scan.nx] (fz) and [scan.nz-2m][scan.ny][scan.nx] (df). */
+typedef struct {
+    ppm_probe probe;
+    ppm_scan scan;
+    int32_t mol;
+    int32_t reserved;
+    int64_t fz_offset;     /* set by ppm_batch_plan: first value in the fz arena */
+    int64_t df_offset;     /* set by ppm_batch_plan: first value in the df arena */
+    int64_t tile_begin;    /* set by ppm_batch_plan: first scan work item */
+} ppm_batch_scan;
+
+/*
+ * ppm_batch_plan -- host-only bookkeeping.  Validates the tables (host memory),
+ * fills their offset fields in place and returns the sizes in totals[5]:
+ *   totals[0] force-field voxels (the FF arena holds 4 floats per voxel)
+ *   totals[1] force-field work items, totals[2] fz values, totals[3] df values
+ *   (0 if dfp is NULL), totals[4] scan work items.
+ * All jobs must share scan.dz when dfp is given.  Errors: PPM_EINVAL for bad
+ * tables (as the single-molecule calls would report), PPM_EUNSUPPORTED for a
+ * stencil wider than 32 or jobs with different dz.
+ */
+ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
+                          ppm_batch_scan *jobs, const ppm_df_params *dfp, int64_t *totals);
+
+/*
+ * ppm_batch_build_ff -- force fields of every molecule (as ppm_build_ff) in one
+ * launch.  mols_host/mols_dev: the planned table in host and device memory
+ * (same content); probe: the probe's LJ parameters and charge; pos/q/R/eps:
+ * concatenated atoms (device, FP64); ff_arena: device, totals[0] x 4 floats.
+ */
+ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
+                              const ppm_batch_mol *mols_dev, const ppm_probe *probe,
+                              const double *pos, const double *q, const double *R,
+                              const double *eps, float *ff_arena, void *stream);
+
+/*
+ * ppm_batch_relaxed_scan -- every scan job (as ppm_relaxed_scan, FIRE and
+ * frequency-shift settings shared) in one launch, with the frequency shift
+ * fused.  fz_arena (totals[2] floats) may be NULL when dfp is given; df_arena
+ * (totals[3] floats) is required with dfp.  With more than 256 heights in any
+ * job and a frequency shift, fz_arena is required.
+ */
+ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
+                                  const ppm_batch_mol *mols_dev, int32_t n_jobs,
+                                  const ppm_batch_scan *jobs_host,
+                                  const ppm_batch_scan *jobs_dev, const ppm_fire *fire,
+                                  const ppm_df_params *dfp, const float *ff_arena,
+                                  float *fz_arena, float *df_arena, void *stream);
 
 #ifdef __cplusplus
 }

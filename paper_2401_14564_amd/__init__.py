@@ -9,6 +9,8 @@ the current HIP stream; every computation runs in the library's HIP kernels.
   df(fz, dz, dfp)                              -> df  [nz-2m, ny, nx] float32
   relaxed_scan_backward(...)                   -> dict(pos, q, R, eps) float64
   AFMStack.apply(pos, q, R, eps, grid, probe, fire, scan, dfp) -> df  (autograd)
+  BatchPipeline(molecules, jobs, probe, fire, dfp)   many molecules x probes in
+      one force-field launch and one scan launch, replayable as a HIP graph
 
 Parameter objects are read by attribute (see workloads.py for the dataclasses).
 Atoms may be given as a workloads.Atoms or as a tuple of device tensors
@@ -21,7 +23,7 @@ import torch
 from . import _lib
 
 __all__ = ["build_ff", "relaxed_scan", "df", "df_half_width", "relaxed_scan_backward",
-           "AFMStack", "atoms_to_device"]
+           "AFMStack", "atoms_to_device", "BatchPipeline"]
 
 
 def _stream():
@@ -157,3 +159,106 @@ class AFMStack(torch.autograd.Function):
         g = relaxed_scan_backward(grid, ff, probe, scan, dfp, (pos, q, R, eps), pp, grad_df)
         return (g["pos"].to(pos.dtype), g["q"].to(q.dtype), g["R"].to(R.dtype),
                 g["eps"].to(eps.dtype), None, None, None, None, None)
+
+
+class BatchPipeline:
+    """Force fields of many molecules and scans of many (molecule, probe) jobs,
+    one launch per stage (ppm_batch_build_ff, ppm_batch_relaxed_scan).
+
+    molecules: list of (atoms, grid); jobs: list of (molecule index, probe, scan).
+    The force fields are built with `probe`'s LJ parameters and charge; every
+    job's probe must share them (its springs may differ).  Tables, atoms and
+    arenas are allocated once here; run() only launches, so it can be captured
+    with capture() and replayed with replay()."""
+
+    def __init__(self, molecules, jobs, probe, fire, dfp, keep_fz: bool = False, device=None):
+        import ctypes as ct
+        L = _lib.lib()
+        dev = device or _device()
+        self.n_mol, self.n_jobs = len(molecules), len(jobs)
+        self.mols = (_lib.BatchMol * self.n_mol)()
+        begin = 0
+        pos, q, R, eps = [], [], [], []
+        for i, (atoms, grid) in enumerate(molecules):
+            self.mols[i].grid = _lib.grid_struct(grid)
+            self.mols[i].atom_begin = begin
+            self.mols[i].n_atoms = int(atoms.n)
+            begin += int(atoms.n)
+            pos.append(torch.as_tensor(atoms.pos, dtype=torch.float64).reshape(-1, 3))
+            q.append(torch.as_tensor(atoms.q, dtype=torch.float64))
+            R.append(torch.as_tensor(atoms.R, dtype=torch.float64))
+            eps.append(torch.as_tensor(atoms.eps, dtype=torch.float64))
+        self.jobs = (_lib.BatchScan * self.n_jobs)()
+        for j, (mi, pr, sc) in enumerate(jobs):
+            self.jobs[j].probe = _lib.probe_struct(pr)
+            self.jobs[j].scan = _lib.scan_struct(sc)
+            self.jobs[j].mol = int(mi)
+        self.dfp = None if dfp is None else _lib.df_struct(dfp)
+        totals = (ct.c_int64 * 5)()
+        _lib.check(L.ppm_batch_plan(self.n_mol, self.mols, self.n_jobs, self.jobs, self.dfp,
+                                    totals), "ppm_batch_plan")
+        self.totals = [int(v) for v in totals]
+        self.mols_dev = torch.frombuffer(bytearray(bytes(self.mols)), dtype=torch.uint8).to(dev)
+        self.jobs_dev = torch.frombuffer(bytearray(bytes(self.jobs)), dtype=torch.uint8).to(dev)
+        self.pos = torch.cat(pos).contiguous().to(dev)
+        self.q = torch.cat(q).contiguous().to(dev)
+        self.R = torch.cat(R).contiguous().to(dev)
+        self.eps = torch.cat(eps).contiguous().to(dev)
+        self.ff = torch.empty((self.totals[0], 4), dtype=torch.float32, device=dev)
+        self.fz = (torch.empty(self.totals[2], dtype=torch.float32, device=dev)
+                   if keep_fz or dfp is None else None)
+        self.df = (torch.empty(self.totals[3], dtype=torch.float32, device=dev)
+                   if dfp is not None else None)
+        self.probe = _lib.probe_struct(probe)
+        self.fire = _lib.fire_struct(fire)
+        self.m = 0 if dfp is None else df_half_width(dfp.A, jobs[0][2].dz)
+        self.graph = None
+
+    def build_ff(self):
+        L = _lib.lib()
+        st = L.ppm_batch_build_ff(self.n_mol, self.mols, _lib.ptr(self.mols_dev), self.probe,
+                                  _lib.ptr(self.pos), _lib.ptr(self.q), _lib.ptr(self.R),
+                                  _lib.ptr(self.eps), _lib.ptr(self.ff), _stream())
+        _lib.check(st, "ppm_batch_build_ff")
+
+    def scan(self):
+        L = _lib.lib()
+        st = L.ppm_batch_relaxed_scan(self.n_mol, self.mols, _lib.ptr(self.mols_dev), self.n_jobs,
+                                      self.jobs, _lib.ptr(self.jobs_dev), self.fire, self.dfp,
+                                      _lib.ptr(self.ff), _lib.ptr(self.fz), _lib.ptr(self.df),
+                                      _stream())
+        _lib.check(st, "ppm_batch_relaxed_scan")
+
+    def run(self):
+        self.build_ff()
+        self.scan()
+
+    def capture(self):
+        """Record run() into a HIP graph (torch.cuda.CUDAGraph)."""
+        self.run()                       # warm up outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    # views into the arenas ------------------------------------------------
+    def ff_grid(self, i):
+        M = self.mols[i]
+        n = M.grid.n
+        v = int(n[0]) * int(n[1]) * int(n[2])
+        return self.ff[M.ff_offset:M.ff_offset + v].view(int(n[2]), int(n[1]), int(n[0]), 4)
+
+    def df_stack(self, j):
+        J = self.jobs[j]
+        nz, ny, nx = J.scan.nz - 2 * self.m, J.scan.ny, J.scan.nx
+        return self.df[J.df_offset:J.df_offset + nz * ny * nx].view(nz, ny, nx)
+
+    def fz_stack(self, j):
+        J = self.jobs[j]
+        nz, ny, nx = J.scan.nz, J.scan.ny, J.scan.nx
+        return self.fz[J.fz_offset:J.fz_offset + nz * ny * nx].view(nz, ny, nx)

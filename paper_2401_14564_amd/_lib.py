@@ -22,7 +22,8 @@ PPM_EUNSUPPORTED = -4
 EXPORTED = (
     "ppm_status_string", "ppm_last_hip_error", "ppm_df_half_width", "ppm_build_ff",
     "ppm_relaxed_scan", "ppm_df", "ppm_backward_workspace_bytes",
-    "ppm_relaxed_scan_backward",
+    "ppm_relaxed_scan_backward", "ppm_batch_plan", "ppm_batch_build_ff",
+    "ppm_batch_relaxed_scan",
 )
 
 
@@ -63,6 +64,16 @@ class DfParams(ct.Structure):
     _fields_ = [("A", ct.c_double), ("f0", ct.c_double), ("k_cant", ct.c_double)]
 
 
+class BatchMol(ct.Structure):
+    _fields_ = [("grid", Grid), ("atom_begin", ct.c_int32), ("n_atoms", ct.c_int32),
+                ("ff_offset", ct.c_int64), ("brick_begin", ct.c_int64)]
+
+
+class BatchScan(ct.Structure):
+    _fields_ = [("probe", Probe), ("scan", Scan), ("mol", ct.c_int32), ("reserved", ct.c_int32),
+                ("fz_offset", ct.c_int64), ("df_offset", ct.c_int64), ("tile_begin", ct.c_int64)]
+
+
 _LIB = None
 _LOCK = threading.Lock()
 
@@ -97,6 +108,15 @@ def lib():
                                                     i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                                     vp, ct.c_size_t, vp]
             L.ppm_relaxed_scan_backward.restype = st
+            L.ppm_batch_plan.argtypes = [i32, P(BatchMol), i32, P(BatchScan), P(DfParams),
+                                         P(ct.c_int64)]
+            L.ppm_batch_plan.restype = st
+            L.ppm_batch_build_ff.argtypes = [i32, P(BatchMol), vp, P(Probe), vp, vp, vp, vp, vp,
+                                             vp]
+            L.ppm_batch_build_ff.restype = st
+            L.ppm_batch_relaxed_scan.argtypes = [i32, P(BatchMol), vp, i32, P(BatchScan), vp,
+                                                 P(Fire), P(DfParams), vp, vp, vp, vp]
+            L.ppm_batch_relaxed_scan.restype = st
             _LIB = L
     return _LIB
 

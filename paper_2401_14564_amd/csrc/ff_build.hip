@@ -23,25 +23,45 @@
 //    cutoff + brick half-diagonal < L/2, which the host checks), atoms beyond
 //    cutoff + half-diagonal of the centre are dropped with a deterministic
 //    ballot compaction, and each pair is masked by rho^2 < cutoff^2.
+#include "ppm.h"
 #include "ppm_kernels.h"
 
 namespace ppm {
 namespace {
 
+template <int BX, int BY, int NZB>
+__device__ __host__ __forceinline__ double ff_brick_half_diagonal_dev(double hx, double hy,
+                                                                      double hz)
+{
+    const double ex = 0.5 * (BX - 1) * hx, ey = 0.5 * (BY - 1) * hy, ez = 0.5 * (NZB - 1) * hz;
+    return sqrt(ex * ex + ey * ey + ez * ez);
+}
+
+// LDS of one brick: staged atoms and per-wave counts of the compaction.
+template <int NT>
+struct BrickLds {
+    float4 geo[NT];   // brick-local (x, y, z) and R_iP^2
+    float4 par[NT];   // e_iP, 12 e_iP, kq_i
+    int wcnt[NT / 64];
+};
+
+// One brick of BX x BY x NZB voxels with corner voxel (ix0, iy0, iz0).
 template <int BX, int BY, int NZB, bool PERIODIC>
-__global__ __launch_bounds__(BX * BY) void ff_build_kernel(
-    const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
-    const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
+__device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int iz0,
+                                         const double *__restrict__ pos,
+                                         const double *__restrict__ q,
+                                         const double *__restrict__ R,
+                                         const double *__restrict__ eps,
+                                         float4 *__restrict__ ff, BrickLds<BX * BY> &lds)
 {
     constexpr int NT = BX * BY;
     constexpr int NW = NT / 64;
-    __shared__ float4 s_geo[NT];   // brick-local (x, y, z) and R_iP^2
-    __shared__ float4 s_par[NT];   // e_iP, 12 e_iP, kq_i
-    __shared__ int s_wcnt[NW];
+    float4 *s_geo = lds.geo;
+    float4 *s_par = lds.par;
+    int *s_wcnt = lds.wcnt;
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
-    const int ix0 = blockIdx.x * BX, iy0 = blockIdx.y * BY, iz0 = blockIdx.z * NZB;
 
     // brick centre in FP64
     const double hcx = 0.5 * (BX - 1), hcy = 0.5 * (BY - 1), hcz = 0.5 * (NZB - 1);
@@ -140,6 +160,67 @@ __global__ __launch_bounds__(BX * BY) void ff_build_kernel(
     }
 }
 
+template <int BX, int BY, int NZB, bool PERIODIC>
+__global__ __launch_bounds__(BX * BY) void ff_build_kernel(
+    const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
+    const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
+{
+    __shared__ BrickLds<BX * BY> lds;
+    ff_brick<BX, BY, NZB, PERIODIC>(a, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * NZB, pos, q,
+                                    R, eps, ff, lds);
+}
+
+// Batched build: one block per brick of any molecule of the batch.  The
+// molecule of a brick is found by a binary search over the table's
+// brick_begin (wave-uniform, scalar loads); its grid, atom range and arena
+// offset come from the table.  The probe (mixing parameters) is shared.
+template <int BX, int BY, int NZB>
+__global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
+    const FFArgs probe_args, const ppm_batch_mol *__restrict__ mols, int n_mol,
+    const double *__restrict__ pos, const double *__restrict__ q, const double *__restrict__ R,
+    const double *__restrict__ eps, float4 *__restrict__ arena)
+{
+    __shared__ BrickLds<BX * BY> lds;
+    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    int lo = 0, hi = n_mol - 1;               // last molecule with brick_begin <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mols[mid].brick_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ppm_batch_mol &M = mols[lo];
+    const int nbx = (M.grid.n[0] + BX - 1) / BX, nby = (M.grid.n[1] + BY - 1) / BY;
+    const long long local = b - M.brick_begin;
+    const int bz = (int)(local / ((long long)nbx * nby));
+    if (bz * NZB >= M.grid.n[2]) return;      // past the last brick of the batch
+    const int rest = (int)(local - (long long)bz * nbx * nby);
+    FFArgs a = probe_args;
+    a.ox = M.grid.origin[0];
+    a.oy = M.grid.origin[1];
+    a.oz = M.grid.origin[2];
+    a.hx = M.grid.step[0];
+    a.hy = M.grid.step[1];
+    a.hz = M.grid.step[2];
+    a.nx = M.grid.n[0];
+    a.ny = M.grid.n[1];
+    a.nz = M.grid.n[2];
+    a.n_atoms = M.n_atoms;
+    const int off = M.atom_begin;
+    float4 *ff = arena + M.ff_offset;
+    if (M.grid.periodic_xy) {
+        const double hd = ff_brick_half_diagonal_dev<BX, BY, NZB>(a.hx, a.hy, a.hz);
+        a.Lx = a.nx * a.hx;
+        a.Ly = a.ny * a.hy;
+        a.rc2 = (float)(M.grid.cutoff * M.grid.cutoff);
+        a.cull2 = (M.grid.cutoff + hd) * (M.grid.cutoff + hd);
+        ff_brick<BX, BY, NZB, true>(a, (rest % nbx) * BX, (rest / nbx) * BY, bz * NZB,
+                                    pos + 3 * (size_t)off, q + off, R + off, eps + off, ff, lds);
+    } else {
+        ff_brick<BX, BY, NZB, false>(a, (rest % nbx) * BX, (rest / nbx) * BY, bz * NZB,
+                                     pos + 3 * (size_t)off, q + off, R + off, eps + off, ff, lds);
+    }
+}
+
 constexpr int kBX = 64, kBY = 4, kNZB = 8;
 
 }  // namespace
@@ -148,8 +229,12 @@ constexpr int kBX = 64, kBY = 4, kNZB = 8;
 // against its half-diagonal).
 double ff_brick_half_diagonal(double hx, double hy, double hz)
 {
-    const double ex = 0.5 * (kBX - 1) * hx, ey = 0.5 * (kBY - 1) * hy, ez = 0.5 * (kNZB - 1) * hz;
-    return sqrt(ex * ex + ey * ey + ez * ez);
+    return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
+}
+
+long long ff_brick_count(int nx, int ny, int nz)
+{
+    return (long long)((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + kNZB - 1) / kNZB);
 }
 
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
@@ -163,6 +248,21 @@ hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
     else
         hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false>), grid, block, 0, stream,
                            a, pos, q, R, eps, ff);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *mols_dev,
+                                 int n_mol, long long n_bricks, const double *pos,
+                                 const double *q, const double *R, const double *eps,
+                                 float4 *arena, hipStream_t stream)
+{
+    if (n_bricks <= 0) return hipSuccess;
+    // 2-D grid: x up to 65536 blocks per row, as many rows as needed
+    const long long gx = n_bricks < 65536 ? n_bricks : 65536;
+    const long long gy = (n_bricks + gx - 1) / gx;
+    hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB>), dim3((unsigned)gx, (unsigned)gy, 1),
+                       dim3(kBX, kBY, 1), 0, stream, probe_args, mols_dev, n_mol, pos, q, R, eps,
+                       arena);
     return hipGetLastError();
 }
 

@@ -7,10 +7,6 @@
 #include "ppm.h"
 #include "ppm_kernels.h"
 
-namespace ppm {
-double ff_brick_half_diagonal(double hx, double hy, double hz);
-}
-
 using namespace ppm;
 
 namespace {
@@ -124,22 +120,7 @@ ScanArgs make_scan_args(const ppm_grid *g, const ppm_probe *p, const ppm_fire *f
 {
     ScanArgs a;
     memset(&a, 0, sizeof(a));
-    a.ox = g->origin[0];
-    a.oy = g->origin[1];
-    a.oz = g->origin[2];
-    a.ihx = 1.0 / g->step[0];
-    a.ihy = 1.0 / g->step[1];
-    a.ihz = 1.0 / g->step[2];
-    a.gnx = g->n[0];
-    a.gny = g->n[1];
-    a.gnz = g->n[2];
-    a.kx = p->k_lat[0];
-    a.ky = p->k_lat[1];
-    a.kR = p->k_rad;
-    a.d0x = p->d0[0];
-    a.d0y = p->d0[1];
-    a.d0z = p->d0[2];
-    a.R0 = sqrt(p->d0[0] * p->d0[0] + p->d0[1] * p->d0[1] + p->d0[2] * p->d0[2]);
+    fill_scan_geometry(a, *g, *p, *s);
     if (f) {
         a.dt0 = f->dt0;
         a.dt_max = f->dt_max;
@@ -152,15 +133,6 @@ ScanArgs make_scan_args(const ppm_grid *g, const ppm_probe *p, const ppm_fire *f
         a.n_min = f->n_min;
         a.max_iter = f->max_iter;
     }
-    a.x0 = s->x0;
-    a.y0 = s->y0;
-    a.sdx = s->dx;
-    a.sdy = s->dy;
-    a.z_top = s->z_top;
-    a.sdz = s->dz;
-    a.snx = s->nx;
-    a.sny = s->ny;
-    a.snz = s->nz;
     return a;
 }
 
@@ -262,6 +234,7 @@ ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_pro
         if (m < 1) return PPM_EINVAL;
         if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
         if (scan->nz < 2 * m + 1) return PPM_EINVAL;
+        if (scan->nz > kMaxScanLdsHeights && !fz) return PPM_EUNSUPPORTED;
         if ((st = df_weights(dfp, scan->dz, m, &W)) != PPM_OK) return st;
         a.m = m;
         a.ndf = scan->nz - 2 * m;
@@ -345,6 +318,162 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
                                       reinterpret_cast<const float4 *>(pp), grad_df, pos, q, R,
                                       eps, rec, partial, g_pos, g_q, g_R, g_eps,
                                       (hipStream_t)stream));
+}
+
+static bool same_probe_lj(const ppm_probe &a, const ppm_probe &b)
+{
+    return a.R_pp == b.R_pp && a.eps_pp == b.eps_pp && a.q_pp == b.q_pp;
+}
+
+ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
+                          ppm_batch_scan *jobs, const ppm_df_params *dfp, int64_t *totals)
+{
+    if (n_mol < 1 || n_jobs < 0 || !mols || (n_jobs > 0 && !jobs) || !totals) return PPM_EINVAL;
+    ppm_status st;
+    long long vox = 0, bricks = 0;
+    for (int i = 0; i < n_mol; ++i) {
+        ppm_batch_mol &M = mols[i];
+        if ((st = check_grid(&M.grid)) != PPM_OK) return st;
+        if (M.n_atoms < 0 || M.atom_begin < 0) return PPM_EINVAL;
+        if (M.grid.periodic_xy) {
+            const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
+            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1], M.grid.step[2]);
+            if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
+                return PPM_EINVAL;
+        }
+        M.ff_offset = vox;
+        M.brick_begin = bricks;
+        vox += (long long)M.grid.n[0] * M.grid.n[1] * M.grid.n[2];
+        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2]);
+    }
+    long long nfz = 0, ndf = 0, tiles = 0;
+    int m = 0;
+    if (dfp) {
+        if (n_jobs > 0) {
+            m = df_half_width(dfp->A, jobs[0].scan.dz);
+            if (m < 1) return PPM_EINVAL;
+            if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+        }
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        ppm_batch_scan &J = jobs[j];
+        if (J.mol < 0 || J.mol >= n_mol) return PPM_EINVAL;
+        if ((st = check_probe(&J.probe)) != PPM_OK) return st;
+        if ((st = check_scan(&J.scan)) != PPM_OK) return st;
+        if (dfp) {
+            if (J.scan.dz != jobs[0].scan.dz) return PPM_EUNSUPPORTED;
+            if (J.scan.nz < 2 * m + 1) return PPM_EINVAL;
+        }
+        J.fz_offset = nfz;
+        J.df_offset = ndf;
+        J.tile_begin = tiles;
+        nfz += (long long)J.scan.nx * J.scan.ny * J.scan.nz;
+        if (dfp) ndf += (long long)J.scan.nx * J.scan.ny * (J.scan.nz - 2 * m);
+        tiles += scan_tile_count(J.scan.nx, J.scan.ny);
+    }
+    totals[0] = vox;
+    totals[1] = bricks;
+    totals[2] = nfz;
+    totals[3] = ndf;
+    totals[4] = tiles;
+    return PPM_OK;
+}
+
+ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
+                              const ppm_batch_mol *mols_dev, const ppm_probe *probe,
+                              const double *pos, const double *q, const double *R,
+                              const double *eps, float *ff_arena, void *stream)
+{
+    if (n_mol < 1 || !mols_host || !mols_dev || !ff_arena) return PPM_EINVAL;
+    ppm_status st;
+    if ((st = check_probe(probe)) != PPM_OK) return st;
+    long long total_atoms = 0, bricks = 0, vox = 0;
+    for (int i = 0; i < n_mol; ++i) {
+        const ppm_batch_mol &M = mols_host[i];
+        if ((st = check_grid(&M.grid)) != PPM_OK) return st;
+        if (M.n_atoms < 0 || M.atom_begin < 0) return PPM_EINVAL;
+        if (M.ff_offset != vox || M.brick_begin != bricks) return PPM_EINVAL;   // not planned
+        if (M.grid.periodic_xy) {
+            const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
+            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1], M.grid.step[2]);
+            if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
+                return PPM_EINVAL;
+        }
+        const long long end = (long long)M.atom_begin + M.n_atoms;
+        if (end > total_atoms) total_atoms = end;
+        vox += (long long)M.grid.n[0] * M.grid.n[1] * M.grid.n[2];
+        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2]);
+    }
+    if (total_atoms > 0 && (!pos || !q || !R || !eps)) return PPM_EINVAL;
+    FFArgs a;
+    memset(&a, 0, sizeof(a));
+    a.R_pp = probe->R_pp;
+    a.eps_pp = probe->eps_pp;
+    a.kq_pp = kCoulomb * probe->q_pp;
+    return hip_status(launch_build_ff_batch(a, mols_dev, n_mol, bricks, pos, q, R, eps,
+                                            reinterpret_cast<float4 *>(ff_arena),
+                                            (hipStream_t)stream));
+}
+
+ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
+                                  const ppm_batch_mol *mols_dev, int32_t n_jobs,
+                                  const ppm_batch_scan *jobs_host,
+                                  const ppm_batch_scan *jobs_dev, const ppm_fire *fire,
+                                  const ppm_df_params *dfp, const float *ff_arena,
+                                  float *fz_arena, float *df_arena, void *stream)
+{
+    if (n_mol < 1 || n_jobs < 1 || !mols_host || !mols_dev || !jobs_host || !jobs_dev ||
+        !ff_arena)
+        return PPM_EINVAL;
+    ppm_status st;
+    if ((st = check_fire(fire)) != PPM_OK) return st;
+    if (!fz_arena && !df_arena) return PPM_EINVAL;
+    if (df_arena && !dfp) return PPM_EINVAL;
+    int m = 0;
+    if (df_arena) {
+        m = df_half_width(dfp->A, jobs_host[0].scan.dz);
+        if (m < 1) return PPM_EINVAL;
+        if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
+    }
+    bool wide = false;
+    for (int i = 0; i < n_mol; ++i) {
+        if ((st = check_grid(&mols_host[i].grid)) != PPM_OK) return st;
+        const double bytes = 16.0 * mols_host[i].grid.n[0] * (double)mols_host[i].grid.n[1] *
+                             mols_host[i].grid.n[2];
+        if (bytes >= 4294967296.0) wide = true;
+    }
+    long long nfz = 0, ndf = 0, tiles = 0;
+    int max_nz = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const ppm_batch_scan &J = jobs_host[j];
+        if (J.mol < 0 || J.mol >= n_mol) return PPM_EINVAL;
+        if ((st = check_probe(&J.probe)) != PPM_OK) return st;
+        if ((st = check_scan(&J.scan)) != PPM_OK) return st;
+        if (J.fz_offset != nfz || J.tile_begin != tiles) return PPM_EINVAL;   // not planned
+        if (df_arena) {
+            if (J.scan.dz != jobs_host[0].scan.dz) return PPM_EUNSUPPORTED;
+            if (J.scan.nz < 2 * m + 1) return PPM_EINVAL;
+            if (J.df_offset != ndf) return PPM_EINVAL;
+            ndf += (long long)J.scan.nx * J.scan.ny * (J.scan.nz - 2 * m);
+        }
+        if (J.scan.nz > max_nz) max_nz = J.scan.nz;
+        nfz += (long long)J.scan.nx * J.scan.ny * J.scan.nz;
+        tiles += scan_tile_count(J.scan.nx, J.scan.ny);
+    }
+    if (df_arena && max_nz > kMaxScanLdsHeights && !fz_arena) return PPM_EUNSUPPORTED;
+    ScanArgs proto = make_scan_args(&mols_host[jobs_host[0].mol].grid, &jobs_host[0].probe, fire,
+                                    &jobs_host[0].scan);
+    DfWeights W;
+    memset(&W, 0, sizeof(W));
+    proto.m = 0;
+    if (df_arena) {
+        if ((st = df_weights(dfp, jobs_host[0].scan.dz, m, &W)) != PPM_OK) return st;
+        proto.m = m;
+    }
+    return hip_status(launch_relaxed_scan_batch(proto, W, mols_dev, jobs_dev, n_jobs, tiles,
+                                                max_nz, wide,
+                                                reinterpret_cast<const float4 *>(ff_arena),
+                                                fz_arena, df_arena, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+
+#include "ppm.h"
 
 namespace ppm {
 
@@ -13,6 +16,9 @@ constexpr double kCoulomb = 14.3996454784;
 constexpr double kEvPerA2InNewtonPerM = 16.02176634;
 // Largest supported frequency-shift half-width (samples on each side).
 constexpr int kMaxDfHalfWidth = 32;
+// Largest scan height count whose per-lane Fz column (one 64-lane block) fits
+// in 64 KiB of LDS; taller scans with a fused frequency shift need the fz output.
+constexpr int kMaxScanLdsHeights = 256;
 
 // ---------------------------------------------------------------- FF build
 struct FFArgs {
@@ -27,6 +33,13 @@ struct FFArgs {
     double cull2;             // (cutoff + brick half-diagonal)^2 (periodic only)
 };
 
+hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *mols_dev,
+                                 int n_mol, long long n_bricks, const double *pos,
+                                 const double *q, const double *R, const double *eps,
+                                 float4 *arena, hipStream_t stream);
+double ff_brick_half_diagonal(double hx, double hy, double hz);
+long long ff_brick_count(int nx, int ny, int nz);
+
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
                            const double *R, const double *eps, float4 *ff,
                            hipStream_t stream);
@@ -36,6 +49,8 @@ struct ScanArgs {
     // grid (interpolation)
     double ox, oy, oz;
     double ihx, ihy, ihz;     // inverse steps
+    double oxi, oyi, ozi;     // -origin * inverse step (grid coordinate = r * ih + oi)
+    double ignx, igny;        // 1/gnx, 1/gny
     int gnx, gny, gnz;
     // probe
     double kx, ky, kR, R0;
@@ -52,6 +67,44 @@ struct ScanArgs {
     int tiles_x, n_tiles;     // tile decomposition of the tip lattice
 };
 
+// Grid, probe and tip-lattice fields of ScanArgs (FIRE, frequency-shift and
+// tiling fields are set by the caller).  Used on the host for single scans and
+// per block on the device for batched scans.
+__host__ __device__ inline void fill_scan_geometry(ScanArgs &a, const ppm_grid &g,
+                                                   const ppm_probe &p, const ppm_scan &s)
+{
+    a.ox = g.origin[0];
+    a.oy = g.origin[1];
+    a.oz = g.origin[2];
+    a.ihx = 1.0 / g.step[0];
+    a.ihy = 1.0 / g.step[1];
+    a.ihz = 1.0 / g.step[2];
+    a.oxi = -g.origin[0] / g.step[0];
+    a.oyi = -g.origin[1] / g.step[1];
+    a.ozi = -g.origin[2] / g.step[2];
+    a.gnx = g.n[0];
+    a.gny = g.n[1];
+    a.gnz = g.n[2];
+    a.ignx = 1.0 / g.n[0];
+    a.igny = 1.0 / g.n[1];
+    a.kx = p.k_lat[0];
+    a.ky = p.k_lat[1];
+    a.kR = p.k_rad;
+    a.d0x = p.d0[0];
+    a.d0y = p.d0[1];
+    a.d0z = p.d0[2];
+    a.R0 = sqrt(p.d0[0] * p.d0[0] + p.d0[1] * p.d0[1] + p.d0[2] * p.d0[2]);
+    a.x0 = s.x0;
+    a.y0 = s.y0;
+    a.sdx = s.dx;
+    a.sdy = s.dy;
+    a.z_top = s.z_top;
+    a.sdz = s.dz;
+    a.snx = s.nx;
+    a.sny = s.ny;
+    a.snz = s.nz;
+}
+
 // Frequency-shift weights padded to the ring-buffer length 2*kMaxDfHalfWidth+1,
 // prefactor included: df(o) = sum_j w[j] * ring[j], ring[j] = Fz(k - (2M - j)).
 struct DfWeights {
@@ -60,6 +113,16 @@ struct DfWeights {
 
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream);
+
+// Batched scan: one 8x8 column tile per block over all jobs of the batch.
+// `proto` carries the FIRE and frequency-shift fields shared by the batch.
+hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
+                                     const ppm_batch_mol *mols_dev,
+                                     const ppm_batch_scan *jobs_dev, int n_jobs,
+                                     long long n_tiles, int max_nz, bool wide,
+                                     const float4 *arena, float *fz_arena, float *df_arena,
+                                     hipStream_t stream);
+long long scan_tile_count(int nx, int ny);
 
 hipError_t launch_df(const float *fz, int nz, int ny, int nx, int m, const DfWeights &w,
                      float *df, hipStream_t stream);

@@ -9,8 +9,9 @@
 // (Eq. 3), evaluated as a sliding dot product over a register ring.
 //
 // Design:
-//  * One lane per tip column; a block of 16 x 16 lanes covers a compact tile of
-//    columns so the gathers of a wave touch neighbouring voxels.  Tiles are
+//  * One lane per tip column; a block of 8 x 8 lanes (one wave) covers a compact
+//    tile of columns so its gathers touch neighbouring voxels, and a
+//    paper-scale scan (240 x 240 columns) spreads over all 256 CUs.  Tiles are
 //    assigned so that consecutive tiles land on the same XCD (the hardware
 //    deals blocks round-robin over 8 XCDs), which keeps a tile neighbourhood's
 //    force-field band in one L2.
@@ -23,73 +24,88 @@
 //    force balance can be resolved far below the FP32 rounding of absolute
 //    coordinates.  The grid itself is FP32 (16 B per voxel, one float4 gather
 //    per corner).
+#include "ppm.h"
+#include "ppm_device.h"
 #include "ppm_kernels.h"
 
 namespace ppm {
 namespace {
 
-constexpr int kTX = 16, kTY = 16;
+constexpr int kTX = 8, kTY = 8;
 
 struct Cell {
-    int i000;                  // flat index of corner (ix, iy, iz)
+    uint32_t i000;             // flat index of corner (ix, iy, iz)
     int dx1, dy1, dz1;         // index offsets to the +x, +y, +z corners
     double tx, ty, tz;         // fractional position in the cell
-    bool zin;                  // false when z was clamped
 };
 
-__device__ __forceinline__ int wrap_index(double f, int n)
+// Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
+// A NaN or huge coordinate is clamped before the integer conversion so the
+// index is always inside [0, n).
+__device__ __forceinline__ int periodic_cell(double u, int n, double &t)
 {
-    // f is integral; return f mod n in [0, n).  NaN, inf or huge values map to a
-    // valid index (the conversion below is only reached with a finite, in-range w).
-    double w = f - (double)n * floor(f / (double)n);
-    if (!(w >= 0.0 && w < (double)n)) w = 0.0;
-    const int i = (int)w;
-    return i >= n ? n - 1 : i;
+    double f = floor(u);
+    t = u - f;
+    f = fmin(fmax(f, -1.0e9), 1.0e9);
+    int i = (int)f;
+    i += (i < 0) ? n : 0;
+    i -= (i >= n) ? n : 0;
+    if ((unsigned)i >= (unsigned)n) {   // more than one period away (rare)
+        i %= n;
+        i += (i < 0) ? n : 0;
+    }
+    return i;
 }
 
 __device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
 {
     Cell c;
-    const double ux = (x - a.ox) * a.ihx, uy = (y - a.oy) * a.ihy, uz = (z - a.oz) * a.ihz;
-    const double fx = floor(ux), fy = floor(uy);
-    c.tx = ux - fx;
-    c.ty = uy - fy;
-    const int ix = wrap_index(fx, a.gnx), iy = wrap_index(fy, a.gny);
-    double fz = floor(uz);
-    c.zin = true;
-    if (!(fz >= 0.0)) {   // below the grid, or NaN
-        fz = 0.0;
-        c.tz = 0.0;
-        c.zin = false;
-    } else if (fz > (double)(a.gnz - 2)) {
-        fz = (double)(a.gnz - 2);
-        c.tz = 1.0;
-        c.zin = false;
-    } else {
-        c.tz = uz - fz;
-    }
-    const int iz = (int)fz;
+    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
+    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
+    // z is clamped to the first/last cell: outside the grid the field is constant
+    const double uz = fma(z, a.ihz, a.ozi);
+    const double fz = floor(uz);
+    const bool below = !(fz >= 0.0);                 // also catches NaN
+    const bool above = fz > (double)(a.gnz - 2);
+    c.tz = below ? 0.0 : (above ? 1.0 : uz - fz);
+    const int iz = below ? 0 : (above ? a.gnz - 2 : (int)fz);
     const int plane = a.gnx * a.gny;
-    c.i000 = iz * plane + iy * a.gnx + ix;
+    c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
     c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
     c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
     c.dz1 = plane;
     return c;
 }
 
+// Corner load.  WIDE grids (16 B x voxels >= 4 GiB) need 64-bit addressing;
+// otherwise a 32-bit byte offset from the (scalar) base address suffices.
+template <bool WIDE>
+__device__ __forceinline__ float3 corner(const float4 *__restrict__ ff, uint32_t i)
+{
+    if (WIDE) {
+        const float4 *p = ff + (size_t)i;
+        return make_float3(p->x, p->y, p->z);
+    } else {
+        const float4 *p = reinterpret_cast<const float4 *>(
+            reinterpret_cast<const char *>(ff) + (uint32_t)(i * 16u));
+        return make_float3(p->x, p->y, p->z);
+    }
+}
+
 // Trilinear interpolation of (Fx, Fy, Fz) in FP64 from FP32 corner values.
+template <bool WIDE>
 __device__ __forceinline__ void interp(const float4 *__restrict__ ff, const Cell &c,
                                        double &Fx, double &Fy, double &Fz)
 {
-    const int i0 = c.i000;
-    const float4 v000 = ff[i0];
-    const float4 v100 = ff[i0 + c.dx1];
-    const float4 v010 = ff[i0 + c.dy1];
-    const float4 v110 = ff[i0 + c.dx1 + c.dy1];
-    const float4 v001 = ff[i0 + c.dz1];
-    const float4 v101 = ff[i0 + c.dz1 + c.dx1];
-    const float4 v011 = ff[i0 + c.dz1 + c.dy1];
-    const float4 v111 = ff[i0 + c.dz1 + c.dx1 + c.dy1];
+    const uint32_t i0 = c.i000;
+    const float3 v000 = corner<WIDE>(ff, i0);
+    const float3 v100 = corner<WIDE>(ff, i0 + c.dx1);
+    const float3 v010 = corner<WIDE>(ff, i0 + c.dy1);
+    const float3 v110 = corner<WIDE>(ff, i0 + c.dx1 + c.dy1);
+    const float3 v001 = corner<WIDE>(ff, i0 + c.dz1);
+    const float3 v101 = corner<WIDE>(ff, i0 + c.dz1 + c.dx1);
+    const float3 v011 = corner<WIDE>(ff, i0 + c.dz1 + c.dy1);
+    const float3 v111 = corner<WIDE>(ff, i0 + c.dz1 + c.dx1 + c.dy1);
     const double tx = c.tx, ty = c.ty, tz = c.tz;
     const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
     const double w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
@@ -103,46 +119,35 @@ __device__ __forceinline__ void interp(const float4 *__restrict__ ff, const Cell
          w001 * v001.z + w101 * v101.z + w011 * v011.z + w111 * v111.z;
 }
 
-// Tip springs, Eq. 2: F^T = -k_R (|d| - R0) d/|d| - k_xy (.) (d - d0).
+// Tip springs, Eq. 2: F^T = -k_R (|d| - R0) d/|d| - k_xy (.) (d - d0),
+// with (|d| - R0)/|d| = 1 - R0/|d|.
 __device__ __forceinline__ void tip_force(const ScanArgs &a, double dx, double dy, double dz,
                                           double &Fx, double &Fy, double &Fz)
 {
-    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    const double fr = -a.kR * (dn - a.R0) / dn;
+    const double id = rsqrt_d(dx * dx + dy * dy + dz * dz);
+    const double fr = -a.kR * fma(-a.R0, id, 1.0);
     Fx = fr * dx - a.kx * (dx - a.d0x);
     Fy = fr * dy - a.ky * (dy - a.d0y);
     Fz = fr * dz;
 }
 
-template <int M>
-__global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
-    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, float *__restrict__ fz_out,
-    float4 *__restrict__ pp_out, float *__restrict__ df_out)
+// DFMODE 0: no frequency shift; 1: each lane keeps its column's Fz in LDS and
+// evaluates the frequency shift after its last height; 2: same, reading the
+// column back from the caller's fz output (used when the column does not fit
+// in LDS).  Either way the per-step loop only pays a store per finished height:
+// with lanes converging at different steps, some lane of a wave changes height
+// on almost every step, so anything on that path is paid on every step.
+// One tip column (ix, iy): all heights, then (DFMODE != 0) its frequency shift.
+template <int DFMODE, bool WIDE>
+__device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
+                                            int iy, int lane, const float4 *__restrict__ ff,
+                                            float *__restrict__ fz_out,
+                                            float4 *__restrict__ pp_out,
+                                            float *__restrict__ df_out, float *s_col)
 {
-    // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
-    // contiguous range of tiles.
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int per = (nb + 7) / 8;
-    const int rem = nb % 8;
-    const int xcd = b % 8, loc = b / 8;
-    // tiles are split into 8 ranges; ranges of the first `rem` XCDs have `per`
-    // tiles, the others per-1 (when rem != 0)
-    int tile;
-    if (rem == 0) tile = xcd * per + loc;
-    else tile = (xcd < rem) ? xcd * per + loc : rem * per + (xcd - rem) * (per - 1) + loc;
-    const int ix = (tile % a.tiles_x) * kTX + (int)threadIdx.x;
-    const int iy = (tile / a.tiles_x) * kTY + (int)threadIdx.y;
-    if (ix >= a.snx || iy >= a.sny) return;
-
     const size_t plane = (size_t)a.snx * a.sny;
     const size_t col = (size_t)iy * a.snx + ix;
     const double ax = a.x0 + ix * a.sdx, ay = a.y0 + iy * a.sdy;
-
-    // frequency-shift ring: ring[j] holds Fz of height k - (2M - j)
-    float ring[2 * M + 1];
-#pragma unroll
-    for (int j = 0; j < 2 * M + 1; ++j) ring[j] = 0.0f;
 
     int k = 0;
     double az = a.z_top;
@@ -154,31 +159,20 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
     while (true) {
         double Sx, Sy, Sz, Tx, Ty, Tz;
         const Cell c = locate(a, rx, ry, rz);
-        interp(ff, c, Sx, Sy, Sz);
+        interp<WIDE>(ff, c, Sx, Sy, Sz);
         tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
         const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
         const double g2 = Gx * Gx + Gy * Gy + Gz * Gz;
-        if (g2 < a.f_conv2 || it >= a.max_iter) {
+        const bool conv = g2 < a.f_conv2;
+        if (conv || it >= a.max_iter) {
             // record this height
             const float fzv = (float)(-Tz);
             const size_t o = (size_t)k * plane + col;
             if (fz_out) fz_out[o] = fzv;
-            if (pp_out) {
-                const float itf = (g2 < a.f_conv2) ? (float)it : -(float)it;
+            if (DFMODE == 1) s_col[k * (kTX * kTY) + lane] = fzv;
+            if (pp_out)
                 pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
-                                        (float)(rz - az - a.d0z), itf);
-            }
-            if (M > 0) {
-#pragma unroll
-                for (int j = 0; j < 2 * M; ++j) ring[j] = ring[j + 1];
-                ring[2 * M] = fzv;
-                if (df_out && k >= 2 * a.m) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < 2 * M + 1; ++j) s = fmaf(wts.w[j], ring[j], s);
-                    df_out[(size_t)(k - 2 * a.m) * plane + col] = s;
-                }
-            }
+                                        (float)(rz - az - a.d0z), conv ? (float)it : -(float)it);
             if (++k >= a.snz) break;
             // warm start: keep the relaxed position, move with the anchor
             const double naz = a.z_top - k * a.sdz;
@@ -191,25 +185,25 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
             it = 0;
             continue;
         }
-        if (it > 0) {
+        {
+            // FIRE velocity update, branch-free (lanes of a wave disagree on the
+            // sign of P): from the second step on, P > 0 mixes v towards G and,
+            // after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
+            // the particle, shrinks dt and resets alpha.
             const double P = Gx * vx + Gy * vy + Gz * vz;
-            if (P > 0.0) {
-                const double vn2 = vx * vx + vy * vy + vz * vz;
-                const double sc = alpha * sqrt(vn2 / g2);
-                const double om = 1.0 - alpha;
-                vx = om * vx + sc * Gx;
-                vy = om * vy + sc * Gy;
-                vz = om * vz + sc * Gz;
-                if (++npos > a.n_min) {
-                    dt = fmin(dt * a.f_inc, a.dt_max);
-                    alpha *= a.f_alpha;
-                }
-            } else {
-                vx = vy = vz = 0.0;
-                dt *= a.f_dec;
-                alpha = a.alpha0;
-                npos = 0;
-            }
+            const bool pos = (it > 0) && (P > 0.0);
+            const bool neg = (it > 0) && !(P > 0.0);
+            const double vn2 = vx * vx + vy * vy + vz * vz;
+            const double mix = alpha * vn2 * rsqrt_d(vn2 * g2);   // alpha |v| / |G|
+            const double sc = pos ? mix : 0.0;
+            const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
+            vx = om * vx + sc * Gx;
+            vy = om * vy + sc * Gy;
+            vz = om * vz + sc * Gz;
+            npos = pos ? npos + 1 : (neg ? 0 : npos);
+            const bool grow = pos && npos > a.n_min;
+            dt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
+            alpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
         }
         const double h = dt * a.inv_mass;
         vx += Gx * h;
@@ -220,6 +214,80 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
         rz += vz * dt;
         ++it;
     }
+
+    if (DFMODE != 0) {
+        // Eq. 3 over the finished column: output o uses samples o .. o + 2m,
+        // wts.w[j] weighting sample o + j.
+        const int m2 = 2 * a.m;
+        for (int o = 0; o + m2 < a.snz; ++o) {
+            float s = 0.0f;
+            for (int j = 0; j <= m2; ++j) {
+                const float f = (DFMODE == 1) ? s_col[(o + j) * (kTX * kTY) + lane]
+                                              : fz_out[(size_t)(o + j) * plane + col];
+                s = fmaf(wts.w[j], f, s);
+            }
+            df_out[(size_t)o * plane + col] = s;
+        }
+    }
+}
+
+template <int DFMODE, bool WIDE>
+__global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
+    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, float *__restrict__ fz_out,
+    float4 *__restrict__ pp_out, float *__restrict__ df_out)
+{
+    extern __shared__ float s_col[];   // DFMODE 1: [snz][kTX * kTY]
+    // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
+    // contiguous range of tiles.
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int per = (nb + 7) / 8;
+    const int rem = nb % 8;
+    const int xcd = b % 8, loc = b / 8;
+    // tiles are split into 8 ranges; ranges of the first `rem` XCDs have `per`
+    // tiles, the others per-1 (when rem != 0)
+    int tile;
+    if (rem == 0) tile = xcd * per + loc;
+    else tile = (xcd < rem) ? xcd * per + loc : rem * per + (xcd - rem) * (per - 1) + loc;
+    const int lane = (int)threadIdx.y * kTX + (int)threadIdx.x;
+    const int ix = (tile % a.tiles_x) * kTX + (int)threadIdx.x;
+    const int iy = (tile / a.tiles_x) * kTY + (int)threadIdx.y;
+    if (ix >= a.snx || iy >= a.sny) return;
+    scan_column<DFMODE, WIDE>(a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col);
+}
+
+// Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
+// job of a tile is found by a binary search over tile_begin (wave-uniform);
+// the job's probe and tip lattice, its molecule's grid and the arena offsets
+// come from the tables; FIRE and frequency-shift settings are shared.
+template <int DFMODE, bool WIDE>
+__global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
+    const ScanArgs proto, const DfWeights wts, const ppm_batch_mol *__restrict__ mols,
+    const ppm_batch_scan *__restrict__ jobs, int n_jobs, const float4 *__restrict__ arena,
+    float *__restrict__ fz_arena, float *__restrict__ df_arena)
+{
+    extern __shared__ float s_col[];
+    const long long t = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;              // last job with tile_begin <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const ppm_batch_scan &J = jobs[lo];
+    const ppm_batch_mol &M = mols[J.mol];
+    ScanArgs a = proto;
+    fill_scan_geometry(a, M.grid, J.probe, J.scan);
+    const int tiles_x = (J.scan.nx + kTX - 1) / kTX;
+    const long long local = t - J.tile_begin;
+    if (local >= (long long)tiles_x * ((J.scan.ny + kTY - 1) / kTY)) return;   // past the end
+    const int lane = (int)threadIdx.y * kTX + (int)threadIdx.x;
+    const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
+    const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
+    if (ix >= a.snx || iy >= a.sny) return;
+    scan_column<DFMODE, WIDE>(a, wts, ix, iy, lane, arena + M.ff_offset,
+                              fz_arena ? fz_arena + J.fz_offset : nullptr, nullptr,
+                              df_arena ? df_arena + J.df_offset : nullptr, s_col);
 }
 
 // Standalone frequency shift: one lane per (x, y) column sliding along z.
@@ -247,6 +315,16 @@ __global__ __launch_bounds__(256) void df_kernel(const float *__restrict__ fz, i
     }
 }
 
+// Weights in sample order for the end-of-column evaluation: o.w[j] multiplies
+// sample o + j of output o, i.e. lag 2m - j in the ring layout.
+DfWeights sample_weights(const DfWeights &w, int m)
+{
+    DfWeights o{};
+    const int K = kMaxDfHalfWidth;
+    for (int j = 0; j <= 2 * m; ++j) o.w[j] = w.w[2 * K - (2 * m - j)];
+    return o;
+}
+
 // Pad the weights of half-width m into the ring layout of capacity M.
 DfWeights repad(const DfWeights &w, int m, int M)
 {
@@ -259,27 +337,81 @@ DfWeights repad(const DfWeights &w, int m, int M)
 
 }  // namespace
 
+template <bool WIDE>
+void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, float *fz,
+                      float4 *pp, float *df, hipStream_t stream)
+{
+    dim3 block(kTX, kTY, 1);
+    dim3 grid(b.n_tiles, 1, 1);
+    if (b.m == 0 || !df) {
+        hipLaunchKernelGGL((relaxed_scan_kernel<0, WIDE>), grid, block, 0, stream, b, w, ff, fz,
+                           pp, nullptr);
+    } else if (b.snz <= kMaxScanLdsHeights) {
+        const size_t lds = (size_t)b.snz * kTX * kTY * sizeof(float);
+        hipLaunchKernelGGL((relaxed_scan_kernel<1, WIDE>), grid, block, lds, stream, b,
+                           sample_weights(w, b.m), ff, fz, pp, df);
+    } else {
+        // the column does not fit in LDS: the host requires fz for this case
+        hipLaunchKernelGGL((relaxed_scan_kernel<2, WIDE>), grid, block, 0, stream, b,
+                           sample_weights(w, b.m), ff, fz, pp, df);
+    }
+}
+
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    dim3 block(kTX, kTY, 1);
     ScanArgs b = a;
     b.tiles_x = (a.snx + kTX - 1) / kTX;
     b.n_tiles = b.tiles_x * ((a.sny + kTY - 1) / kTY);
-    dim3 grid(b.n_tiles, 1, 1);
-    if (b.m == 0) {
-        hipLaunchKernelGGL((relaxed_scan_kernel<0>), grid, block, 0, stream, b, w, ff, fz, pp,
-                           nullptr);
-    } else if (b.m <= 8) {
-        hipLaunchKernelGGL((relaxed_scan_kernel<8>), grid, block, 0, stream, b, repad(w, b.m, 8),
-                           ff, fz, pp, df);
-    } else if (b.m <= 16) {
-        hipLaunchKernelGGL((relaxed_scan_kernel<16>), grid, block, 0, stream, b,
-                           repad(w, b.m, 16), ff, fz, pp, df);
+    const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
+    if (bytes >= 4294967296.0)
+        launch_scan_mode<true>(b, w, ff, fz, pp, df, stream);
+    else
+        launch_scan_mode<false>(b, w, ff, fz, pp, df, stream);
+    return hipGetLastError();
+}
+
+long long scan_tile_count(int nx, int ny)
+{
+    return (long long)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+}
+
+template <bool WIDE>
+void launch_scan_batch_mode(const ScanArgs &proto, const DfWeights &w, const ppm_batch_mol *mols,
+                            const ppm_batch_scan *jobs, int n_jobs, dim3 grid, int max_nz,
+                            const float4 *arena, float *fz, float *df, hipStream_t stream)
+{
+    dim3 block(kTX, kTY, 1);
+    if (proto.m == 0 || !df) {
+        hipLaunchKernelGGL((relaxed_scan_batch_kernel<0, WIDE>), grid, block, 0, stream, proto, w,
+                           mols, jobs, n_jobs, arena, fz, nullptr);
+    } else if (max_nz <= kMaxScanLdsHeights) {
+        const size_t lds = (size_t)max_nz * kTX * kTY * sizeof(float);
+        hipLaunchKernelGGL((relaxed_scan_batch_kernel<1, WIDE>), grid, block, lds, stream, proto,
+                           sample_weights(w, proto.m), mols, jobs, n_jobs, arena, fz, df);
     } else {
-        hipLaunchKernelGGL((relaxed_scan_kernel<32>), grid, block, 0, stream, b,
-                           repad(w, b.m, 32), ff, fz, pp, df);
+        hipLaunchKernelGGL((relaxed_scan_batch_kernel<2, WIDE>), grid, block, 0, stream, proto,
+                           sample_weights(w, proto.m), mols, jobs, n_jobs, arena, fz, df);
     }
+}
+
+hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
+                                     const ppm_batch_mol *mols_dev,
+                                     const ppm_batch_scan *jobs_dev, int n_jobs,
+                                     long long n_tiles, int max_nz, bool wide,
+                                     const float4 *arena, float *fz_arena, float *df_arena,
+                                     hipStream_t stream)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    const long long gx = n_tiles < 65536 ? n_tiles : 65536;
+    const long long gy = (n_tiles + gx - 1) / gx;
+    dim3 grid((unsigned)gx, (unsigned)gy, 1);
+    if (wide)
+        launch_scan_batch_mode<true>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz, arena,
+                                     fz_arena, df_arena, stream);
+    else
+        launch_scan_batch_mode<false>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz, arena,
+                                      fz_arena, df_arena, stream);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 //     per-atom partial sums.
 //  3. reduce: sums the partials of every (atom, component) in a fixed order and
 //     applies the per-atom constant factors -> deterministic result.
+#include "ppm_device.h"
 #include "ppm_kernels.h"
 
 namespace ppm {
@@ -35,16 +36,6 @@ struct EqRecord {
     float4 t;         // tx, ty, tz, unused
     int4 idx;         // ix, iy, iz (cell corner), unused
 };
-
-__device__ __forceinline__ int wrap_index(double f, int n)
-{
-    // f is integral; return f mod n in [0, n).  NaN, inf or huge values map to a
-    // valid index (the conversion below is only reached with a finite, in-range w).
-    double w = f - (double)n * floor(f / (double)n);
-    if (!(w >= 0.0 && w < (double)n)) w = 0.0;
-    const int i = (int)w;
-    return i >= n ? n - 1 : i;
-}
 
 template <int M>
 __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
@@ -86,7 +77,7 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
             const double ux = (x - a.ox) * a.ihx, uy = (y - a.oy) * a.ihy, uz = (z - a.oz) * a.ihz;
             const double fx = floor(ux), fy = floor(uy);
             const double tx = ux - fx, ty = uy - fy;
-            const int cx = wrap_index(fx, a.gnx), cy = wrap_index(fy, a.gny);
+            const int cx = wrap_index(fx, a.gnx, a.ignx), cy = wrap_index(fy, a.gny, a.igny);
             double fz = floor(uz), tz;
             bool zin = true;
             if (!(fz >= 0.0)) { fz = 0.0; tz = 0.0; zin = false; }

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2401_14564_amd import _lib, workloads as W
@@ -135,3 +136,39 @@ def test_df_and_backward_reject_bad_arguments():
     args[-2] = ws
     args[10] = None                                                    # no saved probe state
     assert L.ppm_relaxed_scan_backward(*args) == E
+
+
+def test_batch_plan_offsets_on_host():
+    """ppm_batch_plan fills the table offsets and totals on the host (no GPU)."""
+    L = _lib.lib()
+    ws = [W.config3_molecule(i) for i in range(3)]
+    mols = (_lib.BatchMol * 3)()
+    begin = 0
+    for i, w in enumerate(ws):
+        mols[i].grid = _lib.grid_struct(w.grid)
+        mols[i].atom_begin = begin
+        mols[i].n_atoms = w.atoms.n
+        begin += w.atoms.n
+    jobs = (_lib.BatchScan * 6)()
+    for j in range(6):
+        w = ws[j // 2]
+        jobs[j].probe = _lib.probe_struct(w.probe)
+        jobs[j].scan = _lib.scan_struct(w.scan)
+        jobs[j].mol = j // 2
+    totals = (ct.c_int64 * 5)()
+    assert L.ppm_batch_plan(3, mols, 6, jobs, _lib.df_struct(W.DfParams()), totals) == _lib.PPM_OK
+    vox = [w.grid.nvox for w in ws]
+    assert [m.ff_offset for m in mols] == [0, vox[0], vox[0] + vox[1]]
+    assert totals[0] == sum(vox)
+    bricks = [((w.grid.n[0] + 63) // 64) * ((w.grid.n[1] + 3) // 4) * ((w.grid.n[2] + 7) // 8)
+              for w in ws]
+    assert [m.brick_begin for m in mols] == [0, bricks[0], bricks[0] + bricks[1]]
+    assert totals[1] == sum(bricks)
+    per_fz = [w.scan.nx * w.scan.ny * w.scan.nz for w in ws]
+    assert [j.fz_offset for j in jobs] == list(np.cumsum([0] + [per_fz[k // 2] for k in range(5)]))
+    assert totals[2] == 2 * sum(per_fz)
+    assert totals[3] == 2 * sum(w.scan.nx * w.scan.ny * (w.scan.nz - 10) for w in ws)
+    assert totals[4] == 6 * 256                     # 128x128 tips = 256 tiles of 8x8
+    # a job pointing at a missing molecule is rejected
+    jobs[5].mol = 3
+    assert L.ppm_batch_plan(3, mols, 6, jobs, None, totals) == _lib.PPM_EINVAL
