@@ -4,9 +4,9 @@ One step = one pass of the forward hot path over the paper-scale workload
 (60-atom molecule, 240^3 force-field grid, 240x240 tip columns x 100 heights):
 force-field build -> relaxed scan with the fused frequency shift.  Inputs are
 resident in device memory before timing starts.  The reported value is relaxed
-probe positions (pixel x height) per second of the whole job: consecutive
-steps are pipelined over two streams (the force field of step i+1 is built
-while step i scans), as a production loop over many samples would run.
+probe positions (pixel x height) per second of the whole job.  By default the
+two stages run in order on one stream; --pipeline overlaps the force-field
+build of step i+1 with the scan of step i on a second stream.
 
 Also reported, each timed separately after the main loop:
   * per-kernel durations (HIP events on the launch stream) and the roofline of
@@ -45,6 +45,9 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the backward measurement")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="overlap step i+1's force-field build with step i's scan on a second "
+                         "stream (double-buffered grid)")
     ap.add_argument("--kernels-once", action="store_true",
                     help="for rocprofv3 --pmc: a 1 GiB copy (counter calibration), then one "
                          "launch of each hot kernel on the paper-scale workload")
@@ -79,7 +82,7 @@ def kernels_once():
     w = W.config1()
     ff = ppm.build_ff(w.grid, w.probe, w.atoms)
     torch.cuda.synchronize()
-    ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False)
+    ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=True, pp=False)
     torch.cuda.synchronize()
     print("kernels-once done", flush=True)
 
@@ -172,15 +175,18 @@ def main():
     atoms = ppm.atoms_to_device(w.atoms)
     nx, ny, nz = w.grid.n
     m = ppm.df_half_width(w.df.A, w.scan.dz)
-    # Two buffers so that the force field of step i+1 can be built (stream s_ff)
-    # while step i is still scanning (stream s_scan): the scan's cost is the
-    # serial FIRE chain of its hardest columns and leaves most CUs idle.
+    # With --pipeline, two buffers let the force field of step i+1 be built
+    # (stream s_ff) while step i is still scanning (stream s_scan); by default
+    # both stages run in order on one stream.
     ffs = [torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev) for _ in range(2)]
     outs = [dict(fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32,
                                 device=dev),
                  df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
                                 device=dev)) for _ in range(2)]
-    s_ff, s_scan = torch.cuda.Stream(), torch.cuda.Stream()
+    if a.pipeline:
+        s_ff, s_scan = torch.cuda.Stream(), torch.cuda.Stream()
+    else:
+        s_ff = s_scan = torch.cuda.current_stream()
     ff_done = [torch.cuda.Event() for _ in range(2)]
     scan_done = [torch.cuda.Event() for _ in range(2)]
     for e in scan_done:
@@ -260,8 +266,9 @@ def main():
         "config": {"workload": "paper-scale plain method: 60 atoms, grid 240^3 at 0.1 A, "
                                "scan 240x240 tips x 100 heights, FIRE f_conv 1e-4 eV/A, "
                                "df A=1 A f0=30300 Hz k=1800 N/m",
-                   "pipelining": "step i+1's force-field build overlaps step i's scan on a "
-                                 "second stream (double-buffered grid)",
+                   "pipelining": ("step i+1's force-field build overlaps step i's scan on a "
+                                  "second stream (double-buffered grid)") if a.pipeline else
+                                 "none: build then scan, in order, on one stream",
                    "relaxations_per_step": n_eq, "voxels": w.grid.nvox, "atoms": w.atoms.n},
         "roofline": roof,
         "kernels": {
@@ -279,6 +286,7 @@ def main():
     if not a.no_extra:
         result["backward"] = _bench_backward(ppm, W, torch)
         result["batched"] = _bench_batch(ppm, W, torch)
+        result["large_periodic"] = _bench_large(ppm, W, torch)
 
     if not a.no_cpu:
         result["cpu_baseline"] = _cpu_baseline(w, n_eq)
@@ -414,6 +422,78 @@ def _bench_batch(ppm, W, torch, n_mol=256):
             "batched_stage_ms": {"ff_build": round(ff_ms, 3), "scan": round(scan_ms, 3)},
             "batched_ff_tflops": round(pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12, 2),
             "outputs_identical": bool(same)}
+
+
+def _pairs_within_cutoff(w):
+    """Exact number of (voxel, atom) pairs with rho < cutoff for a grid periodic
+    in x,y (minimum image; cutoff < L/2): per atom and z-layer, lattice rows
+    crossing the disc, and per row the integers inside the chord."""
+    g, at = w.grid, w.atoms
+    hx, hy, hz = g.step
+    nx, ny, nz = g.n
+    rc = g.cutoff
+    iz = np.arange(nz)
+    iy = np.arange(ny)
+    total = 0
+    for a in at.pos:
+        dz = g.origin[2] + iz * hz - a[2]
+        dz = dz[np.abs(dz) < rc]
+        r2 = rc * rc - dz * dz                                   # disc radius^2 per layer
+        # minimum-image y offsets of every lattice row
+        dy = g.origin[1] + iy * hy - a[1]
+        dy -= ny * hy * np.rint(dy / (ny * hy))
+        w2 = r2[:, None] - dy[None, :] ** 2                      # chord half-width^2
+        ok = w2 > 0
+        hw = np.sqrt(np.where(ok, w2, 0.0))
+        x0 = (g.origin[0] - a[0]) % hx                           # lattice offset in x
+        # integers k with |x0 + k hx| < hw
+        cnt = np.ceil((hw - x0) / hx) - np.floor((-hw - x0) / hx) - 1
+        total += int(np.sum(np.where(ok, cnt, 0)))
+    return total
+
+
+def _bench_large(ppm, W, torch):
+    """The large periodic workload (1,600 atoms, 400x400x300 grid, 12 A cutoff,
+    400x400 tips x 120 heights): force-field build and relaxed scan timed
+    separately with HIP events."""
+    dev = torch.device("cuda:0")
+    w = W.config2()
+    atoms = ppm.atoms_to_device(w.atoms)
+    nx, ny, nz = w.grid.n
+    ff = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev)
+    m = ppm.df_half_width(w.df.A, w.scan.dz)
+    out = dict(fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32, device=dev),
+               df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
+                              device=dev))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf, ts = [], []
+    for rep in range(4):
+        e[0].record()
+        ppm.build_ff(w.grid, w.probe, atoms, out=ff)
+        e[1].record()
+        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False,
+                         out=out)
+        e[2].record()
+        torch.cuda.synchronize()
+        if rep:
+            tf.append(e[0].elapsed_time(e[1]))
+            ts.append(e[1].elapsed_time(e[2]))
+    ff_ms, scan_ms = float(np.median(tf)), float(np.median(ts))
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=None, fz=False, pp=True)
+    iters = res["pp"][..., 3]
+    n_eq = w.scan.n_eq
+    evals = float(iters.abs().sum().item()) + n_eq
+    scan_bytes = evals * BYTES_PER_EVAL + n_eq * 4 + (w.scan.nz - 2 * m) * w.scan.nx * w.scan.ny * 4
+    pairs = _pairs_within_cutoff(w)
+    return {"workload": "400-atom flake on a 1,200-atom slab, periodic xy, 12 A cutoff, grid "
+                        "400x400x300, scan 400x400 x 120 heights",
+            "ff_ms": round(ff_ms, 3), "pairs_within_cutoff": pairs,
+            "ff_tflops": round(pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12, 2),
+            "scan_ms": round(scan_ms, 3),
+            "relaxations_per_s": round(n_eq / ((ff_ms + scan_ms) * 1e-3), 1),
+            "mean_fire_steps": round(float(iters.abs().mean().item()), 3),
+            "not_converged": int((iters < 0).sum().item()),
+            "scan_gather_gbs": round(scan_bytes / (scan_ms * 1e-3) / 1e9, 1)}
 
 
 def _cpu_baseline(w, n_eq):

@@ -18,9 +18,13 @@
  *      respect to atom positions, charges and LJ parameters, by implicit
  *      differentiation of the equilibrium condition of Eq. 1
  *                                                 -> ppm_relaxed_scan_backward
- *   5. many molecules of different sizes in one persistent launch per stage
+ *   5. many molecules of different sizes in one launch per stage
  *                                                   -> ppm_batch_build_ff,
  *                                                      ppm_batch_relaxed_scan
+ *   6. the stiffness of the probe's lateral vibration modes at the relaxed
+ *      points (Sec. 3.3)                                -> ppm_lateral_stiffness
+ *   7. the scan on a tricubic interpolant of an energy-only grid (Sec. 5.1.1)
+ *                                 -> ppm_build_energy, ppm_relaxed_scan_tricubic
  *
  * Conventions shared by every entry point
  *   - Units: lengths in Angstrom, energies in eV, charges in e, forces in eV/A,
@@ -138,8 +142,12 @@ int32_t ppm_df_half_width(double A, double dz);
  *      n_atoms >= 0 (0 gives the zero field).
  * out: ff[nz][ny][nx][4] = (Fx, Fy, Fz, E), FP32, device.
  * Voxels closer than ~1e-3 A to an atom may hold inf.
+ * Periodic grids are processed in bricks of 16 x 16 x 8 voxels, each atom taking
+ * the image nearest to the brick centre; this is the exact minimum image for
+ * every voxel of the brick when cutoff + h < min(Lx, Ly)/2, h being the brick's
+ * half-diagonal (1.12 A at 0.1 A spacing).
  * Errors: PPM_EINVAL for NULL pointers (when n_atoms > 0), n[i] < 2, steps
- * <= 0, or periodic_xy with cutoff <= 0 or cutoff + 4 A >= min(Lx, Ly)/2;
+ * <= 0, or periodic_xy with cutoff <= 0 or cutoff + h >= min(Lx, Ly)/2;
  * PPM_ERANGE if the grid has 2^31 voxels or more.
  */
 ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
@@ -168,6 +176,29 @@ ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_
 ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
                             const ppm_fire *fire, const ppm_scan *scan, float *fz,
                             float *pp, const ppm_df_params *dfp, float *df, void *stream);
+
+/*
+ * ppm_build_energy -- energy-only grid for the tricubic scan (Sec. 5.1.1 step 2:
+ * interpolating the potential tricubically avoids storing the forces).  Same
+ * sum and arguments as ppm_build_ff; out: E[nz][ny][nx] (FP32, eV).
+ */
+ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                            const double *pos, const double *q, const double *R,
+                            const double *eps, float *E, void *stream);
+
+/*
+ * ppm_relaxed_scan_tricubic -- the relaxed scan of ppm_relaxed_scan with the
+ * sample force taken from a tricubic interpolant of the energy grid instead of
+ * trilinear forces (the variant Sec. 5.1.1 step 2 describes as under test).
+ * Interpolant: Catmull-Rom (Keys a = -1/2) cubic convolution per axis on the
+ * stencil i-1..i+2; F = -grad of the interpolant.  x,y wrap; the z stencil is
+ * clamped to the grid and outside [0, nz-1] the potential is constant in z.
+ * in:  E[nz][ny][nx] from ppm_build_energy.  Outputs, errors: as ppm_relaxed_scan.
+ */
+ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,
+                                     const ppm_probe *probe, const ppm_fire *fire,
+                                     const ppm_scan *scan, float *fz, float *pp,
+                                     const ppm_df_params *dfp, float *df, void *stream);
 
 /*
  * ppm_df -- standalone frequency shift of an Fz stack (Eq. 3).
@@ -213,6 +244,23 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
                                      const float *grad_df, double *g_pos, double *g_q,
                                      double *g_R, double *g_eps, void *workspace,
                                      size_t workspace_bytes, void *stream);
+
+/*
+ * ppm_lateral_stiffness -- stiffness of the probe's lateral vibration modes at
+ * every relaxed point of a scan (Sec. 3.3: the curvature of the tip-sample
+ * interaction shifts the lateral CO mode, the basis of the IETS contrast).
+ * With K = -dG/dr at the relaxed position (spring Jacobian of Eq. 2 plus the
+ * trilinear cell Jacobian of the grid force), k_out receives the two smallest
+ * eigenvalues of (K + K^T)/2, ascending, in eV/A^2.
+ * in:  grid, ff, probe, scan as given to ppm_relaxed_scan; pp = its probe-state
+ *      output [scan.nz][scan.ny][scan.nx][4].
+ * out: k_out[scan.nz][scan.ny][scan.nx][2] (FP32); NaN where the relaxation did
+ *      not converge.
+ * Errors: as ppm_relaxed_scan for grid/probe/scan; PPM_EINVAL for NULL pointers.
+ */
+ppm_status ppm_lateral_stiffness(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                                 const ppm_scan *scan, const float *pp, float *k_out,
+                                 void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched pipeline: many molecules of different sizes, each scanned with one
@@ -265,6 +313,8 @@ ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
  * launch.  mols_host/mols_dev: the planned table in host and device memory
  * (same content); probe: the probe's LJ parameters and charge; pos/q/R/eps:
  * concatenated atoms (device, FP64); ff_arena: device, totals[0] x 4 floats.
+ * All molecules use 64 x 4 x 8-voxel bricks here, so a periodic molecule needs
+ * cutoff + (half-diagonal of that brick, 3.17 A at 0.1 A) < min(Lx, Ly)/2.
  */
 ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
                               const ppm_batch_mol *mols_dev, const ppm_probe *probe,

@@ -52,6 +52,11 @@ def lib():
             L.orc_relaxed_scan.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i, vp, d,
                                            vp, vp, vp, vp, vp]
             L.orc_residual.argtypes = [vp, vp, vp, vp, i, vp, vp, vp, vp]
+            L.orc_lateral_stiffness.argtypes = [vp, vp, vp, vp, i, vp, vp, vp]
+            L.orc_interp_tricubic.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+            L.orc_relaxed_scan_tricubic.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i, vp, d,
+                                                    vp, vp, vp, vp, vp]
+            L.orc_residual_tricubic.argtypes = [vp, vp, vp, vp, i, vp, vp, vp, vp]
             L.orc_df_m.argtypes = [d, d]
             L.orc_df_m.restype = i
             L.orc_df_weights.argtypes = [d, d, vp]
@@ -219,6 +224,68 @@ def residual(grid, ff, probe, anchors, rs, with_lambda=True):
     lib().orc_residual(_vp(g), _vp(n), _vp(_f64(ff)), _vp(_probe(probe)), m, _vp(anchors),
                        _vp(rs), _vp(gn), _vp(lam))
     return (gn, lam) if with_lambda else gn
+
+
+def interp_tricubic(En, grid, r, with_hessian=False):
+    """Tricubic (Catmull-Rom) interpolated energy, force -grad E and Hessian of
+    the energy grid En [nz][ny][nx] at point r."""
+    g, n = _grid(grid)
+    En = _f64(En)
+    E = np.zeros(1)
+    F = np.zeros(3)
+    H = np.zeros(9) if with_hessian else None
+    lib().orc_interp_tricubic(_vp(En), _vp(g), _vp(n), _vp(_f64(r)), _vp(E), _vp(F), _vp(H))
+    return (E[0], F, H.reshape(3, 3)) if with_hessian else (E[0], F)
+
+
+def relaxed_scan_tricubic(grid, En, probe, fire, scan, cols=None, polish_tol=0.0,
+                          with_lambda=False):
+    """Relaxed scan on the tricubic potential of the energy grid En [nz][ny][nx];
+    same outputs as relaxed_scan."""
+    g, n = _grid(grid)
+    f, fi = _fire(fire)
+    s, ns = _scan(scan)
+    if cols is None:
+        cols = all_columns(scan)
+    cols = np.ascontiguousarray(cols, dtype=np.int32).reshape(-1, 2)
+    nc, nz = len(cols), scan.nz
+    En = _f64(En)
+    assert En.shape == (grid.n[2], grid.n[1], grid.n[0])
+    r = np.zeros((nc, nz, 3))
+    fz = np.zeros((nc, nz))
+    it = np.zeros((nc, nz), dtype=np.int32)
+    gn = np.zeros((nc, nz))
+    lam = np.zeros((nc, nz)) if with_lambda else None
+    lib().orc_relaxed_scan_tricubic(_vp(g), _vp(n), _vp(En), _vp(_probe(probe)), _vp(f), _vp(fi),
+                                    _vp(s), _vp(ns), nc, _vp(cols), float(polish_tol), _vp(r),
+                                    _vp(fz), _vp(it), _vp(gn), _vp(lam))
+    out = dict(cols=cols, r=r, fz=fz, iters=it, gnorm=gn)
+    if with_lambda:
+        out["lam"] = lam
+    return out
+
+
+def residual_tricubic(grid, En, probe, anchors, rs, with_lambda=True):
+    g, n = _grid(grid)
+    anchors = _f64(anchors).reshape(-1, 3)
+    rs = _f64(rs).reshape(-1, 3)
+    m = len(rs)
+    gn = np.zeros(m)
+    lam = np.zeros(m) if with_lambda else None
+    lib().orc_residual_tricubic(_vp(g), _vp(n), _vp(_f64(En)), _vp(_probe(probe)), m,
+                                _vp(anchors), _vp(rs), _vp(gn), _vp(lam))
+    return (gn, lam) if with_lambda else gn
+
+
+def lateral_stiffness(grid, ff, probe, anchors, rs):
+    """Two smallest eigenvalues of sym(-dG/dr) at probe positions rs (soft modes)."""
+    g, n = _grid(grid)
+    anchors = _f64(anchors).reshape(-1, 3)
+    rs = _f64(rs).reshape(-1, 3)
+    out = np.zeros((len(rs), 2))
+    lib().orc_lateral_stiffness(_vp(g), _vp(n), _vp(_f64(ff)), _vp(_probe(probe)), len(rs),
+                                _vp(anchors), _vp(rs), _vp(out))
+    return out
 
 
 # ---------------------------------------------------------- frequency shift --

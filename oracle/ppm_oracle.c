@@ -246,6 +246,88 @@ void orc_interp(const double *ff, const double *g, const int *n, const double *r
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tricubic interpolation of the potential (Sec. 5.1.1, step 2: the variant   */
+/* the paper is experimenting with -- store only E, interpolate it with a      */
+/* cubic in each direction and take the force as minus its gradient).          */
+/* Reading: Catmull-Rom cubic convolution (Keys, a = -1/2) on the 4-point      */
+/* stencil i-1..i+2 per axis; x,y wrap; z indices are clamped to the grid and  */
+/* outside [0, nz-1] the potential is continued constantly in z.               */
+/* ------------------------------------------------------------------------ */
+
+/* Catmull-Rom basis for the stencil offsets -1, 0, 1, 2 at fraction t, with
+ * first (dw) and second (d2w) derivatives with respect to t. */
+static void orc_cr_weights(double t, double *w, double *dw, double *d2w)
+{
+    double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+    dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
+    dw[1] = 0.5 * (9.0 * t2 - 10.0 * t);
+    dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
+    dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
+    d2w[0] = 0.5 * (-6.0 * t + 4.0);
+    d2w[1] = 0.5 * (18.0 * t - 10.0);
+    d2w[2] = 0.5 * (-18.0 * t + 8.0);
+    d2w[3] = 0.5 * (6.0 * t - 2.0);
+}
+
+/* Interpolated energy E, force F = -grad E and (if hess != NULL) the Hessian
+ * of E at r, from the energy grid En[nz][ny][nx]. */
+void orc_interp_tricubic(const double *En, const double *g, const int *n, const double *r,
+                         double *E, double *F, double *hess)
+{
+    double u[3] = { (r[0] - g[0]) / g[3], (r[1] - g[1]) / g[4], (r[2] - g[2]) / g[5] };
+    int zin = 1;
+    if (u[2] < 0.0) { u[2] = 0.0; zin = 0; }
+    if (u[2] > n[2] - 1) { u[2] = n[2] - 1; zin = 0; }
+    int base[3];
+    double t[3], w[3][4], dw[3][4], d2w[3][4];
+    for (int a = 0; a < 3; ++a) {
+        double f = floor(u[a]);
+        if (a == 2 && f > n[2] - 2) f = n[2] - 2;     /* top node: last cell, t = 1 */
+        base[a] = (int)f;
+        t[a] = u[a] - f;
+        orc_cr_weights(t[a], w[a], dw[a], d2w[a]);
+    }
+    int ix[4], iy[4], iz[4];
+    for (int s = 0; s < 4; ++s) {
+        ix[s] = orc_wrap((long)base[0] + s - 1, n[0]);
+        iy[s] = orc_wrap((long)base[1] + s - 1, n[1]);
+        int z = base[2] + s - 1;
+        iz[s] = z < 0 ? 0 : (z > n[2] - 1 ? n[2] - 1 : z);
+    }
+    double h[3] = { g[3], g[4], g[5] };
+    double e = 0, gr[3] = { 0, 0, 0 }, H[9] = { 0 };
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                double v = En[((size_t)iz[c] * n[1] + iy[b]) * n[0] + ix[a]];
+                e += w[0][a] * w[1][b] * w[2][c] * v;
+                gr[0] += dw[0][a] * w[1][b] * w[2][c] * v;
+                gr[1] += w[0][a] * dw[1][b] * w[2][c] * v;
+                gr[2] += w[0][a] * w[1][b] * dw[2][c] * v;
+                if (hess) {
+                    H[0] += d2w[0][a] * w[1][b] * w[2][c] * v;
+                    H[4] += w[0][a] * d2w[1][b] * w[2][c] * v;
+                    H[8] += w[0][a] * w[1][b] * d2w[2][c] * v;
+                    H[1] += dw[0][a] * dw[1][b] * w[2][c] * v;
+                    H[2] += dw[0][a] * w[1][b] * dw[2][c] * v;
+                    H[5] += w[0][a] * dw[1][b] * dw[2][c] * v;
+                }
+            }
+    if (!zin) { gr[2] = 0.0; H[2] = H[5] = H[8] = 0.0; }
+    *E = e;
+    for (int a = 0; a < 3; ++a) F[a] = -gr[a] / h[a];
+    if (hess) {
+        H[3] = H[1]; H[6] = H[2]; H[7] = H[5];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) hess[3 * a + b] = H[3 * a + b] / (h[a] * h[b]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tip springs (Sec. 2.1, Eq. 2)                                              */
 /*   F^T = -k_R (|d| - R0) d/|d| - k_xy (.) (d - d0),  d = r - r_TIP          */
 /* ------------------------------------------------------------------------ */
@@ -281,6 +363,27 @@ static double orc_net(const double *ff, const double *g, const int *n, const dou
     for (int k = 0; k < 3; ++k) G[k] = Ft[k] + Fs[k];
     if (J) for (int k = 0; k < 9; ++k) J[k] = Jt[k] + Js[k];
     return sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+}
+
+/* Net force with the tricubic potential (ff holds the energy grid). */
+static double orc_net_tc(const double *En, const double *g, const int *n, const double *p,
+                         const double *anchor, const double *r, double *G, double *J)
+{
+    double Ft[3], Fs[3], Jt[9], Hs[9], E;
+    orc_tip_force(r, anchor, p, Ft, J ? Jt : NULL);
+    orc_interp_tricubic(En, g, n, r, &E, Fs, J ? Hs : NULL);
+    for (int k = 0; k < 3; ++k) G[k] = Ft[k] + Fs[k];
+    if (J) for (int k = 0; k < 9; ++k) J[k] = Jt[k] - Hs[k];   /* dF^S/dr = -Hessian */
+    return sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+}
+
+/* Interpolation mode of the relaxation: 0 trilinear forces, 1 tricubic potential. */
+static double orc_net_mode(int mode, const double *ff, const double *g, const int *n,
+                           const double *p, const double *anchor, const double *r, double *G,
+                           double *J)
+{
+    return mode ? orc_net_tc(ff, g, n, p, anchor, r, G, J)
+                : orc_net(ff, g, n, p, anchor, r, G, J);
 }
 
 /* Solve the 3x3 system A x = b by Cramer's rule; returns 0 if singular. */
@@ -350,14 +453,14 @@ double orc_sym3_min_eig(const double *S_in)
  * Stops when |G| < f_conv or after max_iter steps.  Returns the number of
  * steps taken, negated if not converged.
  */
-static int orc_fire(const double *ff, const double *g, const int *n, const double *p,
-                    const double *f, const int *fi, const double *anchor, double *r,
-                    double *gnorm)
+static int orc_fire(int mode, const double *ff, const double *g, const int *n,
+                    const double *p, const double *f, const int *fi, const double *anchor,
+                    double *r, double *gnorm)
 {
     double v[3] = { 0, 0, 0 }, G[3];
     double dt = f[0], alpha = f[4];
     int npos = 0;
-    double gn = orc_net(ff, g, n, p, anchor, r, G, NULL);
+    double gn = orc_net_mode(mode, ff, g, n, p, anchor, r, G, NULL);
     int it = 0;
     while (!(gn < f[7]) && it < fi[1]) {
         if (it > 0) {
@@ -382,7 +485,7 @@ static int orc_fire(const double *ff, const double *g, const int *n, const doubl
             v[k] += G[k] * dt / f[6];
             r[k] += v[k] * dt;
         }
-        gn = orc_net(ff, g, n, p, anchor, r, G, NULL);
+        gn = orc_net_mode(mode, ff, g, n, p, anchor, r, G, NULL);
         ++it;
     }
     *gnorm = gn;
@@ -392,11 +495,11 @@ static int orc_fire(const double *ff, const double *g, const int *n, const doubl
 /* Newton refinement of an equilibrium with the exact piecewise Jacobian and a
  * backtracking line search on |G|; used only to make the oracle's equilibria
  * exact to ~1e-12 eV/A so that they serve as the expected value. */
-static double orc_polish(const double *ff, const double *g, const int *n, const double *p,
-                         const double *anchor, double *r, double tol)
+static double orc_polish(int mode, const double *ff, const double *g, const int *n,
+                         const double *p, const double *anchor, double *r, double tol)
 {
     double G[3], J[9];
-    double gn = orc_net(ff, g, n, p, anchor, r, G, J);
+    double gn = orc_net_mode(mode, ff, g, n, p, anchor, r, G, J);
     for (int iter = 0; iter < 60 && gn >= tol; ++iter) {
         double mg[3] = { -G[0], -G[1], -G[2] }, dlt[3];
         if (!orc_solve3(J, mg, dlt)) break;
@@ -405,7 +508,7 @@ static double orc_polish(const double *ff, const double *g, const int *n, const 
         double rt[3], Gt[3], Jt[9], gt = 0;
         for (int b = 0; b < 40; ++b) {
             for (int k = 0; k < 3; ++k) rt[k] = r[k] + s * dlt[k];
-            gt = orc_net(ff, g, n, p, anchor, rt, Gt, Jt);
+            gt = orc_net_mode(mode, ff, g, n, p, anchor, rt, Gt, Jt);
             if (gt < gn) { ok = 1; break; }
             s *= 0.5;
         }
@@ -419,11 +522,11 @@ static double orc_polish(const double *ff, const double *g, const int *n, const 
 }
 
 /* Stability measure at r: smallest eigenvalue of sym(-dG/dr). */
-static double orc_lambda_min(const double *ff, const double *g, const int *n,
+static double orc_lambda_min(int mode, const double *ff, const double *g, const int *n,
                              const double *p, const double *anchor, const double *r)
 {
     double G[3], J[9], S[9];
-    orc_net(ff, g, n, p, anchor, r, G, J);
+    orc_net_mode(mode, ff, g, n, p, anchor, r, G, J);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) S[3 * i + j] = -0.5 * (J[3 * i + j] + J[3 * j + i]);
     return orc_sym3_min_eig(S);
@@ -441,11 +544,11 @@ static double orc_lambda_min(const double *ff, const double *g, const int *n,
  *   r_out[3], fz_out, iters_out (negative = not converged), gnorm_out,
  *   lam_out (smallest eigenvalue of sym(-dG/dr); NULL to skip).
  */
-void orc_relaxed_scan(const double *g, const int *n, const double *ff, const double *p,
-                      const double *f, const int *fi, const double *s, const int *ns,
-                      int ncols, const int *cols, double polish_tol,
-                      double *r_out, double *fz_out, int *iters_out, double *gnorm_out,
-                      double *lam_out)
+static void orc_relaxed_scan_mode(int mode, const double *g, const int *n, const double *ff,
+                                  const double *p, const double *f, const int *fi,
+                                  const double *s, const int *ns, int ncols, const int *cols,
+                                  double polish_tol, double *r_out, double *fz_out,
+                                  int *iters_out, double *gnorm_out, double *lam_out)
 {
     int nz = ns[2];
     #pragma omp parallel for schedule(dynamic, 1)
@@ -458,8 +561,8 @@ void orc_relaxed_scan(const double *g, const int *n, const double *ff, const dou
             if (k > 0) r[2] += az - anchor[2];
             anchor[2] = az;
             double gn;
-            int it = orc_fire(ff, g, n, p, f, fi, anchor, r, &gn);
-            if (polish_tol > 0.0) gn = orc_polish(ff, g, n, p, anchor, r, polish_tol);
+            int it = orc_fire(mode, ff, g, n, p, f, fi, anchor, r, &gn);
+            if (polish_tol > 0.0) gn = orc_polish(mode, ff, g, n, p, anchor, r, polish_tol);
             double Ft[3];
             orc_tip_force(r, anchor, p, Ft, NULL);
             size_t o = (size_t)c * nz + k;
@@ -467,9 +570,86 @@ void orc_relaxed_scan(const double *g, const int *n, const double *ff, const dou
             fz_out[o] = -Ft[2];
             iters_out[o] = it;
             gnorm_out[o] = gn;
-            if (lam_out) lam_out[o] = orc_lambda_min(ff, g, n, p, anchor, r);
+            if (lam_out) lam_out[o] = orc_lambda_min(mode, ff, g, n, p, anchor, r);
         }
     }
+}
+
+/* All three eigenvalues of a symmetric 3x3 matrix, ascending (cyclic Jacobi). */
+static void orc_sym3_eigs(const double *S_in, double *ev)
+{
+    double a[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a[i][j] = S_in[3 * i + j];
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+        if (off < 1e-300) break;
+        for (int pp = 0; pp < 2; ++pp)
+            for (int qq = pp + 1; qq < 3; ++qq) {
+                if (a[pp][qq] == 0.0) continue;
+                double theta = (a[qq][qq] - a[pp][pp]) / (2.0 * a[pp][qq]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {
+                    double akp = a[k][pp], akq = a[k][qq];
+                    a[k][pp] = cs * akp - sn * akq;
+                    a[k][qq] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double apk = a[pp][k], aqk = a[qq][k];
+                    a[pp][k] = cs * apk - sn * aqk;
+                    a[qq][k] = sn * apk + cs * aqk;
+                }
+            }
+    }
+    ev[0] = a[0][0]; ev[1] = a[1][1]; ev[2] = a[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2 - i; ++j)
+            if (ev[j] > ev[j + 1]) { double t = ev[j]; ev[j] = ev[j + 1]; ev[j + 1] = t; }
+}
+
+/*
+ * Lateral vibration stiffness of the probe at relaxed points (Sec. 3.3: the
+ * stiffness of the probe's lateral modes is changed by the curvature of the
+ * tip-sample interaction).  The stiffness matrix is K = -dG/dr (springs of
+ * Eq. 2 plus the interpolated sample force); its symmetric part has one stiff
+ * radial mode and two soft (lateral) modes.  out[2k], out[2k+1] = the two
+ * smallest eigenvalues of sym(K), ascending (eV/A^2).
+ */
+void orc_lateral_stiffness(const double *g, const int *n, const double *ff, const double *p,
+                           int m, const double *anchors, const double *rs, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k < m; ++k) {
+        double G[3], J[9], S[9], ev[3];
+        orc_net(ff, g, n, p, anchors + 3 * k, rs + 3 * k, G, J);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) S[3 * i + j] = -0.5 * (J[3 * i + j] + J[3 * j + i]);
+        orc_sym3_eigs(S, ev);
+        out[2 * k] = ev[0];
+        out[2 * k + 1] = ev[1];
+    }
+}
+
+void orc_relaxed_scan(const double *g, const int *n, const double *ff, const double *p,
+                      const double *f, const int *fi, const double *s, const int *ns,
+                      int ncols, const int *cols, double polish_tol,
+                      double *r_out, double *fz_out, int *iters_out, double *gnorm_out,
+                      double *lam_out)
+{
+    orc_relaxed_scan_mode(0, g, n, ff, p, f, fi, s, ns, ncols, cols, polish_tol, r_out, fz_out,
+                          iters_out, gnorm_out, lam_out);
+}
+
+/* Relaxed scan on the tricubic potential: En is the energy grid [nz][ny][nx]. */
+void orc_relaxed_scan_tricubic(const double *g, const int *n, const double *En, const double *p,
+                               const double *f, const int *fi, const double *s, const int *ns,
+                               int ncols, const int *cols, double polish_tol,
+                               double *r_out, double *fz_out, int *iters_out,
+                               double *gnorm_out, double *lam_out)
+{
+    orc_relaxed_scan_mode(1, g, n, En, p, f, fi, s, ns, ncols, cols, polish_tol, r_out, fz_out,
+                          iters_out, gnorm_out, lam_out);
 }
 
 /* Net force and stability at given points (used for certificates). */
@@ -481,7 +661,20 @@ void orc_residual(const double *g, const int *n, const double *ff, const double 
     for (int k = 0; k < m; ++k) {
         double G[3];
         gnorm[k] = orc_net(ff, g, n, p, anchors + 3 * k, rs + 3 * k, G, NULL);
-        if (lam) lam[k] = orc_lambda_min(ff, g, n, p, anchors + 3 * k, rs + 3 * k);
+        if (lam) lam[k] = orc_lambda_min(0, ff, g, n, p, anchors + 3 * k, rs + 3 * k);
+    }
+}
+
+/* Same on the tricubic potential (En = energy grid). */
+void orc_residual_tricubic(const double *g, const int *n, const double *En, const double *p,
+                           int m, const double *anchors, const double *rs, double *gnorm,
+                           double *lam)
+{
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k < m; ++k) {
+        double G[3];
+        gnorm[k] = orc_net_tc(En, g, n, p, anchors + 3 * k, rs + 3 * k, G, NULL);
+        if (lam) lam[k] = orc_lambda_min(1, En, g, n, p, anchors + 3 * k, rs + 3 * k);
     }
 }
 

@@ -9,6 +9,9 @@ the current HIP stream; every computation runs in the library's HIP kernels.
   df(fz, dz, dfp)                              -> df  [nz-2m, ny, nx] float32
   relaxed_scan_backward(...)                   -> dict(pos, q, R, eps) float64
   AFMStack.apply(pos, q, R, eps, grid, probe, fire, scan, dfp) -> df  (autograd)
+  lateral_stiffness(grid, ff, probe, scan, pp) -> [nz, ny, nx, 2] soft-mode stiffness
+  build_energy(grid, probe, atoms)             -> E   [nz, ny, nx] float32
+  relaxed_scan_tricubic(grid, E, probe, fire, scan, dfp=None, ...) -> as relaxed_scan
   BatchPipeline(molecules, jobs, probe, fire, dfp)   many molecules x probes in
       one force-field launch and one scan launch, replayable as a HIP graph
 
@@ -23,7 +26,8 @@ import torch
 from . import _lib
 
 __all__ = ["build_ff", "relaxed_scan", "df", "df_half_width", "relaxed_scan_backward",
-           "AFMStack", "atoms_to_device", "BatchPipeline"]
+           "AFMStack", "atoms_to_device", "BatchPipeline", "lateral_stiffness",
+           "build_energy", "relaxed_scan_tricubic"]
 
 
 def _stream():
@@ -93,6 +97,45 @@ def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: boo
     return out
 
 
+def build_energy(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Energy-only grid [nz, ny, nx], float32 (input of the tricubic scan)."""
+    L = _lib.lib()
+    pos, q, R, eps = atoms_to_device(atoms)
+    nx, ny, nz = (int(v) for v in grid.n)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=pos.device)
+    assert out.shape == (nz, ny, nx) and out.dtype == torch.float32 and out.is_contiguous()
+    st = L.ppm_build_energy(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
+                            _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps), _lib.ptr(out),
+                            _stream())
+    _lib.check(st, "ppm_build_energy")
+    return out
+
+
+def relaxed_scan_tricubic(grid, E, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
+                          out: dict | None = None) -> dict:
+    """Relaxed scan on the tricubic interpolant of the energy grid E; outputs as
+    relaxed_scan."""
+    L = _lib.lib()
+    dev = E.device
+    nz, ny, nx = int(scan.nz), int(scan.ny), int(scan.nx)
+    out = dict(out or {})
+    if fz and "fz" not in out:
+        out["fz"] = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    if pp and "pp" not in out:
+        out["pp"] = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev)
+    if dfp is not None and "df" not in out:
+        m = df_half_width(dfp.A, scan.dz)
+        out["df"] = torch.empty((max(nz - 2 * m, 0), ny, nx), dtype=torch.float32, device=dev)
+    st = L.ppm_relaxed_scan_tricubic(_lib.grid_struct(grid), _lib.ptr(E), _lib.probe_struct(probe),
+                                     _lib.fire_struct(fire), _lib.scan_struct(scan),
+                                     _lib.ptr(out.get("fz")), _lib.ptr(out.get("pp")),
+                                     None if dfp is None else _lib.df_struct(dfp),
+                                     _lib.ptr(out.get("df")), _stream())
+    _lib.check(st, "ppm_relaxed_scan_tricubic")
+    return out
+
+
 def df(fz: torch.Tensor, dz: float, dfp, out: torch.Tensor | None = None) -> torch.Tensor:
     """Frequency shift of an Fz stack [nz, ny, nx] (scan-index order)."""
     L = _lib.lib()
@@ -130,11 +173,17 @@ def relaxed_scan_backward(grid, ff, probe, scan, dfp, atoms, pp, grad_df,
     return g
 
 
-class _Params:
-    """Attribute holder used to rebuild grid/probe/... objects from tensors."""
-
-    def __init__(self, **kw):
-        self.__dict__.update(kw)
+def lateral_stiffness(grid, ff, probe, scan, pp, out: torch.Tensor | None = None):
+    """Two smallest eigenvalues of the symmetric stiffness matrix -dG/dr at every
+    relaxed point (eV/A^2), [nz, ny, nx, 2]; NaN where not converged."""
+    L = _lib.lib()
+    if out is None:
+        out = torch.empty((int(scan.nz), int(scan.ny), int(scan.nx), 2), dtype=torch.float32,
+                          device=ff.device)
+    st = L.ppm_lateral_stiffness(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
+                                 _lib.scan_struct(scan), _lib.ptr(pp), _lib.ptr(out), _stream())
+    _lib.check(st, "ppm_lateral_stiffness")
+    return out
 
 
 class AFMStack(torch.autograd.Function):

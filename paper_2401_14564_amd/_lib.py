@@ -23,7 +23,8 @@ EXPORTED = (
     "ppm_status_string", "ppm_last_hip_error", "ppm_df_half_width", "ppm_build_ff",
     "ppm_relaxed_scan", "ppm_df", "ppm_backward_workspace_bytes",
     "ppm_relaxed_scan_backward", "ppm_batch_plan", "ppm_batch_build_ff",
-    "ppm_batch_relaxed_scan",
+    "ppm_batch_relaxed_scan", "ppm_lateral_stiffness", "ppm_build_energy",
+    "ppm_relaxed_scan_tricubic",
 )
 
 
@@ -117,6 +118,13 @@ def lib():
             L.ppm_batch_relaxed_scan.argtypes = [i32, P(BatchMol), vp, i32, P(BatchScan), vp,
                                                  P(Fire), P(DfParams), vp, vp, vp, vp]
             L.ppm_batch_relaxed_scan.restype = st
+            L.ppm_lateral_stiffness.argtypes = [P(Grid), vp, P(Probe), P(Scan), vp, vp, vp]
+            L.ppm_lateral_stiffness.restype = st
+            L.ppm_build_energy.argtypes = [P(Grid), P(Probe), i32, vp, vp, vp, vp, vp, vp]
+            L.ppm_build_energy.restype = st
+            L.ppm_relaxed_scan_tricubic.argtypes = [P(Grid), vp, P(Probe), P(Fire), P(Scan), vp,
+                                                    vp, P(DfParams), vp, vp]
+            L.ppm_relaxed_scan_tricubic.restype = st
             _LIB = L
     return _LIB
 

@@ -46,7 +46,9 @@ struct BrickLds {
 };
 
 // One brick of BX x BY x NZB voxels with corner voxel (ix0, iy0, iz0).
-template <int BX, int BY, int NZB, bool PERIODIC>
+// EONLY: only the energy is accumulated and stored (one float per voxel, the
+// input of the tricubic scan); `ff` then points at floats.
+template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY = false>
 __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int iz0,
                                          const double *__restrict__ pos,
                                          const double *__restrict__ q,
@@ -140,10 +142,12 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                 const float s12 = s6 * s6;
                 const float ec = p.z * ir;
                 E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + ec;
-                const float f = fmaf(p.y, s12 - s6, ec) * ir2;
-                Fx[k] = fmaf(f, dx, Fx[k]);
-                Fy[k] = fmaf(f, dy, Fy[k]);
-                Fz[k] = fmaf(f, dz, Fz[k]);
+                if (!EONLY) {
+                    const float f = fmaf(p.y, s12 - s6, ec) * ir2;
+                    Fx[k] = fmaf(f, dx, Fx[k]);
+                    Fy[k] = fmaf(f, dy, Fy[k]);
+                    Fz[k] = fmaf(f, dz, Fz[k]);
+                }
             }
         }
         __syncthreads();
@@ -154,20 +158,23 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
 #pragma unroll
         for (int k = 0; k < NZB; ++k) {
             const int iz = iz0 + k;
-            if (iz < a.nz)
-                ff[((size_t)iz * a.ny + iy) * a.nx + ix] = make_float4(Fx[k], Fy[k], Fz[k], E[k]);
+            if (iz < a.nz) {
+                const size_t o = ((size_t)iz * a.ny + iy) * a.nx + ix;
+                if (EONLY) reinterpret_cast<float *>(ff)[o] = E[k];
+                else ff[o] = make_float4(Fx[k], Fy[k], Fz[k], E[k]);
+            }
         }
     }
 }
 
-template <int BX, int BY, int NZB, bool PERIODIC>
+template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY = false>
 __global__ __launch_bounds__(BX * BY) void ff_build_kernel(
     const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
     const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
 {
     __shared__ BrickLds<BX * BY> lds;
-    ff_brick<BX, BY, NZB, PERIODIC>(a, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * NZB, pos, q,
-                                    R, eps, ff, lds);
+    ff_brick<BX, BY, NZB, PERIODIC, EONLY>(a, blockIdx.x * BX, blockIdx.y * BY,
+                                           blockIdx.z * NZB, pos, q, R, eps, ff, lds);
 }
 
 // Batched build: one block per brick of any molecule of the batch.  The
@@ -221,13 +228,23 @@ __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
     }
 }
 
+// Open samples: 64 x 4 x 8 bricks (a wave's stores are one 1 KiB run).  Periodic
+// samples: 16 x 16 x 8 bricks, whose small half-diagonal keeps the per-brick
+// cull sphere (cutoff + half-diagonal) close to the cutoff sphere.
 constexpr int kBX = 64, kBY = 4, kNZB = 8;
+constexpr int kPBX = 16, kPBY = 16;
 
 }  // namespace
 
 // Brick geometry used by the launcher (the host validates the periodic cutoff
 // against its half-diagonal).
 double ff_brick_half_diagonal(double hx, double hy, double hz)
+{
+    return ff_brick_half_diagonal_dev<kPBX, kPBY, kNZB>(hx, hy, hz);
+}
+
+// The batched build uses the open-sample brick for every molecule.
+double ff_batch_brick_half_diagonal(double hx, double hy, double hz)
 {
     return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
 }
@@ -240,14 +257,35 @@ long long ff_brick_count(int nx, int ny, int nz)
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
                            const double *R, const double *eps, float4 *ff, hipStream_t stream)
 {
-    dim3 block(kBX, kBY, 1);
-    dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
-    if (a.Lx > 0.0)
-        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, true>), grid, block, 0, stream,
+    if (a.Lx > 0.0) {
+        dim3 block(kPBX, kPBY, 1);
+        dim3 grid((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY, (a.nz + kNZB - 1) / kNZB);
+        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true>), grid, block, 0, stream,
                            a, pos, q, R, eps, ff);
-    else
+    } else {
+        dim3 block(kBX, kBY, 1);
+        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
         hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false>), grid, block, 0, stream,
                            a, pos, q, R, eps, ff);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_build_energy(const FFArgs &a, const double *pos, const double *q,
+                               const double *R, const double *eps, float *E, hipStream_t stream)
+{
+    float4 *out = reinterpret_cast<float4 *>(E);   // EONLY kernels store floats
+    if (a.Lx > 0.0) {
+        dim3 block(kPBX, kPBY, 1);
+        dim3 grid((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY, (a.nz + kNZB - 1) / kNZB);
+        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true, true>), grid, block, 0,
+                           stream, a, pos, q, R, eps, out);
+    } else {
+        dim3 block(kBX, kBY, 1);
+        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false, true>), grid, block, 0, stream,
+                           a, pos, q, R, eps, out);
+    }
     return hipGetLastError();
 }
 

@@ -176,58 +176,76 @@ int32_t ppm_last_hip_error(void) { return g_last_hip_error; }
 
 int32_t ppm_df_half_width(double A, double dz) { return df_half_width(A, dz); }
 
-ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
-                        const double *pos, const double *q, const double *R,
-                        const double *eps, float *ff, void *stream)
+static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                           const double *pos, const double *q, const double *R,
+                           const double *eps, const void *out, FFArgs *a)
 {
     ppm_status st = check_grid(grid);
     if (st != PPM_OK) return st;
     if ((st = check_probe(probe)) != PPM_OK) return st;
-    if (n_atoms < 0 || !ff) return PPM_EINVAL;
+    if (n_atoms < 0 || !out) return PPM_EINVAL;
     if (n_atoms > 0 && (!pos || !q || !R || !eps)) return PPM_EINVAL;
-    FFArgs a;
-    memset(&a, 0, sizeof(a));
-    a.ox = grid->origin[0];
-    a.oy = grid->origin[1];
-    a.oz = grid->origin[2];
-    a.hx = grid->step[0];
-    a.hy = grid->step[1];
-    a.hz = grid->step[2];
-    a.nx = grid->n[0];
-    a.ny = grid->n[1];
-    a.nz = grid->n[2];
-    a.n_atoms = n_atoms;
-    a.R_pp = probe->R_pp;
-    a.eps_pp = probe->eps_pp;
-    a.kq_pp = kCoulomb * probe->q_pp;
+    memset(a, 0, sizeof(*a));
+    a->ox = grid->origin[0];
+    a->oy = grid->origin[1];
+    a->oz = grid->origin[2];
+    a->hx = grid->step[0];
+    a->hy = grid->step[1];
+    a->hz = grid->step[2];
+    a->nx = grid->n[0];
+    a->ny = grid->n[1];
+    a->nz = grid->n[2];
+    a->n_atoms = n_atoms;
+    a->R_pp = probe->R_pp;
+    a->eps_pp = probe->eps_pp;
+    a->kq_pp = kCoulomb * probe->q_pp;
     if (grid->periodic_xy) {
         const double Lx = grid->n[0] * grid->step[0], Ly = grid->n[1] * grid->step[1];
         const double hd = ff_brick_half_diagonal(grid->step[0], grid->step[1], grid->step[2]);
         if (!finite_pos(grid->cutoff) || grid->cutoff + hd >= 0.5 * fmin(Lx, Ly))
             return PPM_EINVAL;
-        a.Lx = Lx;
-        a.Ly = Ly;
-        a.rc2 = (float)(grid->cutoff * grid->cutoff);
-        a.cull2 = (grid->cutoff + hd) * (grid->cutoff + hd);
+        a->Lx = Lx;
+        a->Ly = Ly;
+        a->rc2 = (float)(grid->cutoff * grid->cutoff);
+        a->cull2 = (grid->cutoff + hd) * (grid->cutoff + hd);
     }
+    return PPM_OK;
+}
+
+ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                        const double *pos, const double *q, const double *R,
+                        const double *eps, float *ff, void *stream)
+{
+    FFArgs a;
+    ppm_status st = ff_setup(grid, probe, n_atoms, pos, q, R, eps, ff, &a);
+    if (st != PPM_OK) return st;
     return hip_status(launch_build_ff(a, pos, q, R, eps, reinterpret_cast<float4 *>(ff),
                                       (hipStream_t)stream));
 }
 
-ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
-                            const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
-                            const ppm_df_params *dfp, float *df, void *stream)
+ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                            const double *pos, const double *q, const double *R,
+                            const double *eps, float *E, void *stream)
+{
+    FFArgs a;
+    ppm_status st = ff_setup(grid, probe, n_atoms, pos, q, R, eps, E, &a);
+    if (st != PPM_OK) return st;
+    return hip_status(launch_build_energy(a, pos, q, R, eps, E, (hipStream_t)stream));
+}
+
+static ppm_status scan_setup(const ppm_grid *grid, const void *field, const ppm_probe *probe,
+                             const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
+                             const ppm_df_params *dfp, float *df, ScanArgs *a, DfWeights *W)
 {
     ppm_status st;
     if ((st = check_grid(grid)) != PPM_OK) return st;
     if ((st = check_probe(probe)) != PPM_OK) return st;
     if ((st = check_fire(fire)) != PPM_OK) return st;
     if ((st = check_scan(scan)) != PPM_OK) return st;
-    if (!ff || (!fz && !pp && !df)) return PPM_EINVAL;
-    ScanArgs a = make_scan_args(grid, probe, fire, scan);
-    DfWeights W;
-    memset(&W, 0, sizeof(W));
-    a.m = 0;
+    if (!field || (!fz && !pp && !df)) return PPM_EINVAL;
+    *a = make_scan_args(grid, probe, fire, scan);
+    memset(W, 0, sizeof(*W));
+    a->m = 0;
     if (df) {
         if (!dfp) return PPM_EINVAL;
         const int m = df_half_width(dfp->A, scan->dz);
@@ -235,13 +253,38 @@ ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_pro
         if (m > kMaxDfHalfWidth) return PPM_EUNSUPPORTED;
         if (scan->nz < 2 * m + 1) return PPM_EINVAL;
         if (scan->nz > kMaxScanLdsHeights && !fz) return PPM_EUNSUPPORTED;
-        if ((st = df_weights(dfp, scan->dz, m, &W)) != PPM_OK) return st;
-        a.m = m;
-        a.ndf = scan->nz - 2 * m;
+        if ((st = df_weights(dfp, scan->dz, m, W)) != PPM_OK) return st;
+        a->m = m;
+        a->ndf = scan->nz - 2 * m;
     }
+    return PPM_OK;
+}
+
+ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                            const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
+                            const ppm_df_params *dfp, float *df, void *stream)
+{
+    ScanArgs a;
+    DfWeights W;
+    ppm_status st = scan_setup(grid, ff, probe, fire, scan, fz, pp, dfp, df, &a, &W);
+    if (st != PPM_OK) return st;
     return hip_status(launch_relaxed_scan(a, W, reinterpret_cast<const float4 *>(ff), fz,
                                           reinterpret_cast<float4 *>(pp), df,
                                           (hipStream_t)stream));
+}
+
+ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,
+                                     const ppm_probe *probe, const ppm_fire *fire,
+                                     const ppm_scan *scan, float *fz, float *pp,
+                                     const ppm_df_params *dfp, float *df, void *stream)
+{
+    ScanArgs a;
+    DfWeights W;
+    ppm_status st = scan_setup(grid, E, probe, fire, scan, fz, pp, dfp, df, &a, &W);
+    if (st != PPM_OK) return st;
+    if (grid->n[2] < 2) return PPM_EINVAL;
+    return hip_status(launch_relaxed_scan_tricubic(a, W, E, fz, reinterpret_cast<float4 *>(pp),
+                                                   df, (hipStream_t)stream));
 }
 
 ppm_status ppm_df(const float *fz, int32_t nz, int32_t ny, int32_t nx, double dz,
@@ -337,7 +380,8 @@ ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
         if (M.n_atoms < 0 || M.atom_begin < 0) return PPM_EINVAL;
         if (M.grid.periodic_xy) {
             const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
-            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1], M.grid.step[2]);
+            const double hd = ff_batch_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
+                                                           M.grid.step[2]);
             if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
                 return PPM_EINVAL;
         }
@@ -395,7 +439,8 @@ ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
         if (M.ff_offset != vox || M.brick_begin != bricks) return PPM_EINVAL;   // not planned
         if (M.grid.periodic_xy) {
             const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
-            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1], M.grid.step[2]);
+            const double hd = ff_batch_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
+                                                           M.grid.step[2]);
             if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
                 return PPM_EINVAL;
         }
@@ -474,6 +519,21 @@ ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
                                                 max_nz, wide,
                                                 reinterpret_cast<const float4 *>(ff_arena),
                                                 fz_arena, df_arena, (hipStream_t)stream));
+}
+
+ppm_status ppm_lateral_stiffness(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                                 const ppm_scan *scan, const float *pp, float *k_out,
+                                 void *stream)
+{
+    ppm_status st;
+    if ((st = check_grid(grid)) != PPM_OK) return st;
+    if ((st = check_probe(probe)) != PPM_OK) return st;
+    if ((st = check_scan(scan)) != PPM_OK) return st;
+    if (!ff || !pp || !k_out) return PPM_EINVAL;
+    ScanArgs a = make_scan_args(grid, probe, nullptr, scan);
+    return hip_status(launch_lateral_stiffness(a, reinterpret_cast<const float4 *>(ff),
+                                               reinterpret_cast<const float4 *>(pp), k_out,
+                                               (hipStream_t)stream));
 }
 
 }  // extern "C"

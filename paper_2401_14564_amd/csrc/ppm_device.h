@@ -2,6 +2,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppm_kernels.h"
 
 namespace ppm {
 
@@ -25,6 +28,83 @@ __device__ __forceinline__ double rsqrt_d(double x)
     const double h = 0.5 * x * y;
     const double r = fma(-h, y, 0.5);      // 0.5 (1 - x y^2)
     return fma(y, r, y);
+}
+
+struct Cell {
+    uint32_t i000;             // flat index of corner (ix, iy, iz)
+    int dx1, dy1, dz1;         // index offsets to the +x, +y, +z corners
+    double tx, ty, tz;         // fractional position in the cell
+    bool zin;                  // false when z was clamped (field constant in z there)
+};
+
+// Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
+// A NaN or huge coordinate is clamped before the integer conversion so the
+// index is always inside [0, n).
+__device__ __forceinline__ int periodic_cell(double u, int n, double &t)
+{
+    double f = floor(u);
+    t = u - f;
+    f = fmin(fmax(f, -1.0e9), 1.0e9);
+    int i = (int)f;
+    i += (i < 0) ? n : 0;
+    i -= (i >= n) ? n : 0;
+    if ((unsigned)i >= (unsigned)n) {   // more than one period away (rare)
+        i %= n;
+        i += (i < 0) ? n : 0;
+    }
+    return i;
+}
+
+__device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
+{
+    Cell c;
+    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
+    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
+    // z is clamped to the first/last cell: outside the grid the field is constant
+    const double uz = fma(z, a.ihz, a.ozi);
+    const double fz = floor(uz);
+    const bool below = !(fz >= 0.0);                 // also catches NaN
+    const bool above = fz > (double)(a.gnz - 2);
+    c.tz = below ? 0.0 : (above ? 1.0 : uz - fz);
+    c.zin = !(below || above);
+    const int iz = below ? 0 : (above ? a.gnz - 2 : (int)fz);
+    const int plane = a.gnx * a.gny;
+    c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
+    c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
+    c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
+    c.dz1 = plane;
+    return c;
+}
+
+// Corner load.  WIDE grids (16 B x voxels >= 4 GiB) need 64-bit addressing;
+// otherwise a 32-bit byte offset from the (scalar) base address suffices.
+template <bool WIDE>
+__device__ __forceinline__ float3 corner(const float4 *__restrict__ ff, uint32_t i)
+{
+    if (WIDE) {
+        const float4 *p = ff + (size_t)i;
+        return make_float3(p->x, p->y, p->z);
+    } else {
+        const float4 *p = reinterpret_cast<const float4 *>(
+            reinterpret_cast<const char *>(ff) + (uint32_t)(i * 16u));
+        return make_float3(p->x, p->y, p->z);
+    }
+}
+
+// The eight corner values (Fx, Fy, Fz) of a cell: v[i + 2j + 4k] is corner
+// (ix + i, iy + j, iz + k).
+template <bool WIDE>
+__device__ __forceinline__ void gather8(const float4 *__restrict__ ff, const Cell &c, float3 *v)
+{
+    const uint32_t i0 = c.i000;
+    v[0] = corner<WIDE>(ff, i0);
+    v[1] = corner<WIDE>(ff, i0 + c.dx1);
+    v[2] = corner<WIDE>(ff, i0 + c.dy1);
+    v[3] = corner<WIDE>(ff, i0 + c.dx1 + c.dy1);
+    v[4] = corner<WIDE>(ff, i0 + c.dz1);
+    v[5] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1);
+    v[6] = corner<WIDE>(ff, i0 + c.dz1 + c.dy1);
+    v[7] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1 + c.dy1);
 }
 
 }  // namespace ppm

@@ -38,6 +38,7 @@ hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *
                                  const double *q, const double *R, const double *eps,
                                  float4 *arena, hipStream_t stream);
 double ff_brick_half_diagonal(double hx, double hy, double hz);
+double ff_batch_brick_half_diagonal(double hx, double hy, double hz);
 long long ff_brick_count(int nx, int ny, int nz);
 
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
@@ -123,6 +124,14 @@ hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
                                      const float4 *arena, float *fz_arena, float *df_arena,
                                      hipStream_t stream);
 long long scan_tile_count(int nx, int ny);
+
+hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w, const float *En,
+                                        float *fz, float4 *pp, float *df, hipStream_t stream);
+hipError_t launch_build_energy(const FFArgs &a, const double *pos, const double *q,
+                               const double *R, const double *eps, float *E, hipStream_t stream);
+
+hipError_t launch_lateral_stiffness(const ScanArgs &a, const float4 *ff, const float4 *pp,
+                                    float *out, hipStream_t stream);
 
 hipError_t launch_df(const float *fz, int nz, int ny, int nx, int m, const DfWeights &w,
                      float *df, hipStream_t stream);

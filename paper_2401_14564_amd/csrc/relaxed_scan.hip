@@ -9,9 +9,9 @@
 // (Eq. 3), evaluated as a sliding dot product over a register ring.
 //
 // Design:
-//  * One lane per tip column; a block of 8 x 8 lanes (one wave) covers a compact
-//    tile of columns so its gathers touch neighbouring voxels, and a
-//    paper-scale scan (240 x 240 columns) spreads over all 256 CUs.  Tiles are
+//  * One lane per tip column; a block covers a compact tile of columns (16 x 16,
+//    four waves, for single scans; 8 x 8 for batches) so its gathers touch
+//    neighbouring voxels.  Tiles are
 //    assigned so that consecutive tiles land on the same XCD (the hardware
 //    deals blocks round-robin over 8 XCDs), which keeps a tile neighbourhood's
 //    force-field band in one L2.
@@ -32,65 +32,6 @@ namespace ppm {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
-
-struct Cell {
-    uint32_t i000;             // flat index of corner (ix, iy, iz)
-    int dx1, dy1, dz1;         // index offsets to the +x, +y, +z corners
-    double tx, ty, tz;         // fractional position in the cell
-};
-
-// Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
-// A NaN or huge coordinate is clamped before the integer conversion so the
-// index is always inside [0, n).
-__device__ __forceinline__ int periodic_cell(double u, int n, double &t)
-{
-    double f = floor(u);
-    t = u - f;
-    f = fmin(fmax(f, -1.0e9), 1.0e9);
-    int i = (int)f;
-    i += (i < 0) ? n : 0;
-    i -= (i >= n) ? n : 0;
-    if ((unsigned)i >= (unsigned)n) {   // more than one period away (rare)
-        i %= n;
-        i += (i < 0) ? n : 0;
-    }
-    return i;
-}
-
-__device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
-{
-    Cell c;
-    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
-    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
-    // z is clamped to the first/last cell: outside the grid the field is constant
-    const double uz = fma(z, a.ihz, a.ozi);
-    const double fz = floor(uz);
-    const bool below = !(fz >= 0.0);                 // also catches NaN
-    const bool above = fz > (double)(a.gnz - 2);
-    c.tz = below ? 0.0 : (above ? 1.0 : uz - fz);
-    const int iz = below ? 0 : (above ? a.gnz - 2 : (int)fz);
-    const int plane = a.gnx * a.gny;
-    c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
-    c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
-    c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
-    c.dz1 = plane;
-    return c;
-}
-
-// Corner load.  WIDE grids (16 B x voxels >= 4 GiB) need 64-bit addressing;
-// otherwise a 32-bit byte offset from the (scalar) base address suffices.
-template <bool WIDE>
-__device__ __forceinline__ float3 corner(const float4 *__restrict__ ff, uint32_t i)
-{
-    if (WIDE) {
-        const float4 *p = ff + (size_t)i;
-        return make_float3(p->x, p->y, p->z);
-    } else {
-        const float4 *p = reinterpret_cast<const float4 *>(
-            reinterpret_cast<const char *>(ff) + (uint32_t)(i * 16u));
-        return make_float3(p->x, p->y, p->z);
-    }
-}
 
 // Trilinear interpolation of (Fx, Fy, Fz) in FP64 from FP32 corner values.
 template <bool WIDE>
@@ -137,13 +78,90 @@ __device__ __forceinline__ void tip_force(const ScanArgs &a, double dx, double d
 // in LDS).  Either way the per-step loop only pays a store per finished height:
 // with lanes converging at different steps, some lane of a wave changes height
 // on almost every step, so anything on that path is paid on every step.
+// Catmull-Rom (Keys, a = -1/2) weights of the stencil offsets -1, 0, 1, 2 and
+// their derivatives with respect to the fraction t.
+__device__ __forceinline__ void cr_weights(double t, double *w, double *dw)
+{
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+    dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
+    dw[1] = 0.5 * (9.0 * t2 - 10.0 * t);
+    dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
+    dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
+}
+
+// Sample force from the tricubic interpolant of the energy grid En[nz][ny][nx]
+// (the paper's experimental variant of Sec. 5.1.1 step 2): F = -grad E_int,
+// a 4x4x4 stencil contracted axis by axis in FP64.  x,y wrap; the z stencil is
+// clamped to the grid and outside [0, nz-1] the potential is constant in z.
+__device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *__restrict__ En,
+                                               double x, double y, double z, double &Fx,
+                                               double &Fy, double &Fz)
+{
+    double tx, ty;
+    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, tx);
+    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, ty);
+    double uz = fma(z, a.ihz, a.ozi);
+    const bool below = !(uz >= 0.0);                 // also catches NaN
+    const bool above = uz > (double)(a.gnz - 1);
+    uz = below ? 0.0 : (above ? (double)(a.gnz - 1) : uz);
+    const double fz = fmin(floor(uz), (double)(a.gnz - 2));
+    const double tz = uz - fz;
+    const int iz = (int)fz;
+    double wx[4], dwx[4], wy[4], dwy[4], wz[4], dwz[4];
+    cr_weights(tx, wx, dwx);
+    cr_weights(ty, wy, dwy);
+    cr_weights(tz, wz, dwz);
+    int xs[4], ys[4], zs[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        int i = ix + s - 1, j = iy + s - 1, k = iz + s - 1;
+        i += (i < 0) ? a.gnx : 0;
+        i -= (i >= a.gnx) ? a.gnx : 0;
+        j += (j < 0) ? a.gny : 0;
+        j -= (j >= a.gny) ? a.gny : 0;
+        k = k < 0 ? 0 : (k > a.gnz - 1 ? a.gnz - 1 : k);
+        xs[s] = i;
+        ys[s] = j;
+        zs[s] = k;
+    }
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float *row = En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx;
+            const double v0 = row[xs[0]], v1 = row[xs[1]], v2 = row[xs[2]], v3 = row[xs[3]];
+            const double r0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
+            const double r1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
+            s0 += wy[b] * r0;
+            s1 += dwy[b] * r0;
+            s2 += wy[b] * r1;
+        }
+        gx += wz[c] * s2;
+        gy += wz[c] * s1;
+        gz += dwz[c] * s0;
+    }
+    Fx = -gx * a.ihx;
+    Fy = -gy * a.ihy;
+    Fz = (below || above) ? 0.0 : -gz * a.ihz;
+}
+
 // One tip column (ix, iy): all heights, then (DFMODE != 0) its frequency shift.
-template <int DFMODE, bool WIDE>
+// NL = lanes per block (the stride of the per-lane Fz columns in LDS).
+// INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
+// from the energy grid En.
+template <int DFMODE, bool WIDE, int NL, int INTERP = 0>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
                                             float *__restrict__ fz_out,
                                             float4 *__restrict__ pp_out,
-                                            float *__restrict__ df_out, float *s_col)
+                                            float *__restrict__ df_out, float *s_col,
+                                            const float *__restrict__ En = nullptr)
 {
     const size_t plane = (size_t)a.snx * a.sny;
     const size_t col = (size_t)iy * a.snx + ix;
@@ -158,8 +176,12 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
 
     while (true) {
         double Sx, Sy, Sz, Tx, Ty, Tz;
-        const Cell c = locate(a, rx, ry, rz);
-        interp<WIDE>(ff, c, Sx, Sy, Sz);
+        if (INTERP == 0) {
+            const Cell c = locate(a, rx, ry, rz);
+            interp<WIDE>(ff, c, Sx, Sy, Sz);
+        } else {
+            tricubic_force(a, En, rx, ry, rz, Sx, Sy, Sz);
+        }
         tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
         const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
         const double g2 = Gx * Gx + Gy * Gy + Gz * Gz;
@@ -169,7 +191,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             const float fzv = (float)(-Tz);
             const size_t o = (size_t)k * plane + col;
             if (fz_out) fz_out[o] = fzv;
-            if (DFMODE == 1) s_col[k * (kTX * kTY) + lane] = fzv;
+            if (DFMODE == 1) s_col[k * NL + lane] = fzv;
             if (pp_out)
                 pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
                                         (float)(rz - az - a.d0z), conv ? (float)it : -(float)it);
@@ -222,7 +244,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         for (int o = 0; o + m2 < a.snz; ++o) {
             float s = 0.0f;
             for (int j = 0; j <= m2; ++j) {
-                const float f = (DFMODE == 1) ? s_col[(o + j) * (kTX * kTY) + lane]
+                const float f = (DFMODE == 1) ? s_col[(o + j) * NL + lane]
                                               : fz_out[(size_t)(o + j) * plane + col];
                 s = fmaf(wts.w[j], f, s);
             }
@@ -231,12 +253,12 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     }
 }
 
-template <int DFMODE, bool WIDE>
-__global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
-    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, float *__restrict__ fz_out,
-    float4 *__restrict__ pp_out, float *__restrict__ df_out)
+template <int TX, int TY, int DFMODE, bool WIDE, int INTERP>
+__global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
+    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, const float *__restrict__ En,
+    float *__restrict__ fz_out, float4 *__restrict__ pp_out, float *__restrict__ df_out)
 {
-    extern __shared__ float s_col[];   // DFMODE 1: [snz][kTX * kTY]
+    extern __shared__ float s_col[];   // DFMODE 1: [snz][TX * TY]
     // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
     // contiguous range of tiles.
     const int nb = gridDim.x;
@@ -249,11 +271,13 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_kernel(
     int tile;
     if (rem == 0) tile = xcd * per + loc;
     else tile = (xcd < rem) ? xcd * per + loc : rem * per + (xcd - rem) * (per - 1) + loc;
-    const int lane = (int)threadIdx.y * kTX + (int)threadIdx.x;
-    const int ix = (tile % a.tiles_x) * kTX + (int)threadIdx.x;
-    const int iy = (tile / a.tiles_x) * kTY + (int)threadIdx.y;
+    const int lane = (int)threadIdx.y * TX + (int)threadIdx.x;
+    const int tiles_x = (a.snx + TX - 1) / TX;
+    const int ix = (tile % tiles_x) * TX + (int)threadIdx.x;
+    const int iy = (tile / tiles_x) * TY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<DFMODE, WIDE>(a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col);
+    scan_column<DFMODE, WIDE, TX * TY, INTERP>(a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out,
+                                               s_col, En);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
@@ -285,7 +309,7 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
     const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<DFMODE, WIDE>(a, wts, ix, iy, lane, arena + M.ff_offset,
+    scan_column<DFMODE, WIDE, kTX * kTY>(a, wts, ix, iy, lane, arena + M.ff_offset,
                               fz_arena ? fz_arena + J.fz_offset : nullptr, nullptr,
                               df_arena ? df_arena + J.df_offset : nullptr, s_col);
 }
@@ -337,37 +361,62 @@ DfWeights repad(const DfWeights &w, int m, int M)
 
 }  // namespace
 
-template <bool WIDE>
-void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, float *fz,
-                      float4 *pp, float *df, hipStream_t stream)
+template <int TX, int TY, bool WIDE, int INTERP>
+void launch_scan_tiles(const ScanArgs &b, int dfmode, const DfWeights &w, const float4 *ff,
+                       const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    dim3 block(kTX, kTY, 1);
-    dim3 grid(b.n_tiles, 1, 1);
-    if (b.m == 0 || !df) {
-        hipLaunchKernelGGL((relaxed_scan_kernel<0, WIDE>), grid, block, 0, stream, b, w, ff, fz,
-                           pp, nullptr);
-    } else if (b.snz <= kMaxScanLdsHeights) {
-        const size_t lds = (size_t)b.snz * kTX * kTY * sizeof(float);
-        hipLaunchKernelGGL((relaxed_scan_kernel<1, WIDE>), grid, block, lds, stream, b,
-                           sample_weights(w, b.m), ff, fz, pp, df);
+    dim3 block(TX, TY, 1);
+    dim3 grid((unsigned)(((b.snx + TX - 1) / TX) * ((b.sny + TY - 1) / TY)), 1, 1);
+    if (dfmode == 0) {
+        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 0, WIDE, INTERP>), grid, block, 0, stream,
+                           b, w, ff, En, fz, pp, nullptr);
+    } else if (dfmode == 1) {
+        const size_t lds = (size_t)b.snz * TX * TY * sizeof(float);
+        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 1, WIDE, INTERP>), grid, block, lds,
+                           stream, b, sample_weights(w, b.m), ff, En, fz, pp, df);
     } else {
-        // the column does not fit in LDS: the host requires fz for this case
-        hipLaunchKernelGGL((relaxed_scan_kernel<2, WIDE>), grid, block, 0, stream, b,
-                           sample_weights(w, b.m), ff, fz, pp, df);
+        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 2, WIDE, INTERP>), grid, block, 0, stream,
+                           b, sample_weights(w, b.m), ff, En, fz, pp, df);
+    }
+}
+
+// Block shape: 16 x 16 lanes (four waves, one per SIMD of the CU that runs the
+// block).  The kernel's time is the serial FIRE chain of its hardest columns,
+// so those must not share a SIMD; one-wave blocks leave the pairing of waves on
+// SIMDs to the dispatcher.  The fused frequency shift keeps each lane's Fz
+// column in LDS when it fits (64 heights for 256 lanes), else re-reads the fz
+// output; without fz and with more heights, 8 x 8 blocks hold up to 256 heights.
+template <bool WIDE, int INTERP>
+void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, const float *En,
+                      float *fz, float4 *pp, float *df, hipStream_t stream)
+{
+    const bool want_df = b.m != 0 && df;
+    if (!want_df) {
+        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 0, w, ff, En, fz, pp, df, stream);
+    } else if (b.snz * 256 * (int)sizeof(float) <= 65536) {
+        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 1, w, ff, En, fz, pp, df, stream);
+    } else if (fz) {
+        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 2, w, ff, En, fz, pp, df, stream);
+    } else {
+        launch_scan_tiles<kTX, kTY, WIDE, INTERP>(b, 1, w, ff, En, fz, pp, df, stream);
     }
 }
 
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    ScanArgs b = a;
-    b.tiles_x = (a.snx + kTX - 1) / kTX;
-    b.n_tiles = b.tiles_x * ((a.sny + kTY - 1) / kTY);
     const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
-        launch_scan_mode<true>(b, w, ff, fz, pp, df, stream);
+        launch_scan_mode<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
     else
-        launch_scan_mode<false>(b, w, ff, fz, pp, df, stream);
+        launch_scan_mode<false, 0>(a, w, ff, nullptr, fz, pp, df, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w, const float *En,
+                                        float *fz, float4 *pp, float *df, hipStream_t stream)
+{
+    launch_scan_mode<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
     return hipGetLastError();
 }
 

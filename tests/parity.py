@@ -73,9 +73,12 @@ def anchors_for(scan, cols):
 
 
 def grade_scan(grid, ff64, probe, fire, scan, cols, ores, gpu_pp, gpu_fz, gpu_df=None, dfp=None,
-               max_diverged_frac=0.02, label=""):
+               max_diverged_frac=0.02, label="", residual=None):
     """Compare the GPU scan (arrays [nz, ny, nx(,4)]) with the oracle result for the
-    tip columns `cols` (oracle arrays [col, k]).  Returns class counts."""
+    tip columns `cols` (oracle arrays [col, k]).  `residual` evaluates the oracle's
+    force balance at given points (default: trilinear forces from ff64).
+    Returns class counts."""
+    residual = residual or orc.residual
     cols = np.asarray(cols)
     ix, iy = cols[:, 0], cols[:, 1]
     pp = gpu_pp[:, iy, ix, :].transpose(1, 0, 2).astype(np.float64)     # [col, k, 4]
@@ -89,7 +92,7 @@ def grade_scan(grid, ff64, probe, fire, scan, cols, ores, gpu_pp, gpu_fz, gpu_df
     valid = np.ones_like(dr, dtype=bool)          # not in a diverged column segment
     diverged_cols = 0
     # certificate for every GPU point: oracle residual and stability at r_gpu
-    gres, glam = orc.residual(grid, ff64, probe, A.reshape(-1, 3), r_gpu.reshape(-1, 3))
+    gres, glam = residual(grid, ff64, probe, A.reshape(-1, 3), r_gpu.reshape(-1, 3))
     gres = gres.reshape(nc, nz)
     glam = glam.reshape(nc, nz)
     cert = gres <= 2 * fire.f_conv + 1e-6

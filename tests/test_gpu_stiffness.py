@@ -1,0 +1,57 @@
+"""Lateral vibration stiffness of the probe (Sec. 3.3) on the GPU against the
+FP64 oracle, which is pinned by closed forms (rest, constant field) and by a
+library eigensolver on an affine field."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import paper_2401_14564_amd as ppm
+from paper_2401_14564_amd import workloads as W
+from parity import LAM_GRADED, POS_TOL, anchors_for
+
+pytestmark = pytest.mark.gpu
+
+
+def test_stiffness_zero_field_is_lateral_springs():
+    grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (30, 30, 90))
+    ff = torch.zeros((90, 30, 30, 4), dtype=torch.float32, device="cuda")
+    scan = W.Scan(0.33, 0.41, 0.1, 0.1, 17, 5, 8.0, 0.1, 13)
+    probe = W.Probe(k_lat=(0.02, 0.013))
+    res = ppm.relaxed_scan(grid, ff, probe, W.Fire(), scan)
+    k = ppm.lateral_stiffness(grid, ff, probe, scan, res["pp"]).cpu().numpy()
+    np.testing.assert_allclose(k[..., 0], 0.013, rtol=1e-6)
+    np.testing.assert_allclose(k[..., 1], 0.02, rtol=1e-6)
+
+
+def test_stiffness_parity_c0():
+    w = W.config0()
+    fire = W.parity_fire(w.fire)
+    ref = orc.build_ff(w.grid, w.probe, w.atoms)
+    ff32 = ref.astype(np.float32)
+    ff64 = ff32.astype(np.float64)
+    ff = torch.as_tensor(ff32, device="cuda")
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, fire, w.scan)
+    k = ppm.lateral_stiffness(w.grid, ff, w.probe, w.scan, res["pp"]).cpu().numpy()
+    pp = res["pp"].cpu().numpy()
+    ores = orc.relaxed_scan(w.grid, ff64, w.probe, fire, w.scan, polish_tol=1e-12,
+                            with_lambda=True)
+    cols = ores["cols"]
+    A = anchors_for(w.scan, cols)
+    ko = orc.lateral_stiffness(w.grid, ff64, w.probe, A.reshape(-1, 3),
+                               ores["r"].reshape(-1, 3)).reshape(len(cols), w.scan.nz, 2)
+    kg = k[:, cols[:, 1], cols[:, 0], :].transpose(1, 0, 2)
+    rg = A + np.asarray(w.probe.d0) + pp[:, cols[:, 1], cols[:, 0], :3].transpose(1, 0, 2)
+    dr = np.linalg.norm(rg - ores["r"], axis=-1)
+    # points whose position lies within 1e-3 cell of a cell face may sit in a
+    # neighbouring cell on the other side (the trilinear Jacobian jumps there)
+    u = (ores["r"] - np.asarray(w.grid.origin)) / np.asarray(w.grid.step)
+    frac = u - np.floor(u)
+    near_face = np.any((frac < 1e-3) | (frac > 1 - 1e-3), axis=-1)
+    ok = (ores["lam"] >= LAM_GRADED) & (dr <= POS_TOL) & ~near_face
+    d = np.abs(kg - ko)
+    tol = 1e-4 + 1e-3 * np.abs(ko)
+    assert ok.mean() > 0.9
+    assert np.all(d[ok] <= tol[ok]), f"{np.sum(d[ok] > tol[ok])} off, worst {d[ok].max():.3e}"
+    print("stiffness graded", int(ok.sum()), "of", ok.size, "worst", float(d[ok].max()),
+          flush=True)

@@ -1,0 +1,56 @@
+"""Energy-only grid and the relaxed scan on its tricubic interpolant (the
+variant of Sec. 5.1.1 step 2) against the FP64 oracle, whose tricubic path is
+pinned in test_oracle_tricubic.py."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import paper_2401_14564_amd as ppm
+from paper_2401_14564_amd import workloads as W
+from parity import FF_RTOL, grade_scan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("cfg", ["config0", "config1"])
+def test_energy_grid_full(cfg):
+    w = getattr(W, cfg)()
+    ref, sc = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
+    E = ppm.build_energy(w.grid, w.probe, w.atoms).cpu().numpy().astype(np.float64)
+    ok = sc[..., 2] >= 0.5
+    err = np.abs(E - ref[..., 3])[ok] / sc[..., 1][ok]
+    assert err.max() <= FF_RTOL, err.max()
+    # the energy-only build sums exactly like the E channel of the full build
+    full = ppm.build_ff(w.grid, w.probe, w.atoms)[..., 3].cpu().numpy()
+    assert np.array_equal(full, E.astype(np.float32))
+
+
+def test_tricubic_zero_field_rest():
+    grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (30, 30, 90))
+    E = torch.zeros((90, 30, 30), dtype=torch.float32, device="cuda")
+    scan = W.Scan(0.33, 0.41, 0.1, 0.1, 17, 5, 8.0, 0.1, 13)
+    res = ppm.relaxed_scan_tricubic(grid, E, W.Probe(), W.Fire(), scan, dfp=W.DfParams())
+    assert torch.all(res["fz"] == 0) and torch.all(res["pp"] == 0) and torch.all(res["df"] == 0)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 40), (17, 5, 12)])
+def test_tricubic_scan_parity_c0(shape):
+    """Oracle energy grid rounded to FP32 feeds both sides; GPU at the parity
+    threshold against the polished oracle, graded as the trilinear scan."""
+    nx, ny, nz = shape
+    w = W.config0()
+    scan = W.Scan(w.scan.x0, w.scan.y0, 0.1, 0.1, nx, ny, w.scan.z_top, 0.1, nz)
+    fire = W.parity_fire(w.fire)
+    E32 = orc.build_ff(w.grid, w.probe, w.atoms)[..., 3].astype(np.float32)
+    E64 = E32.astype(np.float64)
+    dfp = w.df if nz >= 11 else None
+    res = ppm.relaxed_scan_tricubic(w.grid, torch.as_tensor(E32, device="cuda"), w.probe, fire,
+                                    scan, dfp=dfp)
+    g = {k: v.cpu().numpy() for k, v in res.items()}
+    ores = orc.relaxed_scan_tricubic(w.grid, E64, w.probe, fire, scan, polish_tol=1e-12,
+                                     with_lambda=True)
+    info = grade_scan(w.grid, E64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+                      g.get("df"), dfp, label=f"tricubic {shape}", residual=orc.residual_tricubic)
+    print("tricubic scan", info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]

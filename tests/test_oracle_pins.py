@@ -457,3 +457,47 @@ def test_df_weights_golden():
     path = os.path.join(os.path.dirname(__file__), "golden", "df_weights_A1.0_dz0.1.txt")
     ref = np.loadtxt(path)
     np.testing.assert_allclose(orc.df_weights(1.0, 0.1), ref, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------- lateral stiffness
+def test_lateral_stiffness_at_rest_and_in_constant_field():
+    """Sec. 3.3 lateral-mode stiffness: with no sample force the soft modes are the
+    lateral springs (k_x, k_y) of Eq. 2; under a constant vertical force c the
+    compressed radial spring adds k_R (1 - R0/|d|), |d| = R0 - c/k_R, to both."""
+    probe = W.Probe(k_lat=(0.02, 0.013), k_rad=1.3)
+    g = _grid(origin=(0, 0, 0), n=(10, 10, 80))
+    anchor = np.array([0.45, 0.55, 9.0])
+    ff = np.zeros((80, 10, 10, 4))
+    k = orc.lateral_stiffness(g, ff, probe, [anchor], [anchor + np.array(probe.d0)])[0]
+    np.testing.assert_allclose(k, [0.013, 0.02], atol=1e-15)
+    c = 0.037
+    ff[..., 2] = c
+    dn = 4.0 - c / probe.k_rad
+    r = anchor + np.array([0.0, 0.0, -dn])
+    k = orc.lateral_stiffness(g, ff, probe, [anchor], [r])[0]
+    shift = probe.k_rad * (1 - 4.0 / dn)
+    np.testing.assert_allclose(k, [0.013 + shift, 0.02 + shift], rtol=1e-12)
+
+
+def test_lateral_stiffness_affine_field_matches_eigvalsh():
+    """For an affine sample force A r + b the stiffness matrix is exact:
+    -(spring Jacobian) - A; its symmetric part's two smallest eigenvalues equal
+    numpy's symmetric eigensolver at the Newton equilibrium."""
+    rng = np.random.default_rng(21)
+    M = rng.normal(size=(3, 3)) * 0.004
+    Amat = -(M @ M.T) - 0.003 * np.eye(3) + (M - M.T) * 0.5
+    n, step, origin = (40, 40, 60), (0.1, 0.1, 0.1), (0.0, 0.0, 0.0)
+    g = _grid(origin=origin, step=step, n=n)
+    b = np.array([0.004, -0.003, 0.02]) - Amat @ np.array([2.0, 2.0, 3.0])
+    ff = _affine_ff(n, step, origin, Amat, b)
+    anchor = np.array([1.93, 2.07, 7.05])
+    r = _newton_equilibrium(anchor, PROBE, Amat, b, anchor + np.array(PROBE.d0))
+    d = r - anchor
+    dn = np.linalg.norm(d)
+    R0 = np.linalg.norm(PROBE.d0)
+    Jt = -PROBE.k_rad * ((1 - R0 / dn) * np.eye(3) + R0 * np.outer(d, d) / dn ** 3) - \
+        np.diag([PROBE.k_lat[0], PROBE.k_lat[1], 0.0])
+    K = -(Jt + Amat)
+    ref = np.linalg.eigvalsh(0.5 * (K + K.T))[:2]
+    got = orc.lateral_stiffness(g, ff, PROBE, [anchor], [r])[0]
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-14)
