@@ -41,8 +41,8 @@ def lib():
             vp = ct.c_void_p
             i = ct.c_int
             d = ct.c_double
-            L.orc_mix.argtypes = [i, vp, vp, vp, vp, vp, vp, vp]
-            L.orc_point.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_mix.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_point.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_build_ff.argtypes = [vp, vp, vp, i, vp, vp, vp, vp, i, i, vp, vp]
             L.orc_ff_voxels.argtypes = [vp, vp, vp, i, vp, vp, vp, vp, i, vp, vp, vp]
             L.orc_interp.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -83,7 +83,7 @@ def _grid(grid):
 
 def _probe(probe):
     return _f64([probe.R_pp, probe.eps_pp, probe.q_pp, probe.k_lat[0], probe.k_lat[1],
-                 probe.k_rad, *probe.d0])
+                 probe.k_rad, *probe.d0, probe.q_zz])
 
 
 def _fire(fire):
@@ -110,25 +110,26 @@ def num_threads() -> int:
 
 # ------------------------------------------------------------- force field --
 def mix(atoms, probe):
-    """Per-atom mixed parameters (R_iP, e_iP, kq_i)."""
+    """Per-atom mixed parameters (R_iP, e_iP, kq_i, kQ_i)."""
     pos, q, R, eps = _atoms(atoms)
     n = len(q)
-    RiP, eiP, kqi = np.zeros(n), np.zeros(n), np.zeros(n)
-    lib().orc_mix(n, _vp(R), _vp(eps), _vp(q), _vp(_probe(probe)), _vp(RiP), _vp(eiP), _vp(kqi))
-    return RiP, eiP, kqi
+    RiP, eiP, kqi, kQi = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_mix(n, _vp(R), _vp(eps), _vp(q), _vp(_probe(probe)), _vp(RiP), _vp(eiP), _vp(kqi),
+                  _vp(kQi))
+    return RiP, eiP, kqi, kQi
 
 
 def point_ff(points, atoms, probe, grid):
     """(Fx,Fy,Fz,E) and scale (sum|f_i|, sum|E_i|, rho_min, tie) at arbitrary points."""
     pts = _f64(points).reshape(-1, 3)
     pos, q, R, eps = _atoms(atoms)
-    RiP, eiP, kqi = mix(atoms, probe)
+    RiP, eiP, kqi, kQi = mix(atoms, probe)
     g, n = _grid(grid)
     out = np.zeros((len(pts), 4))
     sc = np.zeros((len(pts), 4))
     L = lib()
     for k in range(len(pts)):
-        L.orc_point(_vp(pts[k]), len(q), _vp(pos), _vp(RiP), _vp(eiP), _vp(kqi), _vp(g),
+        L.orc_point(_vp(pts[k]), len(q), _vp(pos), _vp(RiP), _vp(eiP), _vp(kqi), _vp(kQi), _vp(g),
                     _vp(n), _vp(out[k]), _vp(sc[k]))
     return out, sc
 

@@ -12,6 +12,8 @@
  *
  *   - per-atom mixing rules ............ Sec. 2.2.1 (Eq. 5), Sec. 2.2.2 (Eq. 6)
  *   - LJ + point-charge energy/force ... Eq. 5, Eq. 6, with F = -grad E (Sec. 2.2)
+ *   - quadrupolar probe charge ......... Sec. 2.2.3 (d_z2 charge of the CO tip,
+ *                                        moment -0.025 to -0.15 e A^2)
  *   - grid projection of the force field Sec. 5.1.1, step 1
  *   - trilinear force interpolation .... Sec. 5.1.1, step 2
  *   - tip springs ...................... Sec. 2.1, Eq. 2
@@ -48,21 +50,23 @@
 /* ------------------------------------------------------------------------ */
 /* Parameter packing (this oracle's own convention)                          */
 /*   grid  g[8]  = ox, oy, oz, hx, hy, hz, periodic_xy, cutoff ; n[3]         */
-/*   probe p[9]  = R_pp, eps_pp, q_pp, kx, ky, kR, d0x, d0y, d0z              */
+/*   probe p[10] = R_pp, eps_pp, q_pp, kx, ky, kR, d0x, d0y, d0z, q_zz        */
 /*   fire  f[8]  = dt0, dt_max, f_inc, f_dec, alpha0, f_alpha, mass, f_conv   */
 /*         fi[2] = n_min, max_iter                                             */
 /*   scan  s[6]  = x0, y0, dx, dy, z_top, dz ; ns[3] = nx, ny, nz             */
 /* ------------------------------------------------------------------------ */
 
 /* Mixing rules of Sec. 2.2.1: R_iP = R_i + R_PP, e_iP = sqrt(e_i e_PP);
- * Coulomb prefactor of Eq. 6: kq_i = k_e q_i q_PP. */
+ * Coulomb prefactor of Eq. 6: kq_i = k_e q_i q_PP; the same for the probe's
+ * quadrupole moment: kQ_i = k_e q_i q_zz (kQi may be NULL). */
 void orc_mix(int n, const double *R, const double *eps, const double *q,
-             const double *p, double *RiP, double *eiP, double *kqi)
+             const double *p, double *RiP, double *eiP, double *kqi, double *kQi)
 {
     for (int i = 0; i < n; ++i) {
         RiP[i] = R[i] + p[0];
         eiP[i] = sqrt(eps[i] * p[1]);
         kqi[i] = ORC_KE * q[i] * p[2];
+        if (kQi) kQi[i] = ORC_KE * q[i] * p[9];
     }
 }
 
@@ -81,20 +85,47 @@ static void orc_disp(const double *r, const double *a, const double *g,
 }
 
 /*
+ * Quadrupolar probe charge (Sec. 2.2.3).  The paper gives the moment of the
+ * CO tip's d_z2 charge (in e A^2) but no convention; this oracle reads it as
+ * the point density rho_PP = q_zz d^2 delta / dz^2, i.e. the limit h -> 0 of
+ * charges (+q, -2q, +q) at z + h, z, z - h with q h^2 = q_zz.  Its energy in
+ * the potential V_i = k_e q_i / |r - r_i| of atom i is the cross-correlation
+ * of Sec. 2.2.3 with this density:
+ *   E_i = q_zz d^2 V_i / dz^2 = kQ_i (3 dz^2 - rho^2) / rho^5,  kQ_i = k_e q_i q_zz,
+ * and F_i = -grad E_i = kQ_i / rho^5 [ (15 dz^2 / rho^2 - 3) d - 6 dz e_z ].
+ */
+static void orc_quad(double kQ, const double *d, double rho2, double *E, double *F,
+                     double *sE, double *sF)
+{
+    double rho = sqrt(rho2);
+    double ir5 = 1.0 / (rho2 * rho2 * rho);
+    double z = d[2];
+    double c = 15.0 * z * z / rho2 - 3.0;
+    *E += kQ * (3.0 * z * z - rho2) * ir5;
+    F[0] += kQ * ir5 * c * d[0];
+    F[1] += kQ * ir5 * c * d[1];
+    F[2] += kQ * ir5 * (c * d[2] - 6.0 * z);
+    *sE += fabs(kQ) * (3.0 * z * z + rho2) * ir5;
+    *sF += fabs(kQ) * ir5 * ((15.0 * z * z / rho2 + 3.0) * rho + 6.0 * fabs(z));
+}
+
+/*
  * Energy and force on the probe particle at point r from all atoms
  * (Eq. 5 + Eq. 6, F = -grad E):
  *   E   = sum_i e_iP [ (R_iP/rho)^12 - 2 (R_iP/rho)^6 ] + kq_i / rho
  *   F   = sum_i { 12 e_iP [ (R_iP/rho)^12 - (R_iP/rho)^6 ] / rho^2 + kq_i / rho^3 } (r - r_i)
+ * plus the quadrupole term of orc_quad when kQi != NULL.
  * out[4] = Fx, Fy, Fz, E.  If scale != NULL it receives the magnitude sums of
  * every term that enters the sums (the scale of their rounding error):
  * scale[0] = sum_i [12 e_iP ((R/rho)^12 + (R/rho)^6)/rho^2 + |kq_i|/rho^3] rho,
  * scale[1] = sum_i e_iP ((R/rho)^12 + 2 (R/rho)^6) + |kq_i|/rho,
- * scale[2] = min rho, scale[3] = min |rho^2 - rc^2|.
+ * (each plus the quadrupole's magnitude bound), scale[2] = min rho,
+ * scale[3] = min |rho^2 - rc^2|.
  * With periodic_xy only pairs with rho^2 < rc^2 contribute.
  */
 void orc_point(const double *r, int na, const double *pos, const double *RiP,
-               const double *eiP, const double *kqi, const double *g, const int *n,
-               double *out, double *scale)
+               const double *eiP, const double *kqi, const double *kQi, const double *g,
+               const int *n, double *out, double *scale)
 {
     double E = 0, Fx = 0, Fy = 0, Fz = 0, sF = 0, sE = 0, rmin = 1e300, tie = 1e300;
     int periodic = g[6] != 0.0;
@@ -122,6 +153,11 @@ void orc_point(const double *r, int na, const double *pos, const double *RiP,
         Fz += phi * d[2];
         sF += (12.0 * eiP[i] * (s12 + s6) / rho2 + fabs(kqi[i]) / (rho2 * rho)) * rho;
         sE += eiP[i] * (s12 + 2.0 * s6) + fabs(eC);
+        if (kQi && kQi[i] != 0.0) {
+            double Fq[3] = { 0.0, 0.0, 0.0 };
+            orc_quad(kQi[i], d, rho2, &E, Fq, &sE, &sF);
+            Fx += Fq[0]; Fy += Fq[1]; Fz += Fq[2];
+        }
     }
     out[0] = Fx; out[1] = Fy; out[2] = Fz; out[3] = E;
     if (scale) { scale[0] = sF; scale[1] = sE; scale[2] = rmin; scale[3] = tie; }
@@ -139,7 +175,8 @@ void orc_build_ff(const double *g, const int *n, const double *p, int na,
     double *RiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *eiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *kqi = malloc(sizeof(double) * (na > 0 ? na : 1));
-    orc_mix(na, R, eps, q, p, RiP, eiP, kqi);
+    double *kQi = malloc(sizeof(double) * (na > 0 ? na : 1));
+    orc_mix(na, R, eps, q, p, RiP, eiP, kqi, kQi);
     int nx = n[0], ny = n[1];
     #pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (int iz = iz0; iz < iz1; ++iz)
@@ -147,10 +184,10 @@ void orc_build_ff(const double *g, const int *n, const double *p, int na,
             for (int ix = 0; ix < nx; ++ix) {
                 double r[3] = { g[0] + ix * g[3], g[1] + iy * g[4], g[2] + iz * g[5] };
                 size_t o = (((size_t)(iz - iz0) * ny + iy) * nx + ix) * 4;
-                orc_point(r, na, pos, RiP, eiP, kqi, g, n, ff + o,
+                orc_point(r, na, pos, RiP, eiP, kqi, kQi, g, n, ff + o,
                           scale ? scale + o : NULL);
             }
-    free(RiP); free(eiP); free(kqi);
+    free(RiP); free(eiP); free(kqi); free(kQi);
 }
 
 /* Same as orc_point for a list of voxel indices idx[m][3] (sampled checks). */
@@ -161,15 +198,16 @@ void orc_ff_voxels(const double *g, const int *n, const double *p, int na,
     double *RiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *eiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *kqi = malloc(sizeof(double) * (na > 0 ? na : 1));
-    orc_mix(na, R, eps, q, p, RiP, eiP, kqi);
+    double *kQi = malloc(sizeof(double) * (na > 0 ? na : 1));
+    orc_mix(na, R, eps, q, p, RiP, eiP, kqi, kQi);
     #pragma omp parallel for schedule(static)
     for (int k = 0; k < m; ++k) {
         double r[3] = { g[0] + idx[3 * k] * g[3], g[1] + idx[3 * k + 1] * g[4],
                         g[2] + idx[3 * k + 2] * g[5] };
-        orc_point(r, na, pos, RiP, eiP, kqi, g, n, out + 4 * (size_t)k,
+        orc_point(r, na, pos, RiP, eiP, kqi, kQi, g, n, out + 4 * (size_t)k,
                   scale ? scale + 4 * (size_t)k : NULL);
     }
-    free(RiP); free(eiP); free(kqi);
+    free(RiP); free(eiP); free(kqi); free(kQi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -761,7 +799,10 @@ void orc_df(const double *fz, int nz, int ncol, double dz, double A, double f0,
  * dL/dtheta = sum_k mu . dF^S_h/dtheta, and dF^S_h/dtheta is the trilinear
  * combination of d f_i(v)/dtheta over the eight cell corners v.
  *   f_i(v) = phi(rho) d, d = v - a_i,
- *   phi = 12 e (R^12 rho^-14 - R^6 rho^-8) + kq rho^-3  (e = e_iP, R = R_iP).
+ *   phi = 12 e (R^12 rho^-14 - R^6 rho^-8) + kq rho^-3  (e = e_iP, R = R_iP),
+ * plus, for a quadrupolar probe, f_i = -kQ_i grad u with u = (3 dz^2 - rho^2)/rho^5
+ * (orc_quad); grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7, b = 6 dz rho^-5,
+ * so d f_i / d a_i = kQ_i hess u and d f_i / d q_i = -k_e q_zz grad u.
  * rstar [ncol][nz][3] in the order of cols; grad_df [nz-2m][ncol].
  */
 void orc_scan_backward(const double *g, const int *n, const double *ff, const double *p,
@@ -781,7 +822,8 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
     double *RiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *eiP = malloc(sizeof(double) * (na > 0 ? na : 1));
     double *kqi = malloc(sizeof(double) * (na > 0 ? na : 1));
-    orc_mix(na, R, eps, q, p, RiP, eiP, kqi);
+    double *kQi = malloc(sizeof(double) * (na > 0 ? na : 1));
+    orc_mix(na, R, eps, q, p, RiP, eiP, kqi, kQi);
     for (int i = 0; i < na; ++i) {
         g_pos[3 * i] = g_pos[3 * i + 1] = g_pos[3 * i + 2] = 0.0;
         g_q[i] = g_R[i] = g_eps[i] = 0.0;
@@ -852,6 +894,22 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
                                    d e_iP / d e_i = e_PP / (2 e_iP) */
                                 if (e > 0.0)
                                     lp[6 * i + 5] += (p[1] / (2.0 * e)) * 12.0 * (s12 - s6) * ir2 * md;
+                                if (p[9] != 0.0) {
+                                    double z = d[2];
+                                    double ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
+                                    double ua = 3.0 * ir5 - 15.0 * z * z * ir7;
+                                    double ub = 6.0 * z * ir5;
+                                    /* grad a . mw and grad b . mw */
+                                    double ga = (-15.0 * ir7 + 105.0 * z * z * ir9) * md
+                                                - 30.0 * z * ir7 * mw[2];
+                                    double gb = 6.0 * ir5 * mw[2] - 30.0 * z * ir7 * md;
+                                    double Hm[3] = { ua * mw[0] + d[0] * ga,
+                                                     ua * mw[1] + d[1] * ga,
+                                                     ua * mw[2] + d[2] * ga + gb };
+                                    for (int t = 0; t < 3; ++t)
+                                        lp[6 * i + t] += kQi[i] * Hm[t];
+                                    lp[6 * i + 3] -= ORC_KE * p[9] * (ua * md + ub * mw[2]);
+                                }
                             }
                         }
             }
@@ -867,7 +925,7 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
         }
         free(lp);
     }
-    free(w); free(RiP); free(eiP); free(kqi);
+    free(w); free(RiP); free(eiP); free(kqi); free(kQi);
 }
 
 /* Number of OpenMP threads the oracle runs with. */

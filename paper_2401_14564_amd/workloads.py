@@ -86,6 +86,7 @@ class Probe:
     k_lat: Tuple[float, float] = (0.25 * N_PER_M, 0.25 * N_PER_M)   # eV/A^2
     k_rad: float = 20.0 * N_PER_M        # eV/A^2
     d0: Tuple[float, float, float] = (0.0, 0.0, -4.0)               # A
+    q_zz: float = 0.0                    # e A^2, quadrupolar (d_z2) probe charge
 
 
 @dataclass

@@ -34,18 +34,24 @@ def _loss(atoms, grid, scan, fire, dfp, gdf, probe=W.Probe()):
     return float(np.sum(gdf * df)), ff, res
 
 
-def test_adjoint_matches_central_differences():
+# the monopole probe of the workloads, and the d_z2 quadrupole probe of the
+# model comparison (Sec. 2.2.5: -0.05 e A^2, no monopole)
+PROBES = [W.Probe(), W.Probe(q_pp=0.0, q_zz=-0.05)]
+
+
+@pytest.mark.parametrize("probe", PROBES, ids=["monopole", "quadrupole"])
+def test_adjoint_matches_central_differences(probe):
     atoms, grid, scan, fire, dfp, gdf = _problem()
-    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf)
+    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf, probe)
     assert np.all(res["gnorm"] < 1e-12)
-    g = orc.scan_backward(grid, ff, W.Probe(), scan, res["cols"], res["r"], gdf, dfp, atoms)
+    g = orc.scan_backward(grid, ff, probe, scan, res["cols"], res["r"], gdf, dfp, atoms)
 
     def fd(mod, h):
         ap, am = atoms.copy(), atoms.copy()
         mod(ap, +h)
         mod(am, -h)
-        Lp = _loss(ap, grid, scan, fire, dfp, gdf)[0]
-        Lm = _loss(am, grid, scan, fire, dfp, gdf)[0]
+        Lp = _loss(ap, grid, scan, fire, dfp, gdf, probe)[0]
+        Lm = _loss(am, grid, scan, fire, dfp, gdf, probe)[0]
         return (Lp - Lm) / (2 * h)
 
     scale = max(np.abs(g["pos"]).max(), 1e-12)
@@ -66,12 +72,13 @@ def test_adjoint_matches_central_differences():
         assert g["eps"][i] == pytest.approx(fd(mode, he), rel=2e-4, abs=1e-3)
 
 
-def test_adjoint_translation_identity():
+@pytest.mark.parametrize("probe", PROBES, ids=["monopole", "quadrupole"])
+def test_adjoint_translation_identity(probe):
     """sum_i dL/dr_i = -dL/d(delta) with delta a common shift of the grid origin
     and the tip lattice (the sample-probe system is translation invariant)."""
     atoms, grid, scan, fire, dfp, gdf = _problem()
-    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf)
-    g = orc.scan_backward(grid, ff, W.Probe(), scan, res["cols"], res["r"], gdf, dfp, atoms)
+    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf, probe)
+    g = orc.scan_backward(grid, ff, probe, scan, res["cols"], res["r"], gdf, dfp, atoms)
     tot = g["pos"].sum(axis=0)
     # small step: the interpolated field is only continuous across cell faces,
     # and a common shift of all atoms by 1e-4 A already crosses one here
@@ -84,6 +91,6 @@ def test_adjoint_translation_identity():
             g2 = W.Grid(tuple(np.array(grid.origin) + e), grid.step, grid.n)
             s2 = W.Scan(scan.x0 + e[0], scan.y0 + e[1], scan.dx, scan.dy, scan.nx, scan.ny,
                         scan.z_top + e[2], scan.dz, scan.nz)
-            vals.append(_loss(atoms, g2, s2, fire, dfp, gdf)[0])
+            vals.append(_loss(atoms, g2, s2, fire, dfp, gdf, probe)[0])
         dshift = (vals[0] - vals[1]) / (2 * h)
         assert tot[k] == pytest.approx(-dshift, rel=1e-5, abs=1e-7 * np.abs(g["pos"]).max())
