@@ -66,6 +66,8 @@ def lib():
             L.orc_scan_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, vp, vp, vp, d, d, d,
                                             i, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_num_threads.restype = i
+            L.orc_tip_density.argtypes = [vp, vp, d, d, d, vp]
+            L.orc_correlate.argtypes = [vp, vp, vp, vp, i, vp, vp]
             _lib = L
     return _lib
 
@@ -337,3 +339,63 @@ def scan_backward(grid, ff, probe, scan, cols, rstar, grad_df, dfp, atoms):
                             float(dfp.A), float(dfp.f0), float(dfp.k_cant), na, _vp(pos),
                             _vp(q), _vp(R), _vp(eps), _vp(gp), _vp(gq), _vp(gR), _vp(ge))
     return dict(pos=gp, q=gq, R=gR, eps=ge)
+
+
+# ------------------------------------------------- grid electrostatics --
+def tip_density(grid, q_pp, q_zz, sigma):
+    """Probe charge density [nz][ny][nx] on the grid's lattice of offsets from the
+    probe centre (Gaussian-smeared point charge + d_z2 quadrupole)."""
+    g, n = _grid(grid)
+    rho = np.zeros((n[2], n[1], n[0]))
+    lib().orc_tip_density(_vp(g), _vp(n), float(q_pp), float(q_zz), float(sigma), _vp(rho))
+    return rho
+
+
+def correlate(grid, rho, V, idx=None):
+    """E[j] = dV sum_i rho[i] V[i + j] (periodic), at voxels idx[m][3] or everywhere."""
+    g, n = _grid(grid)
+    rho = _f64(rho)
+    V = _f64(V)
+    assert rho.shape == V.shape == (n[2], n[1], n[0])
+    if idx is None:
+        E = np.zeros((n[2], n[1], n[0]))
+        lib().orc_correlate(_vp(g), _vp(n), _vp(rho), _vp(V), 0, None, _vp(E))
+        return E
+    idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
+    E = np.zeros(len(idx))
+    lib().orc_correlate(_vp(g), _vp(n), _vp(rho), _vp(V), len(idx), _vp(idx), _vp(E))
+    return E
+
+
+def wavenumbers(n, h):
+    """Signed angular wavenumbers of a periodic axis of n points and step h (the
+    Nyquist term of an even n is set to zero, so that derivatives of real data
+    stay real)."""
+    m = np.arange(n)
+    m = np.where(2 * m < n, m, m - n).astype(np.float64)
+    if n % 2 == 0:
+        m[n // 2] = 0.0
+    return 2.0 * np.pi * m / (n * h)
+
+
+def _spectral_gradient(a, grid):
+    """d a / d x_c (c = x, y, z) of a periodic grid array a [nz][ny][nx], as the
+    derivative of its trigonometric interpolant (numpy FFT)."""
+    kx = wavenumbers(grid.n[0], grid.step[0])[None, None, :]
+    ky = wavenumbers(grid.n[1], grid.step[1])[None, :, None]
+    kz = wavenumbers(grid.n[2], grid.step[2])[:, None, None]
+    ak = np.fft.fftn(a)
+    return [np.real(np.fft.ifftn(1j * k * ak)) for k in (kx, ky, kz)]
+
+
+def hartree_ff(grid, rho, V, idx=None):
+    """Electrostatic energy of the probe and its force, (Fx, Fy, Fz, E), on the
+    whole grid ([nz][ny][nx][4]) or at voxels idx[m][3] ([m][4]).
+    E is the cross-correlation of rho with V (direct sum).  F = -grad E is
+    taken as the derivative of E's trigonometric interpolant; moving the
+    derivative onto the density (summation by parts on the periodic grid),
+    F_c = correlate(d rho / d x_c, V), with d rho / d x_c the spectral
+    derivative of rho."""
+    drho = _spectral_gradient(_f64(rho), grid)
+    parts = [correlate(grid, d, V, idx) for d in drho] + [correlate(grid, rho, V, idx)]
+    return np.stack(parts, axis=-1)

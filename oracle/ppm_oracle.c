@@ -21,6 +21,9 @@
  *   - FIRE relaxation .................. Sec. 5.1.1, step 2 (Bitzek et al. 2006)
  *   - tip force readout ................ Sec. 2.1 (text after Eq. 2)
  *   - frequency shift .................. Sec. 2.1, Eq. 3 (Giessibl)
+ *   - grid electrostatics .............. Sec. 2.2.3 (cross-correlation of the
+ *                                        probe density with the sample
+ *                                        potential), Sec. 5.1.2
  *   - implicit adjoint ................. not in the paper; derived here from
  *                                        the equilibrium condition of Eq. 1
  *
@@ -926,6 +929,81 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
         free(lp);
     }
     free(w); free(RiP); free(eiP); free(kqi); free(kQi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Electrostatics from a grid potential (Sec. 2.2.3, Eq. of the cross-       */
+/* correlation; Sec. 5.1.2)                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Signed offset of index i on a periodic axis of n points: i for i < n/2,
+ * i - n above (for even n the index n/2 is taken as -n/2). */
+static int orc_wrap_offset(int i, int n)
+{
+    return (2 * i < n) ? i : i - n;
+}
+
+/*
+ * Charge density of the probe particle sampled on the grid's periodic lattice
+ * of offsets from the probe centre (index 0 = the centre, negative offsets
+ * wrapped to the far end):
+ *   rho(r) = q_pp G(r) + q_zz d^2 G / dz^2,
+ *   G(r)   = (2 pi sigma^2)^(-3/2) exp(-r^2 / (2 sigma^2)),
+ * i.e. the point charge and the d_z2 quadrupole of the probe smeared by a
+ * Gaussian of width sigma (as sigma -> 0 the quadrupole part is the point
+ * density q_zz d^2 delta/dz^2).  rho is [nz][ny][nx], e/A^3.
+ */
+void orc_tip_density(const double *g, const int *n, double q_pp, double q_zz, double sigma,
+                     double *rho)
+{
+    double s2 = sigma * sigma;
+    double norm = 1.0 / pow(2.0 * ORC_PI * s2, 1.5);
+    for (int iz = 0; iz < n[2]; ++iz)
+        for (int iy = 0; iy < n[1]; ++iy)
+            for (int ix = 0; ix < n[0]; ++ix) {
+                double x = orc_wrap_offset(ix, n[0]) * g[3];
+                double y = orc_wrap_offset(iy, n[1]) * g[4];
+                double z = orc_wrap_offset(iz, n[2]) * g[5];
+                double G = norm * exp(-(x * x + y * y + z * z) / (2.0 * s2));
+                double d2G = G * (z * z / (s2 * s2) - 1.0 / s2);
+                rho[((size_t)iz * n[1] + iy) * n[0] + ix] = q_pp * G + q_zz * d2G;
+            }
+}
+
+/*
+ * Cross-correlation of the probe density with the sample potential (the
+ * electrostatic energy of the probe, Sec. 2.2.3), as the plain sum over the
+ * periodic grid that the integral becomes:
+ *   E[j] = dV sum_i rho[i] V[(i + j) mod n],   dV = hx hy hz,
+ * with rho from orc_tip_density (offsets from the probe centre) and V the
+ * sample potential on the grid (eV/e).  E is evaluated at the m voxels
+ * idx[m][3] = (ix, iy, iz), or at every voxel ([nz][ny][nx]) if idx is NULL.
+ */
+void orc_correlate(const double *g, const int *n, const double *rho, const double *V, int m,
+                   const int *idx, double *E)
+{
+    int nx = n[0], ny = n[1], nz = n[2];
+    size_t N = (size_t)nx * ny * nz;
+    double dV = g[3] * g[4] * g[5];
+    long long cnt = idx ? m : (long long)N;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long long t = 0; t < cnt; ++t) {
+        int jx, jy, jz;
+        if (idx) { jx = idx[3 * t]; jy = idx[3 * t + 1]; jz = idx[3 * t + 2]; }
+        else { jx = (int)(t % nx); jy = (int)((t / nx) % ny); jz = (int)(t / ((size_t)nx * ny)); }
+        double acc = 0.0;
+        for (int iz = 0; iz < nz; ++iz) {
+            int kz = (iz + jz) % nz;
+            for (int iy = 0; iy < ny; ++iy) {
+                int ky = (iy + jy) % ny;
+                const double *r = rho + ((size_t)iz * ny + iy) * nx;
+                const double *v = V + ((size_t)kz * ny + ky) * nx;
+                for (int ix = 0; ix < nx; ++ix)
+                    acc += r[ix] * v[(ix + jx) % nx];
+            }
+        }
+        E[t] = dV * acc;
+    }
 }
 
 /* Number of OpenMP threads the oracle runs with. */

@@ -276,6 +276,50 @@ def config4() -> Tuple[Workload, Atoms]:
     return w, target
 
 
+# Grid electrostatics (the Hartree-potential route).  The sample potential of
+# a DFT calculation is not available; its stand-in is the periodic potential of
+# the atoms' partial charges, each smeared by a Gaussian of width HARTREE_SIGMA.
+# The probe density is a Gaussian of width TIP_SIGMA carrying the probe's
+# point charge and d_z2 quadrupole.
+HARTREE_SIGMA = 0.5      # A
+TIP_SIGMA = 0.7          # A
+KE = 14.3996454784       # eV A / e^2
+
+
+def hartree_potential(atoms: Atoms, grid: Grid, sigma: float = HARTREE_SIGMA,
+                      trunc: float = 8.0) -> np.ndarray:
+    """Synthetic sample potential V [nz][ny][nx] (eV/e) on the grid's periodic
+    cell: the charges are spread as Gaussians (cut at trunc*sigma, wrapped) and
+    the Poisson equation is solved in Fourier space (zero mean)."""
+    n = np.asarray(grid.n)
+    h = np.asarray(grid.step, dtype=np.float64)
+    o = np.asarray(grid.origin, dtype=np.float64)
+    rho = np.zeros((n[2], n[1], n[0]))
+    rc = trunc * sigma
+    norm = (2 * np.pi * sigma ** 2) ** -1.5
+    for p, q in zip(np.asarray(atoms.pos, dtype=np.float64).reshape(-1, 3), atoms.q):
+        if q == 0.0:
+            continue
+        ax = []
+        for c in range(3):
+            u = (p[c] - o[c]) / h[c]
+            i = np.arange(int(np.floor(u - rc / h[c])), int(np.ceil(u + rc / h[c])) + 1)
+            ax.append((i % n[c], (i - u) * h[c]))
+        (ix, dx), (iy, dy), (iz, dz) = ax
+        r2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+        np.add.at(rho, (iz[:, None, None], iy[None, :, None], ix[None, None, :]),
+                  q * norm * np.exp(-r2 / (2 * sigma ** 2)))
+    k2 = 0.0
+    for c, ax_shape in ((0, (1, 1, -1)), (1, (1, -1, 1)), (2, (-1, 1, 1))):
+        m = np.arange(n[c])
+        m = np.where(2 * m < n[c], m, m - n[c])
+        k2 = k2 + ((2 * np.pi * m / (n[c] * h[c])) ** 2).reshape(ax_shape)
+    rk = np.fft.fftn(rho)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        vk = np.where(k2 > 0, 4 * np.pi * KE * rk / np.where(k2 > 0, k2, 1.0), 0.0)
+    return np.real(np.fft.ifftn(vk))
+
+
 def parity_fire(fire: Fire, f_conv: float = 1e-7, max_iter: int = 20000) -> Fire:
     """FIRE settings for parity runs: a tight convergence threshold so that the
     remaining residual maps to position errors far below the tolerance."""
