@@ -25,6 +25,11 @@
  *      points (Sec. 3.3)                                -> ppm_lateral_stiffness
  *   7. the scan on a tricubic interpolant of an energy-only grid (Sec. 5.1.1)
  *                                 -> ppm_build_energy, ppm_relaxed_scan_tricubic
+ *   8. a quadrupolar (d_z2) probe charge in the point-charge force field
+ *      (Sec. 2.2.3, Sec. 2.2.5)                          -> ppm_probe.q_zz
+ *   9. electrostatics from a sample potential on the grid, by cross-correlation
+ *      with the probe's charge density (Sec. 2.2.3, Sec. 5.1.2)
+ *                                          -> ppm_tip_density, ppm_hartree_ff
  *
  * Conventions shared by every entry point
  *   - Units: lengths in Angstrom, energies in eV, charges in e, forces in eV/A,
@@ -78,14 +83,19 @@ typedef struct {
 } ppm_grid;
 
 /* Probe particle and tip (Sec. 2.1, Eq. 2; Sec. 2.2.1 mixing rules).
- * R_pp, eps_pp: LJ radius and depth of the probe; q_pp: its point charge.
+ * R_pp, eps_pp: LJ radius and depth of the probe; q_pp: its point charge (e).
  * k_lat: lateral stiffnesses (k_x, k_y); k_rad: radial stiffness (eV/A^2).
- * d0: rest displacement probe - anchor; R0 = |d0|. */
+ * d0: rest displacement probe - anchor; R0 = |d0|.
+ * q_zz: quadrupole moment of the probe's d_z2 charge (Sec. 2.2.3, e A^2; the
+ * CO tip of Sec. 2.2.5 uses -0.05), taken as the point density
+ * q_zz d^2 delta/dz^2, the limit of charges (+q, -2q, +q) at z+h, z, z-h with
+ * q h^2 = q_zz; 0 for a point-charge probe. */
 typedef struct {
     double R_pp, eps_pp, q_pp;
     double k_lat[2];
     double k_rad;
     double d0[3];
+    double q_zz;
 } ppm_probe;
 
 /* FIRE relaxation parameters (Bitzek et al. 2006, as used in Sec. 5.1.1).
@@ -138,6 +148,9 @@ int32_t ppm_df_half_width(double A, double dz);
  * kq_i = k_e q_i q_pp (k_e = 14.3996454784 eV*A/e^2), rho = |v - r_i|:
  *   E(v) = sum_i e_iP [(R_iP/rho)^12 - 2 (R_iP/rho)^6] + kq_i/rho
  *   F(v) = sum_i {12 e_iP [(R_iP/rho)^12 - (R_iP/rho)^6]/rho^2 + kq_i/rho^3} (v - r_i)
+ * and, for a probe with q_zz != 0, per atom kQ_i (3 dz^2 - rho^2)/rho^5 in E
+ * (kQ_i = k_e q_i q_zz, dz = z_v - z_i, i.e. q_zz d^2/dz^2 of the atom's
+ * Coulomb potential) and its negative gradient in F.
  * in:  pos[n_atoms][3], q[n_atoms], R[n_atoms], eps[n_atoms] (FP64, device);
  *      n_atoms >= 0 (0 gives the zero field).
  * out: ff[nz][ny][nx][4] = (Fx, Fy, Fz, E), FP32, device.
@@ -263,6 +276,51 @@ ppm_status ppm_lateral_stiffness(const ppm_grid *grid, const float *ff, const pp
                                  void *stream);
 
 /* ------------------------------------------------------------------------
+ * Electrostatics from a sample potential given on the grid (Sec. 2.2.3: the
+ * probe's energy is the cross-correlation of its charge density with the
+ * sample's Hartree potential; Sec. 5.1.2: evaluated by the convolution
+ * theorem).  The grid is taken periodic in x, y and z (the potential of a
+ * periodic DFT cell); periodic_xy and cutoff are ignored.  Each n[i] must be
+ * 2^a 3^b 5^c and at most 1024, else PPM_EUNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * ppm_tip_density -- charge density of the probe particle on the grid's
+ * lattice of offsets from the probe centre (index 0 is the centre; negative
+ * offsets wrap to the far end):
+ *   rho(r) = q_pp G(r) + q_zz d^2 G / dz^2,  G = (2 pi sigma^2)^(-3/2) exp(-r^2 / (2 sigma^2)),
+ * a Gaussian-smeared point charge (e) and d_z2 quadrupole (e A^2, the moment
+ * of ppm_probe.q_zz).  The cell should span several sigma on each side.
+ * out: rho[nz][ny][nx] (FP32, e/A^3, device).
+ * Errors: PPM_EINVAL for a bad grid, rho NULL, sigma <= 0 or non-finite charges.
+ */
+ppm_status ppm_tip_density(const ppm_grid *grid, double q_pp, double q_zz, double sigma,
+                           float *rho, void *stream);
+
+/* Workspace (bytes) ppm_hartree_ff needs for this grid: three complex FP64
+ * grids; 0 if the grid is invalid or unsupported. */
+size_t ppm_hartree_workspace_bytes(const ppm_grid *grid);
+
+/*
+ * ppm_hartree_ff -- energy and force of the probe in the sample potential V:
+ *   E[j] = dV sum_i rho[i] V[(i + j) mod n],   dV = hx hy hz,
+ *   F = -grad E (gradient of the trigonometric interpolant of E),
+ * computed as E^ = dV conj(rho^) V^ and F^ = -i kappa E^ with FP64 FFTs.
+ * in:  V[nz][ny][nx] (eV/e), rho[nz][ny][nx] from ppm_tip_density or any
+ *      density on the same lattice of offsets (FP32, device).
+ * out: ff[nz][ny][nx][4] = (Fx, Fy, Fz, E) (FP32), overwritten if accumulate
+ *      is 0 or added to the values there if accumulate is 1 (e.g. onto the
+ *      Lennard-Jones grid of ppm_build_ff with q_pp = q_zz = 0).
+ * workspace: device buffer of at least ppm_hartree_workspace_bytes() bytes.
+ * Errors: PPM_EINVAL for a bad grid, NULL pointers, accumulate not 0 or 1, or
+ * a workspace that is too small; PPM_EUNSUPPORTED for axis lengths the FFT
+ * does not handle.
+ */
+ppm_status ppm_hartree_ff(const ppm_grid *grid, const float *V, const float *rho,
+                          int32_t accumulate, float *ff, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched pipeline: many molecules of different sizes, each scanned with one
  * or more probes, in one launch per stage.  Host tables describe the work; the
  * same tables copied to device memory are read by the kernels.  Force fields,
@@ -282,7 +340,7 @@ typedef struct {
 } ppm_batch_mol;
 
 /* One scan job: molecule `mol` scanned with `probe` over `scan`.  The probe's
- * R_pp, eps_pp and q_pp must equal those the batch's force fields were built
+ * R_pp, eps_pp, q_pp and q_zz must equal those the batch's force fields were built
  * with; its springs and d0 may differ per job.  Outputs are stacks
  * [scan.nz][scan.ny][scan.nx] (fz) and [scan.nz-2m][scan.ny][scan.nx] (df). */
 typedef struct {

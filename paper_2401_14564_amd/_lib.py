@@ -24,7 +24,8 @@ EXPORTED = (
     "ppm_relaxed_scan", "ppm_df", "ppm_backward_workspace_bytes",
     "ppm_relaxed_scan_backward", "ppm_batch_plan", "ppm_batch_build_ff",
     "ppm_batch_relaxed_scan", "ppm_lateral_stiffness", "ppm_build_energy",
-    "ppm_relaxed_scan_tricubic",
+    "ppm_relaxed_scan_tricubic", "ppm_tip_density", "ppm_hartree_workspace_bytes",
+    "ppm_hartree_ff",
 )
 
 
@@ -45,7 +46,8 @@ class Grid(ct.Structure):
 
 class Probe(ct.Structure):
     _fields_ = [("R_pp", ct.c_double), ("eps_pp", ct.c_double), ("q_pp", ct.c_double),
-                ("k_lat", ct.c_double * 2), ("k_rad", ct.c_double), ("d0", ct.c_double * 3)]
+                ("k_lat", ct.c_double * 2), ("k_rad", ct.c_double), ("d0", ct.c_double * 3),
+                ("q_zz", ct.c_double)]
 
 
 class Fire(ct.Structure):
@@ -125,6 +127,12 @@ def lib():
             L.ppm_relaxed_scan_tricubic.argtypes = [P(Grid), vp, P(Probe), P(Fire), P(Scan), vp,
                                                     vp, P(DfParams), vp, vp]
             L.ppm_relaxed_scan_tricubic.restype = st
+            L.ppm_tip_density.argtypes = [P(Grid), d, d, d, vp, vp]
+            L.ppm_tip_density.restype = st
+            L.ppm_hartree_workspace_bytes.argtypes = [P(Grid)]
+            L.ppm_hartree_workspace_bytes.restype = ct.c_size_t
+            L.ppm_hartree_ff.argtypes = [P(Grid), vp, vp, i32, vp, vp, ct.c_size_t, vp]
+            L.ppm_hartree_ff.restype = st
             _LIB = L
     return _LIB
 
@@ -146,7 +154,7 @@ def grid_struct(g) -> Grid:
 
 def probe_struct(p) -> Probe:
     return Probe(p.R_pp, p.eps_pp, p.q_pp, (ct.c_double * 2)(*p.k_lat), p.k_rad,
-                 (ct.c_double * 3)(*p.d0))
+                 (ct.c_double * 3)(*p.d0), float(getattr(p, "q_zz", 0.0)))
 
 
 def fire_struct(f) -> Fire:

@@ -2,8 +2,11 @@
 //
 // Every voxel sums the Lennard-Jones (Eq. 5) and point-charge Coulomb (Eq. 6)
 // energy of the probe particle and the force F = -grad E over the sample's
-// atoms (Sec. 2.2, Sec. 5.1.1 step 1).  The work is O(n_atoms * n_voxels) and
-// bound by the FP32 vector ALU; it is not a dense contraction, so no MFMA.
+// atoms (Sec. 2.2, Sec. 5.1.1 step 1).  A probe with a quadrupolar d_z2 charge
+// q_zz (Sec. 2.2.3) adds, per atom, q_zz d^2 V_i/dz^2 with V_i the atom's
+// Coulomb potential: kQ_i (3 dz^2 - rho^2) / rho^5, kQ_i = k_e q_i q_zz.  The
+// work is O(n_atoms * n_voxels) and bound by the FP32 vector ALU; it is not a
+// dense contraction, so no MFMA.
 //
 // Design:
 //  * A block of BX x BY threads owns a brick of BX x BY x NZB voxels; each
@@ -41,14 +44,15 @@ __device__ __host__ __forceinline__ double ff_brick_half_diagonal_dev(double hx,
 template <int NT>
 struct BrickLds {
     float4 geo[NT];   // brick-local (x, y, z) and R_iP^2
-    float4 par[NT];   // e_iP, 12 e_iP, kq_i
+    float4 par[NT];   // e_iP, 12 e_iP, kq_i, kQ_i
     int wcnt[NT / 64];
 };
 
 // One brick of BX x BY x NZB voxels with corner voxel (ix0, iy0, iz0).
 // EONLY: only the energy is accumulated and stored (one float per voxel, the
-// input of the tricubic scan); `ff` then points at floats.
-template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY = false>
+// input of the tricubic scan); `ff` then points at floats.  QUAD: the probe
+// carries a quadrupole moment (kQ_pp != 0).
+template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY, bool QUAD>
 __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int iz0,
                                          const double *__restrict__ pos,
                                          const double *__restrict__ q,
@@ -97,7 +101,8 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             const double RiP = R[i] + a.R_pp;
             const double eiP = sqrt(eps[i] * a.eps_pp);
             geo = make_float4((float)dx, (float)dy, (float)dz, (float)(RiP * RiP));
-            par = make_float4((float)eiP, (float)(12.0 * eiP), (float)(a.kq_pp * q[i]), 0.f);
+            par = make_float4((float)eiP, (float)(12.0 * eiP), (float)(a.kq_pp * q[i]),
+                              (float)(a.kQ_pp * q[i]));
         }
         int cnt, slot;
         if (PERIODIC) {
@@ -142,8 +147,20 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                 const float s12 = s6 * s6;
                 const float ec = p.z * ir;
                 E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + ec;
+                float f = 0.0f;
+                if (!EONLY) f = fmaf(p.y, s12 - s6, ec) * ir2;
+                if (QUAD) {
+                    // u = (3 dz^2 - rho^2)/rho^5,
+                    // -grad u = rho^-5 [(15 dz^2/rho^2 - 3) d - 6 dz e_z]
+                    const float z2 = dz * dz;
+                    const float q5 = p.w * (ir2 * ir2 * ir);          // kQ_i / rho^5
+                    E[k] = fmaf(q5, fmaf(3.0f, z2, -r2), E[k]);
+                    if (!EONLY) {
+                        f = fmaf(q5, fmaf(15.0f * z2, ir2, -3.0f), f);
+                        Fz[k] = fmaf(-6.0f * q5, dz, Fz[k]);
+                    }
+                }
                 if (!EONLY) {
-                    const float f = fmaf(p.y, s12 - s6, ec) * ir2;
                     Fx[k] = fmaf(f, dx, Fx[k]);
                     Fy[k] = fmaf(f, dy, Fy[k]);
                     Fz[k] = fmaf(f, dz, Fz[k]);
@@ -167,21 +184,21 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     }
 }
 
-template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY = false>
+template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY, bool QUAD>
 __global__ __launch_bounds__(BX * BY) void ff_build_kernel(
     const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
     const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
 {
     __shared__ BrickLds<BX * BY> lds;
-    ff_brick<BX, BY, NZB, PERIODIC, EONLY>(a, blockIdx.x * BX, blockIdx.y * BY,
-                                           blockIdx.z * NZB, pos, q, R, eps, ff, lds);
+    ff_brick<BX, BY, NZB, PERIODIC, EONLY, QUAD>(a, blockIdx.x * BX, blockIdx.y * BY,
+                                                 blockIdx.z * NZB, pos, q, R, eps, ff, lds);
 }
 
 // Batched build: one block per brick of any molecule of the batch.  The
 // molecule of a brick is found by a binary search over the table's
 // brick_begin (wave-uniform, scalar loads); its grid, atom range and arena
 // offset come from the table.  The probe (mixing parameters) is shared.
-template <int BX, int BY, int NZB>
+template <int BX, int BY, int NZB, bool QUAD>
 __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
     const FFArgs probe_args, const ppm_batch_mol *__restrict__ mols, int n_mol,
     const double *__restrict__ pos, const double *__restrict__ q, const double *__restrict__ R,
@@ -220,11 +237,13 @@ __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
         a.Ly = a.ny * a.hy;
         a.rc2 = (float)(M.grid.cutoff * M.grid.cutoff);
         a.cull2 = (M.grid.cutoff + hd) * (M.grid.cutoff + hd);
-        ff_brick<BX, BY, NZB, true>(a, (rest % nbx) * BX, (rest / nbx) * BY, bz * NZB,
-                                    pos + 3 * (size_t)off, q + off, R + off, eps + off, ff, lds);
+        ff_brick<BX, BY, NZB, true, false, QUAD>(a, (rest % nbx) * BX, (rest / nbx) * BY,
+                                                 bz * NZB, pos + 3 * (size_t)off, q + off,
+                                                 R + off, eps + off, ff, lds);
     } else {
-        ff_brick<BX, BY, NZB, false>(a, (rest % nbx) * BX, (rest / nbx) * BY, bz * NZB,
-                                     pos + 3 * (size_t)off, q + off, R + off, eps + off, ff, lds);
+        ff_brick<BX, BY, NZB, false, false, QUAD>(a, (rest % nbx) * BX, (rest / nbx) * BY,
+                                                  bz * NZB, pos + 3 * (size_t)off, q + off,
+                                                  R + off, eps + off, ff, lds);
     }
 }
 
@@ -254,20 +273,28 @@ long long ff_brick_count(int nx, int ny, int nz)
     return (long long)((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + kNZB - 1) / kNZB);
 }
 
-hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
-                           const double *R, const double *eps, float4 *ff, hipStream_t stream)
+template <bool EONLY, bool QUAD>
+void launch_build(const FFArgs &a, const double *pos, const double *q, const double *R,
+                  const double *eps, float4 *out, hipStream_t stream)
 {
     if (a.Lx > 0.0) {
         dim3 block(kPBX, kPBY, 1);
         dim3 grid((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true>), grid, block, 0, stream,
-                           a, pos, q, R, eps, ff);
+        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true, EONLY, QUAD>), grid, block, 0,
+                           stream, a, pos, q, R, eps, out);
     } else {
         dim3 block(kBX, kBY, 1);
         dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false>), grid, block, 0, stream,
-                           a, pos, q, R, eps, ff);
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false, EONLY, QUAD>), grid, block, 0,
+                           stream, a, pos, q, R, eps, out);
     }
+}
+
+hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
+                           const double *R, const double *eps, float4 *ff, hipStream_t stream)
+{
+    if (a.kQ_pp != 0.0) launch_build<false, true>(a, pos, q, R, eps, ff, stream);
+    else launch_build<false, false>(a, pos, q, R, eps, ff, stream);
     return hipGetLastError();
 }
 
@@ -275,17 +302,8 @@ hipError_t launch_build_energy(const FFArgs &a, const double *pos, const double 
                                const double *R, const double *eps, float *E, hipStream_t stream)
 {
     float4 *out = reinterpret_cast<float4 *>(E);   // EONLY kernels store floats
-    if (a.Lx > 0.0) {
-        dim3 block(kPBX, kPBY, 1);
-        dim3 grid((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true, true>), grid, block, 0,
-                           stream, a, pos, q, R, eps, out);
-    } else {
-        dim3 block(kBX, kBY, 1);
-        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false, true>), grid, block, 0, stream,
-                           a, pos, q, R, eps, out);
-    }
+    if (a.kQ_pp != 0.0) launch_build<true, true>(a, pos, q, R, eps, out, stream);
+    else launch_build<true, false>(a, pos, q, R, eps, out, stream);
     return hipGetLastError();
 }
 
@@ -298,9 +316,14 @@ hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *
     // 2-D grid: x up to 65536 blocks per row, as many rows as needed
     const long long gx = n_bricks < 65536 ? n_bricks : 65536;
     const long long gy = (n_bricks + gx - 1) / gx;
-    hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB>), dim3((unsigned)gx, (unsigned)gy, 1),
-                       dim3(kBX, kBY, 1), 0, stream, probe_args, mols_dev, n_mol, pos, q, R, eps,
-                       arena);
+    if (probe_args.kQ_pp != 0.0)
+        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB, true>),
+                           dim3((unsigned)gx, (unsigned)gy, 1), dim3(kBX, kBY, 1), 0, stream,
+                           probe_args, mols_dev, n_mol, pos, q, R, eps, arena);
+    else
+        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB, false>),
+                           dim3((unsigned)gx, (unsigned)gy, 1), dim3(kBX, kBY, 1), 0, stream,
+                           probe_args, mols_dev, n_mol, pos, q, R, eps, arena);
     return hipGetLastError();
 }
 

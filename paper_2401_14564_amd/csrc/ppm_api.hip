@@ -38,7 +38,8 @@ ppm_status check_grid(const ppm_grid *g)
 ppm_status check_probe(const ppm_probe *p)
 {
     if (!p) return PPM_EINVAL;
-    if (!isfinite(p->R_pp) || !(p->eps_pp >= 0.0) || !isfinite(p->eps_pp) || !isfinite(p->q_pp))
+    if (!isfinite(p->R_pp) || !(p->eps_pp >= 0.0) || !isfinite(p->eps_pp) || !isfinite(p->q_pp) ||
+        !isfinite(p->q_zz))
         return PPM_EINVAL;
     if (!(p->k_lat[0] >= 0.0) || !(p->k_lat[1] >= 0.0) || !(p->k_rad >= 0.0)) return PPM_EINVAL;
     if (!isfinite(p->k_lat[0]) || !isfinite(p->k_lat[1]) || !isfinite(p->k_rad)) return PPM_EINVAL;
@@ -199,6 +200,7 @@ static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t
     a->R_pp = probe->R_pp;
     a->eps_pp = probe->eps_pp;
     a->kq_pp = kCoulomb * probe->q_pp;
+    a->kQ_pp = kCoulomb * probe->q_zz;
     if (grid->periodic_xy) {
         const double Lx = grid->n[0] * grid->step[0], Ly = grid->n[1] * grid->step[1];
         const double hd = ff_brick_half_diagonal(grid->step[0], grid->step[1], grid->step[2]);
@@ -353,6 +355,7 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
     A.eps_pp = probe->eps_pp;
     A.kq_pp = kCoulomb * probe->q_pp;
     A.ke_qpp = kCoulomb * probe->q_pp;
+    A.kQ_pp = kCoulomb * probe->q_zz;
     backward_chunks(scan, &A.n_eq_blocks, &A.eq_per_block);
     char *ws = static_cast<char *>(workspace);
     float4 *rec = reinterpret_cast<float4 *>(ws);
@@ -365,7 +368,7 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
 
 static bool same_probe_lj(const ppm_probe &a, const ppm_probe &b)
 {
-    return a.R_pp == b.R_pp && a.eps_pp == b.eps_pp && a.q_pp == b.q_pp;
+    return a.R_pp == b.R_pp && a.eps_pp == b.eps_pp && a.q_pp == b.q_pp && a.q_zz == b.q_zz;
 }
 
 ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
@@ -455,6 +458,7 @@ ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
     a.R_pp = probe->R_pp;
     a.eps_pp = probe->eps_pp;
     a.kq_pp = kCoulomb * probe->q_pp;
+    a.kQ_pp = kCoulomb * probe->q_zz;
     return hip_status(launch_build_ff_batch(a, mols_dev, n_mol, bricks, pos, q, R, eps,
                                             reinterpret_cast<float4 *>(ff_arena),
                                             (hipStream_t)stream));
@@ -534,6 +538,57 @@ ppm_status ppm_lateral_stiffness(const ppm_grid *grid, const float *ff, const pp
     return hip_status(launch_lateral_stiffness(a, reinterpret_cast<const float4 *>(ff),
                                                reinterpret_cast<const float4 *>(pp), k_out,
                                                (hipStream_t)stream));
+}
+
+static ppm_status hartree_plans(const ppm_grid *grid, FftPlan plans[3])
+{
+    ppm_status st;
+    if ((st = check_grid(grid)) != PPM_OK) return st;
+    for (int i = 0; i < 3; ++i)
+        if (!fft_plan(grid->n[i], &plans[i])) return PPM_EUNSUPPORTED;
+    return PPM_OK;
+}
+
+size_t ppm_hartree_workspace_bytes(const ppm_grid *grid)
+{
+    FftPlan plans[3];
+    if (hartree_plans(grid, plans) != PPM_OK) return 0;
+    const size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+    return 3 * align256(N * 16);
+}
+
+ppm_status ppm_tip_density(const ppm_grid *grid, double q_pp, double q_zz, double sigma,
+                           float *rho, void *stream)
+{
+    ppm_status st;
+    if ((st = check_grid(grid)) != PPM_OK) return st;
+    if (!rho || !(sigma > 0.0) || !isfinite(sigma) || !isfinite(q_pp) || !isfinite(q_zz))
+        return PPM_EINVAL;
+    return hip_status(launch_tip_density(grid->n[0], grid->n[1], grid->n[2], grid->step[0],
+                                         grid->step[1], grid->step[2], q_pp, q_zz, sigma, rho,
+                                         (hipStream_t)stream));
+}
+
+ppm_status ppm_hartree_ff(const ppm_grid *grid, const float *V, const float *rho,
+                          int32_t accumulate, float *ff, void *workspace,
+                          size_t workspace_bytes, void *stream)
+{
+    FftPlan plans[3];
+    ppm_status st;
+    if ((st = hartree_plans(grid, plans)) != PPM_OK) return st;
+    if (!V || !rho || !ff || !workspace) return PPM_EINVAL;
+    if (accumulate != 0 && accumulate != 1) return PPM_EINVAL;
+    const size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+    const size_t one = align256(N * 16);
+    if (workspace_bytes < 3 * one) return PPM_EINVAL;
+    char *ws = static_cast<char *>(workspace);
+    return hip_status(launch_hartree(plans, grid->n[0], grid->n[1], grid->n[2], grid->step[0],
+                                     grid->step[1], grid->step[2], V, rho, accumulate,
+                                     reinterpret_cast<float4 *>(ff),
+                                     reinterpret_cast<double2 *>(ws),
+                                     reinterpret_cast<double2 *>(ws + one),
+                                     reinterpret_cast<double2 *>(ws + 2 * one),
+                                     (hipStream_t)stream));
 }
 
 }  // extern "C"

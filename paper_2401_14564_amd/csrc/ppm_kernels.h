@@ -28,6 +28,7 @@ struct FFArgs {
     int n_atoms;
     double R_pp, eps_pp;      // probe LJ parameters
     double kq_pp;             // k_e * q_pp
+    double kQ_pp;             // k_e * q_zz (quadrupolar probe charge)
     double Lx, Ly;            // periods (periodic only)
     float rc2;                // cutoff^2 (periodic only)
     double cull2;             // (cutoff + brick half-diagonal)^2 (periodic only)
@@ -136,6 +137,27 @@ hipError_t launch_lateral_stiffness(const ScanArgs &a, const float4 *ff, const f
 hipError_t launch_df(const float *fz, int nz, int ny, int nx, int m, const DfWeights &w,
                      float *df, hipStream_t stream);
 
+// ------------------------------------------------ grid electrostatics (FFT)
+constexpr int kMaxFftLength = 1024;      // points per axis
+constexpr int kMaxFftStages = 16;
+
+// Radix sequence of one axis and the number of lines a block transforms.
+struct FftPlan {
+    int n;
+    int lines;
+    int n_stages;
+    int radix[kMaxFftStages];
+};
+
+// false if n is not 2^a 3^b 5^c with 2 <= n <= kMaxFftLength
+bool fft_plan(int n, FftPlan *p);
+hipError_t launch_tip_density(int nx, int ny, int nz, double hx, double hy, double hz,
+                              double q_pp, double q_zz, double sigma, float *rho,
+                              hipStream_t stream);
+hipError_t launch_hartree(const FftPlan plans[3], int nx, int ny, int nz, double hx, double hy,
+                          double hz, const float *V, const float *rho, int accumulate,
+                          float4 *ff, double2 *Z, double2 *A, double2 *B, hipStream_t stream);
+
 // ---------------------------------------------------------------- backward
 struct BwdArgs {
     ScanArgs s;               // same grid/probe/scan description as the forward
@@ -145,6 +167,7 @@ struct BwdArgs {
     float rc2;
     int n_atoms;
     double R_pp, eps_pp, kq_pp, ke_qpp;
+    double kQ_pp;             // k_e * q_zz; the scatter adds the quadrupole terms if != 0
     int eq_per_block;         // equilibria handled by one block of the scatter
     int n_eq_blocks;          // number of equilibrium chunks
 };

@@ -152,7 +152,12 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
     }
 }
 
-// One wave per chunk of relaxed points; lane = atom.
+// One wave per chunk of relaxed points; lane = atom.  QUAD: the probe carries
+// the d_z2 quadrupole q_zz, whose pair force is f = -kQ grad u with
+// u = (3 dz^2 - rho^2)/rho^5 and grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7,
+// b = 6 dz rho^-5; its derivatives are df/d(atom) = kQ hess u and
+// df/dq = -k_e q_zz grad u.
+template <bool QUAD>
 __global__ __launch_bounds__(64) void atom_scatter_kernel(
     const BwdArgs A, const EqRecord *__restrict__ rec, const double *__restrict__ pos,
     const double *__restrict__ q, const double *__restrict__ R, const double *__restrict__ eps,
@@ -168,8 +173,9 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
     const double eiP = sqrt(eps[ia] * A.eps_pp);
     const float e12 = (float)(12.0 * eiP);
     const float kq = (float)(A.kq_pp * q[ia]);
+    const float kQ = (float)(A.kQ_pp * q[ia]);
 
-    double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0;
+    double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0, gqq = 0.0;
     const size_t n_eq = (size_t)a.snx * a.sny * a.snz;
     const size_t e0 = (size_t)blockIdx.x * A.eq_per_block;
     const size_t e1 = min(n_eq, e0 + (size_t)A.eq_per_block);
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
                               (float)(a.oz + (r.idx.z + 1) * A.hz - pz)};
         const float tx = r.t.x, ty = r.t.y, tz = r.t.z;
         const float wx[2] = {1.0f - tx, tx}, wy[2] = {1.0f - ty, ty}, wz[2] = {1.0f - tz, tz};
-        float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f;
+        float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f, aqq = 0.f;
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
             const int i = cc & 1, j = (cc >> 1) & 1, k = cc >> 2;
@@ -221,6 +227,20 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
             aq = fmaf(ir3, md, aq);                       // x k_e q_pp
             aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
             ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+            if (QUAD) {
+                const float ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
+                const float z2 = dz * dz;
+                const float ua = fmaf(-15.0f * z2, ir7, 3.0f * ir5);
+                const float ub = 6.0f * dz * ir5;
+                // grad a . m and grad b . m
+                const float ga = fmaf(fmaf(105.0f * z2, ir9, -15.0f * ir7), md,
+                                      -30.0f * dz * ir7 * mz);
+                const float gb = fmaf(6.0f * ir5, mz, -30.0f * dz * ir7 * md);
+                ax_ = fmaf(kQ, fmaf(ua, mx, dx * ga), ax_);
+                ay_ = fmaf(kQ, fmaf(ua, my, dy * ga), ay_);
+                az_ = fmaf(kQ, fmaf(ua, mz, fmaf(dz, ga, gb)), az_);
+                aqq = fmaf(ua, md, fmaf(ub, mz, aqq));    // x -k_e q_zz
+            }
         }
         gx += ax_;
         gy += ay_;
@@ -228,6 +248,7 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
         gq += aq;
         gR += aR;
         ge += ae;
+        gqq += aqq;
     }
     if (live) {
         const int na_pad = gridDim.y * 64;
@@ -235,7 +256,7 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
         out[0] = gx;
         out[1] = gy;
         out[2] = gz;
-        out[3] = gq * A.ke_qpp;
+        out[3] = gq * A.ke_qpp - (QUAD ? gqq * A.kQ_pp : 0.0);
         out[4] = gR * 72.0 * eiP / RiP;
         out[5] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
     }
@@ -308,8 +329,12 @@ hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *f
     if (A.n_atoms == 0) return hipSuccess;
     const int na_blocks = (A.n_atoms + 63) / 64;
     dim3 g2(A.n_eq_blocks, na_blocks, 1);
-    hipLaunchKernelGGL(atom_scatter_kernel, g2, dim3(64, 1, 1), 0, stream, A, rec, pos, q, R, eps,
-                       partial_ws);
+    if (A.kQ_pp != 0.0)
+        hipLaunchKernelGGL(atom_scatter_kernel<true>, g2, dim3(64, 1, 1), 0, stream, A, rec, pos,
+                           q, R, eps, partial_ws);
+    else
+        hipLaunchKernelGGL(atom_scatter_kernel<false>, g2, dim3(64, 1, 1), 0, stream, A, rec, pos,
+                           q, R, eps, partial_ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_kernel, dim3(A.n_atoms * 6, 1, 1), dim3(256, 1, 1), 0, stream,

@@ -1,0 +1,105 @@
+"""Quadrupolar (d_z2) probe charge of Sec. 2.2.3 on the GPU against the FP64
+oracle, whose quadrupole term is pinned in test_oracle_quadrupole.py: the
+force-field and energy grids, the batched build, and the backward."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import paper_2401_14564_amd as ppm
+from paper_2401_14564_amd import workloads as W
+from parity import check_ff
+
+pytestmark = pytest.mark.gpu
+
+# the CO tip of the model comparison (Sec. 2.2.5), and one carrying both charges
+QUAD_PROBES = {"quadrupole": dict(q_pp=0.0, q_zz=-0.05),
+               "mixed": dict(q_pp=-0.05, q_zz=-0.1)}
+
+
+def _with(w, **kw):
+    return dataclasses.replace(w, probe=dataclasses.replace(w.probe, **kw))
+
+
+@pytest.mark.parametrize("kind", list(QUAD_PROBES))
+def test_quadrupole_ff_c0_full_grid(kind):
+    w = _with(W.config0(), **QUAD_PROBES[kind])
+    ref, sc = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
+    got = ppm.build_ff(w.grid, w.probe, w.atoms).cpu().numpy()
+    info = check_ff(got, ref, sc, f"C0 {kind}")
+    print("C0 quadrupole ff", kind, info, flush=True)
+    # the energy-only build sums exactly like the E channel of the full build
+    E = ppm.build_energy(w.grid, w.probe, w.atoms).cpu().numpy()
+    assert np.array_equal(E, got[..., 3])
+
+
+def test_quadrupole_ff_c1_sampled_voxels():
+    w = _with(W.config1(), q_pp=0.0, q_zz=-0.05)
+    got = ppm.build_ff(w.grid, w.probe, w.atoms).cpu().numpy()
+    rng = np.random.default_rng(21)
+    n = np.asarray(w.grid.n)
+    idx = np.stack([rng.integers(0, n[0], 20000), rng.integers(0, n[1], 20000),
+                    rng.integers(0, n[2], 20000)], axis=1).astype(np.int32)
+    ref, sc = orc.ff_voxels(w.grid, w.probe, w.atoms, idx)
+    g = got[idx[:, 2], idx[:, 1], idx[:, 0]]
+    info = check_ff(g, ref, sc, "C1 quadrupole sampled")
+    print("C1 quadrupole sampled", info, flush=True)
+
+
+@pytest.mark.parametrize("n,natoms,periodic", [((67, 9, 13), 300, 0), ((130, 90, 11), 40, 1)])
+def test_quadrupole_ff_ragged_and_periodic(n, natoms, periodic):
+    rng = np.random.default_rng(sum(n) + natoms + 7)
+    h = 0.1
+    L = np.array(n) * h
+    atoms = W.random_atoms(rng, natoms, [0, 0, -1.0], [L[0], L[1], 0.0])
+    cutoff = 0.5 * min(L[0], L[1]) - 3.5 if periodic else 0.0
+    grid = W.Grid((0.0, 0.0, 1.5), (h, h, h), n, periodic, cutoff)
+    probe = W.Probe(q_zz=-0.05)
+    ref, sc = orc.build_ff(grid, probe, atoms, with_scale=True)
+    got = ppm.build_ff(grid, probe, atoms).cpu().numpy()
+    check_ff(got, ref, sc, f"quadrupole grid {n} periodic {periodic}")
+
+
+def test_quadrupole_batch_equals_single_calls():
+    ws = [W.config3_molecule(i) for i in (0, 1)]
+    probe = dataclasses.replace(ws[0].probe, q_pp=0.0, q_zz=-0.05)
+    mols = [(w.atoms, w.grid) for w in ws]
+    jobs = [(i, probe, w.scan) for i, w in enumerate(ws)]
+    bp = ppm.BatchPipeline(mols, jobs, probe, ws[0].fire, ws[0].df)
+    bp.run()
+    torch.cuda.synchronize()
+    for i, w in enumerate(ws):
+        ff = ppm.build_ff(w.grid, probe, w.atoms)
+        assert torch.equal(bp.ff_grid(i), ff), i
+        res = ppm.relaxed_scan(w.grid, ff, probe, w.fire, w.scan, dfp=w.df, pp=False)
+        assert torch.equal(bp.df_stack(i), res["df"]), i
+
+
+def test_quadrupole_backward_against_oracle():
+    """Gradient of sum(gdf * df) with a quadrupolar probe vs the oracle's FP64
+    adjoint (pinned by central differences with the same probe)."""
+    rng = np.random.default_rng(78)
+    atoms = W.random_atoms(rng, 7, [0.8, 0.8, -0.2], [2.6, 2.6, 0.2], q_max=0.3)
+    grid = W.Grid((0.0, 0.0, -1.0), (0.1, 0.1, 0.1), (36, 36, 70))
+    scan = W.Scan(1.13, 1.21, 0.17, 0.19, 9, 7, 8.2, 0.1, 16)
+    probe = W.Probe(q_pp=0.0, q_zz=-0.05)
+    dfp = W.DfParams()
+    fire = W.parity_fire(W.Fire(), f_conv=1e-8)
+    m = orc.df_m(dfp.A, scan.dz)
+    gdf = np.random.default_rng(6).normal(size=(scan.nz - 2 * m, scan.ny, scan.nx))
+    ff = ppm.build_ff(grid, probe, atoms)
+    res = ppm.relaxed_scan(grid, ff, probe, fire, scan, dfp=dfp)
+    g = ppm.relaxed_scan_backward(grid, ff, probe, scan, dfp, atoms, res["pp"],
+                                  torch.as_tensor(gdf, dtype=torch.float32, device="cuda"))
+    off = orc.build_ff(grid, probe, atoms)
+    ores = orc.relaxed_scan(grid, off, probe, fire, scan, polish_tol=1e-12)
+    o = orc.scan_backward(grid, off, probe, scan, ores["cols"], ores["r"],
+                          gdf.reshape(gdf.shape[0], -1), dfp, atoms)
+    for k in ("pos", "q", "R", "eps"):
+        a = g[k].cpu().numpy().reshape(-1)
+        b = o[k].reshape(-1)
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print(f"quadrupole backward {k}: rel err {err:.3e}", flush=True)
+        assert err <= 1e-3, (k, err)
