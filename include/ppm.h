@@ -298,7 +298,8 @@ ppm_status ppm_tip_density(const ppm_grid *grid, double q_pp, double q_zz, doubl
                            float *rho, void *stream);
 
 /* Workspace (bytes) ppm_hartree_ff needs for this grid: three complex FP64
- * grids; 0 if the grid is invalid or unsupported. */
+ * grids and a few KiB of reduction scratch; 0 if the grid is invalid or
+ * unsupported. */
 size_t ppm_hartree_workspace_bytes(const ppm_grid *grid);
 
 /*

@@ -186,6 +186,50 @@ def lateral_stiffness(grid, ff, probe, scan, pp, out: torch.Tensor | None = None
     return out
 
 
+def tip_density(grid, q_pp: float, q_zz: float, sigma: float,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """Probe charge density [nz, ny, nx] (float32, e/A^3) on the grid's lattice of
+    offsets from the probe centre: Gaussian-smeared point charge + d_z2 quadrupole."""
+    L = _lib.lib()
+    nx, ny, nz = (int(v) for v in grid.n)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=_device())
+    assert out.shape == (nz, ny, nx) and out.dtype == torch.float32 and out.is_contiguous()
+    st = L.ppm_tip_density(_lib.grid_struct(grid), float(q_pp), float(q_zz), float(sigma),
+                           _lib.ptr(out), _stream())
+    _lib.check(st, "ppm_tip_density")
+    return out
+
+
+def hartree_workspace(grid, device=None) -> torch.Tensor:
+    """Workspace buffer for hartree_ff on this grid."""
+    nbytes = int(_lib.lib().ppm_hartree_workspace_bytes(_lib.grid_struct(grid)))
+    if nbytes == 0:
+        _lib.check(_lib.PPM_EUNSUPPORTED, "ppm_hartree_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or _device())
+
+
+def hartree_ff(grid, V: torch.Tensor, rho: torch.Tensor, out: torch.Tensor | None = None,
+               accumulate: bool = False, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Energy and force of the probe density rho in the sample potential V (both
+    [nz, ny, nx] float32): (Fx, Fy, Fz, E) [nz, ny, nx, 4], written, or added to
+    `out` when accumulate is set."""
+    L = _lib.lib()
+    nx, ny, nz = (int(v) for v in grid.n)
+    for t in (V, rho):
+        assert t.shape == (nz, ny, nx) and t.dtype == torch.float32 and t.is_contiguous()
+    if out is None:
+        assert not accumulate
+        out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=V.device)
+    assert out.shape == (nz, ny, nx, 4) and out.dtype == torch.float32 and out.is_contiguous()
+    if workspace is None:
+        workspace = hartree_workspace(grid, V.device)
+    st = L.ppm_hartree_ff(_lib.grid_struct(grid), _lib.ptr(V), _lib.ptr(rho), int(accumulate),
+                          _lib.ptr(out), _lib.ptr(workspace), workspace.numel(), _stream())
+    _lib.check(st, "ppm_hartree_ff")
+    return out
+
+
 class AFMStack(torch.autograd.Function):
     """df = AFMStack.apply(pos, q, R, eps, grid, probe, fire, scan, dfp)
 

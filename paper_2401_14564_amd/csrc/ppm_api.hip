@@ -554,7 +554,7 @@ size_t ppm_hartree_workspace_bytes(const ppm_grid *grid)
     FftPlan plans[3];
     if (hartree_plans(grid, plans) != PPM_OK) return 0;
     const size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
-    return 3 * align256(N * 16);
+    return 3 * align256(N * 16) + align256(hartree_scratch_bytes());
 }
 
 ppm_status ppm_tip_density(const ppm_grid *grid, double q_pp, double q_zz, double sigma,
@@ -580,14 +580,14 @@ ppm_status ppm_hartree_ff(const ppm_grid *grid, const float *V, const float *rho
     if (accumulate != 0 && accumulate != 1) return PPM_EINVAL;
     const size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
     const size_t one = align256(N * 16);
-    if (workspace_bytes < 3 * one) return PPM_EINVAL;
+    if (workspace_bytes < 3 * one + align256(hartree_scratch_bytes())) return PPM_EINVAL;
     char *ws = static_cast<char *>(workspace);
     return hip_status(launch_hartree(plans, grid->n[0], grid->n[1], grid->n[2], grid->step[0],
                                      grid->step[1], grid->step[2], V, rho, accumulate,
                                      reinterpret_cast<float4 *>(ff),
                                      reinterpret_cast<double2 *>(ws),
                                      reinterpret_cast<double2 *>(ws + one),
-                                     reinterpret_cast<double2 *>(ws + 2 * one),
+                                     reinterpret_cast<double2 *>(ws + 2 * one), ws + 3 * one,
                                      (hipStream_t)stream));
 }
 

@@ -154,9 +154,12 @@ bool fft_plan(int n, FftPlan *p);
 hipError_t launch_tip_density(int nx, int ny, int nz, double hx, double hy, double hz,
                               double q_pp, double q_zz, double sigma, float *rho,
                               hipStream_t stream);
+// scratch: hartree_scratch_bytes() of device memory (reduction partials, alpha)
+size_t hartree_scratch_bytes();
 hipError_t launch_hartree(const FftPlan plans[3], int nx, int ny, int nz, double hx, double hy,
                           double hz, const float *V, const float *rho, int accumulate,
-                          float4 *ff, double2 *Z, double2 *A, double2 *B, hipStream_t stream);
+                          float4 *ff, double2 *Z, double2 *A, double2 *B, void *scratch,
+                          hipStream_t stream);
 
 // ---------------------------------------------------------------- backward
 struct BwdArgs {

@@ -172,3 +172,23 @@ def test_batch_plan_offsets_on_host():
     # a job pointing at a missing molecule is rejected
     jobs[5].mol = 3
     assert L.ppm_batch_plan(3, mols, 6, jobs, None, totals) == _lib.PPM_EINVAL
+
+
+def test_hartree_sizes_and_bad_arguments():
+    L = _lib.lib()
+    E, U = _lib.PPM_EINVAL, _lib.PPM_EUNSUPPORTED
+    g = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (240, 30, 27)))
+    nbytes = L.ppm_hartree_workspace_bytes(g)
+    n = 240 * 30 * 27
+    assert nbytes >= 3 * ((n * 16 + 255) // 256 * 256) and nbytes % 256 == 0
+    for bad in ((7, 8, 8), (8, 8, 1030), (8, 11, 8)):        # prime factor 7/11, too long
+        gb = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), bad))
+        assert L.ppm_hartree_workspace_bytes(gb) == 0
+        assert L.ppm_hartree_ff(gb, FAKE, FAKE, 0, FAKE, FAKE, 1 << 40, None) == U
+    assert L.ppm_hartree_ff(g, None, FAKE, 0, FAKE, FAKE, nbytes, None) == E
+    assert L.ppm_hartree_ff(g, FAKE, FAKE, 2, FAKE, FAKE, nbytes, None) == E
+    assert L.ppm_hartree_ff(g, FAKE, FAKE, 0, FAKE, FAKE, nbytes - 1, None) == E
+    assert L.ppm_hartree_ff(g, FAKE, FAKE, 0, FAKE, None, nbytes, None) == E
+    assert L.ppm_tip_density(g, 0.0, -0.05, 0.0, FAKE, None) == E
+    assert L.ppm_tip_density(g, float("nan"), -0.05, 0.7, FAKE, None) == E
+    assert L.ppm_tip_density(g, 0.0, -0.05, 0.7, None, None) == E
