@@ -124,6 +124,12 @@ def summarize_pmc(fetch_dir, write_dir):
         e = out.get(key)
         if e and "fetch_size_bytes" in e and "write_size_bytes" in e:
             e["hbm_bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
+    out["commands"] = [
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/" + fetch_dir.rstrip("/").split(
+            "/")[-1] + " -o pmc -- python3 $REPO/bench.py --kernels-once",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/" + write_dir.rstrip("/").split(
+            "/")[-1] + " -o pmc -- python3 $REPO/bench.py --kernels-once",
+        f"python3 bench.py --summarize-pmc {fetch_dir} {write_dir}"]
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
@@ -287,6 +293,7 @@ def main():
         result["backward"] = _bench_backward(ppm, W, torch)
         result["batched"] = _bench_batch(ppm, W, torch)
         result["large_periodic"] = _bench_large(ppm, W, torch)
+        result["next_rows"] = _bench_next_rows(ppm, W, torch)
 
     if not a.no_cpu:
         result["cpu_baseline"] = _cpu_baseline(w, n_eq)
@@ -494,6 +501,54 @@ def _bench_large(ppm, W, torch):
             "mean_fire_steps": round(float(iters.abs().mean().item()), 3),
             "not_converged": int((iters < 0).sum().item()),
             "scan_gather_gbs": round(scan_bytes / (scan_ms * 1e-3) / 1e9, 1)}
+
+
+FLOP_PER_PAIR_ENERGY = 20     # energy only: d 3, r^2 5, rsq 1, 1/r^2 1, s^2 1, s^6 2,
+                              # s^12 1, E_LJ 3, E_C 1, E sum 2
+
+
+def _bench_next_rows(ppm, W, torch):
+    """Paper-scale workload: lateral-mode stiffness post-pass over every relaxed
+    point, and the tricubic variant (energy-only grid + scan on its tricubic
+    interpolant)."""
+    w = W.config1()
+    atoms = ppm.atoms_to_device(w.atoms)
+    ff = ppm.build_ff(w.grid, w.probe, atoms)
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df)
+    kbuf = ppm.lateral_stiffness(w.grid, ff, w.probe, w.scan, res["pp"])
+    E = ppm.build_energy(w.grid, w.probe, atoms)
+    tri = ppm.relaxed_scan_tricubic(w.grid, E, w.probe, w.fire, w.scan, dfp=w.df)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    tk, te, ts = [], [], []
+    for _ in range(4):
+        e[0].record()
+        ppm.lateral_stiffness(w.grid, ff, w.probe, w.scan, res["pp"], out=kbuf)
+        e[1].record()
+        ppm.build_energy(w.grid, w.probe, atoms, out=E)
+        e[2].record()
+        ppm.relaxed_scan_tricubic(w.grid, E, w.probe, w.fire, w.scan, dfp=w.df, out=tri)
+        e[3].record()
+        torch.cuda.synchronize()
+        tk.append(e[0].elapsed_time(e[1]))
+        te.append(e[1].elapsed_time(e[2]))
+        ts.append(e[2].elapsed_time(e[3]))
+    n_eq = w.scan.n_eq
+    pairs = w.grid.nvox * w.atoms.n
+    k_ms, e_ms, s_ms = (float(np.median(x[1:])) for x in (tk, te, ts))
+    it = tri["pp"][..., 3]
+    return {"workload": "paper-scale (60 atoms, 240^3 grid, 240x240x100 scan)",
+            "lateral_stiffness": {"ms": round(k_ms, 3),
+                                  "points_per_s": round(n_eq / (k_ms * 1e-3), 1),
+                                  "gather_gbs": round(n_eq * (BYTES_PER_EVAL + 16 + 8) /
+                                                      (k_ms * 1e-3) / 1e9, 1)},
+            "tricubic": {"energy_grid_ms": round(e_ms, 3),
+                         "energy_grid_tflops": round(pairs * FLOP_PER_PAIR_ENERGY /
+                                                     (e_ms * 1e-3) / 1e12, 2),
+                         "scan_ms": round(s_ms, 3),
+                         "relaxations_per_s": round(n_eq / ((e_ms + s_ms) * 1e-3), 1),
+                         "mean_fire_steps": round(float(it.abs().mean().item()), 3),
+                         "not_converged": int((it < 0).sum().item()),
+                         "grid_bytes": int(w.grid.nvox * 4)}}
 
 
 def _cpu_baseline(w, n_eq):
