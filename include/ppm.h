@@ -72,7 +72,9 @@ typedef int32_t ppm_status;
  * x and y with periods n[0]*step[0] and n[1]*step[1]: each pair uses the
  * minimum image and is included iff rho^2 < cutoff^2.  With periodic_xy = 0 the
  * sum runs over all atoms (open boundary) and cutoff is ignored.  For
- * interpolation the grid wraps in x and y and is clamped in z (the field is
+ * interpolation a periodic grid wraps in x and y; an open grid is clamped to
+ * its first/last cell in x and y (the field is continued constantly beyond
+ * its edges, having no images to wrap to); z is always clamped (the field is
  * constant above and below the grid). */
 typedef struct {
     double origin[3];
@@ -104,8 +106,9 @@ typedef struct {
  * than n_min such steps in a row dt = min(dt*f_inc, dt_max), alpha *= f_alpha;
  * if P <= 0, v = 0, dt *= f_dec, alpha = alpha0.  Then v += G dt/mass,
  * r += v dt.  A point is converged when |G|_2 < f_conv (eV/A); after max_iter
- * steps it is recorded as not converged.  dt, alpha and v restart at every
- * height. */
+ * steps it is recorded as not converged.  alpha and v restart at every
+ * height; dt starts at dt0 and then continues from height to height (see
+ * ppm_scan). */
 typedef struct {
     double dt0, dt_max, f_inc, f_dec, alpha0, f_alpha, mass, f_conv;
     int32_t n_min, max_iter;
@@ -113,8 +116,11 @@ typedef struct {
 
 /* Tip lattice: anchor of column (ix, iy) at height index k is
  * (x0 + ix*dx, y0 + iy*dy, z_top - k*dz), ix < nx, iy < ny, k < nz.
- * At k = 0 the probe starts at anchor + d0; at k > 0 at the previous height's
- * relaxed position moved by the anchor's step (warm start). */
+ * At k = 0 the probe starts at anchor + d0.  Warm start at k > 0: with
+ * u(k) = relaxed position - anchor(k), the relaxation starts from
+ * anchor(k) + u(k-1) + (u(k-1) - u(k-2)) (linear extrapolation; anchor(1) + u(0)
+ * at k = 1), with zero velocity, alpha = alpha0 and the FIRE time step
+ * continued from the previous height's final value (not below dt0). */
 typedef struct {
     double x0, y0, dx, dy;
     int32_t nx, ny;
@@ -204,8 +210,9 @@ ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_
  * sample force taken from a tricubic interpolant of the energy grid instead of
  * trilinear forces (the variant Sec. 5.1.1 step 2 describes as under test).
  * Interpolant: Catmull-Rom (Keys a = -1/2) cubic convolution per axis on the
- * stencil i-1..i+2; F = -grad of the interpolant.  x,y wrap; the z stencil is
- * clamped to the grid and outside [0, nz-1] the potential is constant in z.
+ * stencil i-1..i+2; F = -grad of the interpolant.  x,y wrap on a periodic
+ * grid; otherwise, and always in z, the point is clamped to the grid box:
+ * outside [0, n-1] the force is continued constantly along that axis.
  * in:  E[nz][ny][nx] from ppm_build_energy.  Outputs, errors: as ppm_relaxed_scan.
  */
 ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,

@@ -30,11 +30,17 @@
  * Readings where the paper is silent (also listed in the design notes):
  *   units A / eV / e; k_e = 14.3996454784 eV*A/e^2; 1 eV/A^2 = 16.02176634 N/m;
  *   d0 points from the anchor down to the probe (z up); voxel (i,j,k) sits at
- *   origin + (i hx, j hy, k hz); interpolation wraps x,y and clamps z;
+ *   origin + (i hx, j hy, k hz); interpolation wraps x,y on a periodic grid
+ *   and clamps them to the first/last cell otherwise (a sample built without
+ *   images has no field to wrap to), and always clamps z;
  *   FIRE parameters are inputs, the first step from rest skips the power test;
- *   convergence is |G|_2 < f_conv; warm start r0(k) = r*(k-1) + (anchor(k) -
- *   anchor(k-1)); frequency shift integrates the piecewise-linear interpolant
- *   of the Fz samples exactly ("valid" outputs only).
+ *   convergence is |G|_2 < f_conv; warm start between heights: with
+ *   u(k) = r*(k) - anchor(k) the relaxed displacement, the relaxation at height
+ *   k starts from anchor(k) + u(k-1) + (u(k-1) - u(k-2)) (linear extrapolation;
+ *   anchor(k) + u(k-1) at k = 1, anchor + d0 at k = 0), with v = 0, alpha =
+ *   alpha0, and dt = max(the previous height's final dt, dt0); frequency shift
+ *   integrates the piecewise-linear interpolant of the Fz samples exactly
+ *   ("valid" outputs only).
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so ppm_oracle.c -lm
  */
@@ -220,7 +226,7 @@ void orc_ff_voxels(const double *g, const int *n, const double *p, int na,
 typedef struct {
     int ix[2], iy[2], iz[2];     /* voxel indices of the cell corners */
     double tx, ty, tz;           /* fractional position inside the cell */
-    int zin;                     /* 0 when z was clamped (field constant in z) */
+    int xin, yin, zin;           /* 0 when the axis was clamped (field constant along it) */
 } orc_cell;
 
 static int orc_wrap(long i, int n)
@@ -229,23 +235,39 @@ static int orc_wrap(long i, int n)
     return (int)(m < 0 ? m + n : m);
 }
 
+/* Cell of grid coordinate u on an axis of n points clamped to the first/last
+ * cell: outside the grid the field is continued constantly. */
+static int orc_clamp_cell(double u, int n, double *t, int *in)
+{
+    double f = floor(u);
+    *in = 1;
+    if (f < 0) { *t = 0.0; *in = 0; return 0; }
+    if (f > n - 2) { *t = 1.0; *in = 0; return n - 2; }
+    *t = u - f;
+    return (int)f;
+}
+
 static void orc_locate(const double *g, const int *n, const double *r, orc_cell *c)
 {
     double ux = (r[0] - g[0]) / g[3];
     double uy = (r[1] - g[1]) / g[4];
     double uz = (r[2] - g[2]) / g[5];
-    double fx = floor(ux), fy = floor(uy);
-    c->tx = ux - fx;
-    c->ty = uy - fy;
-    c->ix[0] = orc_wrap((long)fx, n[0]); c->ix[1] = orc_wrap((long)fx + 1, n[0]);
-    c->iy[0] = orc_wrap((long)fy, n[1]); c->iy[1] = orc_wrap((long)fy + 1, n[1]);
-    /* z: clamp to the first/last cell; outside the grid the field is constant */
-    double fz = floor(uz);
-    c->zin = 1;
-    if (fz < 0) { fz = 0; c->tz = 0.0; c->zin = 0; }
-    else if (fz > n[2] - 2) { fz = n[2] - 2; c->tz = 1.0; c->zin = 0; }
-    else c->tz = uz - fz;
-    c->iz[0] = (int)fz; c->iz[1] = (int)fz + 1;
+    if (g[6] != 0.0) {
+        /* periodic in x,y: wrap */
+        double fx = floor(ux), fy = floor(uy);
+        c->tx = ux - fx;
+        c->ty = uy - fy;
+        c->ix[0] = orc_wrap((long)fx, n[0]); c->ix[1] = orc_wrap((long)fx + 1, n[0]);
+        c->iy[0] = orc_wrap((long)fy, n[1]); c->iy[1] = orc_wrap((long)fy + 1, n[1]);
+        c->xin = c->yin = 1;
+    } else {
+        int i = orc_clamp_cell(ux, n[0], &c->tx, &c->xin);
+        int j = orc_clamp_cell(uy, n[1], &c->ty, &c->yin);
+        c->ix[0] = i; c->ix[1] = i + 1;
+        c->iy[0] = j; c->iy[1] = j + 1;
+    }
+    int k = orc_clamp_cell(uz, n[2], &c->tz, &c->zin);
+    c->iz[0] = k; c->iz[1] = k + 1;
 }
 
 static const double *orc_vox(const double *ff, const int *n, int ix, int iy, int iz)
@@ -264,6 +286,8 @@ void orc_interp(const double *ff, const double *g, const int *n, const double *r
            wz[2] = { 1.0 - c.tz, c.tz };
     double dwx[2] = { -1.0 / g[3], 1.0 / g[3] }, dwy[2] = { -1.0 / g[4], 1.0 / g[4] },
            dwz[2] = { -1.0 / g[5], 1.0 / g[5] };
+    if (!c.xin) { dwx[0] = 0.0; dwx[1] = 0.0; }
+    if (!c.yin) { dwy[0] = 0.0; dwy[1] = 0.0; }
     if (!c.zin) { dwz[0] = 0.0; dwz[1] = 0.0; }
     F[0] = F[1] = F[2] = 0.0;
     if (jac) for (int k = 0; k < 9; ++k) jac[k] = 0.0;
@@ -291,8 +315,10 @@ void orc_interp(const double *ff, const double *g, const int *n, const double *r
 /* the paper is experimenting with -- store only E, interpolate it with a      */
 /* cubic in each direction and take the force as minus its gradient).          */
 /* Reading: Catmull-Rom cubic convolution (Keys, a = -1/2) on the 4-point      */
-/* stencil i-1..i+2 per axis; x,y wrap; z indices are clamped to the grid and  */
-/* outside [0, nz-1] the potential is continued constantly in z.               */
+/* stencil i-1..i+2 per axis; x,y wrap on a periodic grid; otherwise (and     */
+/* always for z) the point is clamped to the grid box: outside [0, n-1] the    */
+/* force is continued constantly along that axis, as the trilinear field is   */
+/* (the energy reported there is the value at the clamped point).             */
 /* ------------------------------------------------------------------------ */
 
 /* Catmull-Rom basis for the stencil offsets -1, 0, 1, 2 at fraction t, with
@@ -320,23 +346,32 @@ void orc_interp_tricubic(const double *En, const double *g, const int *n, const 
                          double *E, double *F, double *hess)
 {
     double u[3] = { (r[0] - g[0]) / g[3], (r[1] - g[1]) / g[4], (r[2] - g[2]) / g[5] };
-    int zin = 1;
-    if (u[2] < 0.0) { u[2] = 0.0; zin = 0; }
-    if (u[2] > n[2] - 1) { u[2] = n[2] - 1; zin = 0; }
+    int periodic = g[6] != 0.0;
+    int in[3] = { 1, 1, 1 };
+    for (int a = 0; a < 3; ++a) {
+        if (a < 2 && periodic) continue;
+        if (u[a] < 0.0) { u[a] = 0.0; in[a] = 0; }
+        if (u[a] > n[a] - 1) { u[a] = n[a] - 1; in[a] = 0; }
+    }
     int base[3];
     double t[3], w[3][4], dw[3][4], d2w[3][4];
     for (int a = 0; a < 3; ++a) {
         double f = floor(u[a]);
-        if (a == 2 && f > n[2] - 2) f = n[2] - 2;     /* top node: last cell, t = 1 */
+        if ((a == 2 || !periodic) && f > n[a] - 2) f = n[a] - 2;   /* top node: last cell, t = 1 */
         base[a] = (int)f;
         t[a] = u[a] - f;
         orc_cr_weights(t[a], w[a], dw[a], d2w[a]);
     }
     int ix[4], iy[4], iz[4];
     for (int s = 0; s < 4; ++s) {
-        ix[s] = orc_wrap((long)base[0] + s - 1, n[0]);
-        iy[s] = orc_wrap((long)base[1] + s - 1, n[1]);
-        int z = base[2] + s - 1;
+        int x = base[0] + s - 1, y = base[1] + s - 1, z = base[2] + s - 1;
+        if (periodic) {
+            ix[s] = orc_wrap((long)x, n[0]);
+            iy[s] = orc_wrap((long)y, n[1]);
+        } else {
+            ix[s] = x < 0 ? 0 : (x > n[0] - 1 ? n[0] - 1 : x);
+            iy[s] = y < 0 ? 0 : (y > n[1] - 1 ? n[1] - 1 : y);
+        }
         iz[s] = z < 0 ? 0 : (z > n[2] - 1 ? n[2] - 1 : z);
     }
     double h[3] = { g[3], g[4], g[5] };
@@ -358,13 +393,16 @@ void orc_interp_tricubic(const double *En, const double *g, const int *n, const 
                     H[5] += w[0][a] * dw[1][b] * dw[2][c] * v;
                 }
             }
-    if (!zin) { gr[2] = 0.0; H[2] = H[5] = H[8] = 0.0; }
     *E = e;
     for (int a = 0; a < 3; ++a) F[a] = -gr[a] / h[a];
     if (hess) {
+        /* hess[a][b] = -dF_a/dx_b: the Hessian of the interpolant at the clamped
+         * point, with the columns of clamped axes zero (the force does not
+         * change along them); not symmetric then */
         H[3] = H[1]; H[6] = H[2]; H[7] = H[5];
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) hess[3 * a + b] = H[3 * a + b] / (h[a] * h[b]);
+            for (int b = 0; b < 3; ++b)
+                hess[3 * a + b] = in[b] ? H[3 * a + b] / (h[a] * h[b]) : 0.0;
     }
 }
 
@@ -492,14 +530,15 @@ double orc_sym3_min_eig(const double *S_in)
  *       P <= 0: v <- 0, dt <- dt f_dec, alpha <- alpha0
  *   semi-implicit Euler: v += G dt/m ; r += v dt ; re-evaluate G.
  * Stops when |G| < f_conv or after max_iter steps.  Returns the number of
- * steps taken, negated if not converged.
+ * steps taken, negated if not converged.  dt_io: the initial time step on
+ * entry, the final one on return.
  */
 static int orc_fire(int mode, const double *ff, const double *g, const int *n,
                     const double *p, const double *f, const int *fi, const double *anchor,
-                    double *r, double *gnorm)
+                    double *r, double *gnorm, double *dt_io)
 {
     double v[3] = { 0, 0, 0 }, G[3];
-    double dt = f[0], alpha = f[4];
+    double dt = *dt_io, alpha = f[4];
     int npos = 0;
     double gn = orc_net_mode(mode, ff, g, n, p, anchor, r, G, NULL);
     int it = 0;
@@ -530,6 +569,7 @@ static int orc_fire(int mode, const double *ff, const double *g, const int *n,
         ++it;
     }
     *gnorm = gn;
+    *dt_io = dt;
     return gn < f[7] ? it : -it;
 }
 
@@ -597,12 +637,18 @@ static void orc_relaxed_scan_mode(int mode, const double *g, const int *n, const
         int ix = cols[2 * c], iy = cols[2 * c + 1];
         double anchor[3] = { s[0] + ix * s[2], s[1] + iy * s[3], s[4] };
         double r[3] = { anchor[0] + p[6], anchor[1] + p[7], anchor[2] + p[8] };
+        double u1[3] = { 0, 0, 0 }, u2[3] = { 0, 0, 0 };   /* u(k-1), u(k-2) */
+        double dt = f[0];
         for (int k = 0; k < nz; ++k) {
             double az = s[4] - k * s[5];
-            if (k > 0) r[2] += az - anchor[2];
             anchor[2] = az;
+            if (k == 1)
+                for (int q = 0; q < 3; ++q) r[q] = anchor[q] + u1[q];
+            else if (k >= 2)
+                for (int q = 0; q < 3; ++q) r[q] = anchor[q] + u1[q] + (u1[q] - u2[q]);
+            dt = fmax(dt, f[0]);
             double gn;
-            int it = orc_fire(mode, ff, g, n, p, f, fi, anchor, r, &gn);
+            int it = orc_fire(mode, ff, g, n, p, f, fi, anchor, r, &gn, &dt);
             if (polish_tol > 0.0) gn = orc_polish(mode, ff, g, n, p, anchor, r, polish_tol);
             double Ft[3];
             orc_tip_force(r, anchor, p, Ft, NULL);
@@ -612,6 +658,7 @@ static void orc_relaxed_scan_mode(int mode, const double *g, const int *n, const
             iters_out[o] = it;
             gnorm_out[o] = gn;
             if (lam_out) lam_out[o] = orc_lambda_min(mode, ff, g, n, p, anchor, r);
+            for (int q = 0; q < 3; ++q) { u2[q] = u1[q]; u1[q] = r[q] - anchor[q]; }
         }
     }
 }

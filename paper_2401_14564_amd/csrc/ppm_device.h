@@ -34,8 +34,21 @@ struct Cell {
     uint32_t i000;             // flat index of corner (ix, iy, iz)
     int dx1, dy1, dz1;         // index offsets to the +x, +y, +z corners
     double tx, ty, tz;         // fractional position in the cell
-    bool zin;                  // false when z was clamped (field constant in z there)
+    bool xin, yin, zin;        // false when the axis was clamped (field constant along it)
 };
+
+// Cell of a grid coordinate along an axis clamped to its first/last cell:
+// index in [0, n-2], t in [0, 1]; outside the grid the field is continued
+// constantly (in = false).  NaN lands in the first cell.
+__device__ __forceinline__ int clamp_cell(double u, int n, double &t, bool &in)
+{
+    const double f = floor(u);
+    const bool below = !(f >= 0.0);
+    const bool above = f > (double)(n - 2);
+    t = below ? 0.0 : (above ? 1.0 : u - f);
+    in = !(below || above);
+    return below ? 0 : (above ? n - 2 : (int)f);
+}
 
 // Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
 // A NaN or huge coordinate is clamped before the integer conversion so the
@@ -58,16 +71,18 @@ __device__ __forceinline__ int periodic_cell(double u, int n, double &t)
 __device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
 {
     Cell c;
-    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
-    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
+    int ix, iy;
+    if (a.periodic) {
+        ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
+        iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
+        c.xin = c.yin = true;
+    } else {
+        // a sample without periodic images: x,y clamped like z
+        ix = clamp_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx, c.xin);
+        iy = clamp_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty, c.yin);
+    }
     // z is clamped to the first/last cell: outside the grid the field is constant
-    const double uz = fma(z, a.ihz, a.ozi);
-    const double fz = floor(uz);
-    const bool below = !(fz >= 0.0);                 // also catches NaN
-    const bool above = fz > (double)(a.gnz - 2);
-    c.tz = below ? 0.0 : (above ? 1.0 : uz - fz);
-    c.zin = !(below || above);
-    const int iz = below ? 0 : (above ? a.gnz - 2 : (int)fz);
+    const int iz = clamp_cell(fma(z, a.ihz, a.ozi), a.gnz, c.tz, c.zin);
     const int plane = a.gnx * a.gny;
     c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
     c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;

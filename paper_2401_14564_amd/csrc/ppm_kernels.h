@@ -54,6 +54,7 @@ struct ScanArgs {
     double oxi, oyi, ozi;     // -origin * inverse step (grid coordinate = r * ih + oi)
     double ignx, igny;        // 1/gnx, 1/gny
     int gnx, gny, gnz;
+    int periodic;             // 1: x,y wrap (periodic sample); 0: clamped like z
     // probe
     double kx, ky, kR, R0;
     double d0x, d0y, d0z;
@@ -89,6 +90,7 @@ __host__ __device__ inline void fill_scan_geometry(ScanArgs &a, const ppm_grid &
     a.gnz = g.n[2];
     a.ignx = 1.0 / g.n[0];
     a.igny = 1.0 / g.n[1];
+    a.periodic = g.periodic_xy ? 1 : 0;
     a.kx = p.k_lat[0];
     a.ky = p.k_lat[1];
     a.kR = p.k_rad;

@@ -93,24 +93,38 @@ __device__ __forceinline__ void cr_weights(double t, double *w, double *dw)
     dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
 }
 
+// Cell of the cubic stencil along a clamped axis: the coordinate is clamped to
+// [0, n-1] (NaN counts as below), the cell index to [0, n-2], so the top node
+// is the last cell at t = 1.
+__device__ __forceinline__ int cubic_clamp_cell(double u, int n, double &t)
+{
+    const bool below = !(u >= 0.0);
+    const bool above = u > (double)(n - 1);
+    u = below ? 0.0 : (above ? (double)(n - 1) : u);
+    const double f = fmin(floor(u), (double)(n - 2));
+    t = u - f;
+    return (int)f;
+}
+
 // Sample force from the tricubic interpolant of the energy grid En[nz][ny][nx]
 // (the paper's experimental variant of Sec. 5.1.1 step 2): F = -grad E_int,
-// a 4x4x4 stencil contracted axis by axis in FP64.  x,y wrap; the z stencil is
-// clamped to the grid and outside [0, nz-1] the potential is constant in z.
+// a 4x4x4 stencil contracted axis by axis in FP64.  x,y wrap on a periodic
+// grid; otherwise, and always for z, the point is clamped to the grid box:
+// outside [0, n-1] the force is continued constantly along that axis.
 __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *__restrict__ En,
                                                double x, double y, double z, double &Fx,
                                                double &Fy, double &Fz)
 {
-    double tx, ty;
-    const int ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, tx);
-    const int iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, ty);
-    double uz = fma(z, a.ihz, a.ozi);
-    const bool below = !(uz >= 0.0);                 // also catches NaN
-    const bool above = uz > (double)(a.gnz - 1);
-    uz = below ? 0.0 : (above ? (double)(a.gnz - 1) : uz);
-    const double fz = fmin(floor(uz), (double)(a.gnz - 2));
-    const double tz = uz - fz;
-    const int iz = (int)fz;
+    double tx, ty, tz;
+    int ix, iy;
+    if (a.periodic) {
+        ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, tx);
+        iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, ty);
+    } else {
+        ix = cubic_clamp_cell(fma(x, a.ihx, a.oxi), a.gnx, tx);
+        iy = cubic_clamp_cell(fma(y, a.ihy, a.oyi), a.gny, ty);
+    }
+    const int iz = cubic_clamp_cell(fma(z, a.ihz, a.ozi), a.gnz, tz);
     double wx[4], dwx[4], wy[4], dwy[4], wz[4], dwz[4];
     cr_weights(tx, wx, dwx);
     cr_weights(ty, wy, dwy);
@@ -119,10 +133,15 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         int i = ix + s - 1, j = iy + s - 1, k = iz + s - 1;
-        i += (i < 0) ? a.gnx : 0;
-        i -= (i >= a.gnx) ? a.gnx : 0;
-        j += (j < 0) ? a.gny : 0;
-        j -= (j >= a.gny) ? a.gny : 0;
+        if (a.periodic) {
+            i += (i < 0) ? a.gnx : 0;
+            i -= (i >= a.gnx) ? a.gnx : 0;
+            j += (j < 0) ? a.gny : 0;
+            j -= (j >= a.gny) ? a.gny : 0;
+        } else {
+            i = i < 0 ? 0 : (i > a.gnx - 1 ? a.gnx - 1 : i);
+            j = j < 0 ? 0 : (j > a.gny - 1 ? a.gny - 1 : j);
+        }
         k = k < 0 ? 0 : (k > a.gnz - 1 ? a.gnz - 1 : k);
         xs[s] = i;
         ys[s] = j;
@@ -148,7 +167,7 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
     }
     Fx = -gx * a.ihx;
     Fy = -gy * a.ihy;
-    Fz = (below || above) ? 0.0 : -gz * a.ihz;
+    Fz = -gz * a.ihz;
 }
 
 // One tip column (ix, iy): all heights, then (DFMODE != 0) its frequency shift.
@@ -172,6 +191,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     double rx = ax + a.d0x, ry = ay + a.d0y, rz = az + a.d0z;
     double vx = 0.0, vy = 0.0, vz = 0.0;
     double dt = a.dt0, alpha = a.alpha0;
+    double u1x = 0.0, u1y = 0.0, u1z = 0.0;      // relaxed displacement of the previous height
     int npos = 0, it = 0;
 
     while (true) {
@@ -195,13 +215,25 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             if (pp_out)
                 pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
                                         (float)(rz - az - a.d0z), conv ? (float)it : -(float)it);
-            if (++k >= a.snz) break;
-            // warm start: keep the relaxed position, move with the anchor
-            const double naz = a.z_top - k * a.sdz;
-            rz += naz - az;
-            az = naz;
+            if (k + 1 >= a.snz) break;
+            // warm start: the next height starts from its anchor plus the relaxed
+            // displacement extrapolated linearly from this height and the
+            // previous one (just the displacement after the first height);
+            // v and alpha restart, dt carries over (not below dt0)
+            const double ux = rx - ax, uy = ry - ay, uz = rz - az;
+            const bool lin = k >= 1;
+            const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
+                         ez = lin ? uz - u1z : 0.0;
+            u1x = ux;
+            u1y = uy;
+            u1z = uz;
+            ++k;
+            az = a.z_top - k * a.sdz;
+            rx = ax + (ux + ex);
+            ry = ay + (uy + ey);
+            rz = az + (uz + ez);
             vx = vy = vz = 0.0;
-            dt = a.dt0;
+            dt = fmax(dt, a.dt0);
             alpha = a.alpha0;
             npos = 0;
             it = 0;

@@ -75,15 +75,20 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
             const double x = ax + dx, y = ay + dy, z = az + dz;
             // cell
             const double ux = (x - a.ox) * a.ihx, uy = (y - a.oy) * a.ihy, uz = (z - a.oz) * a.ihz;
-            const double fx = floor(ux), fy = floor(uy);
-            const double tx = ux - fx, ty = uy - fy;
-            const int cx = wrap_index(fx, a.gnx, a.ignx), cy = wrap_index(fy, a.gny, a.igny);
-            double fz = floor(uz), tz;
-            bool zin = true;
-            if (!(fz >= 0.0)) { fz = 0.0; tz = 0.0; zin = false; }
-            else if (fz > (double)(a.gnz - 2)) { fz = (double)(a.gnz - 2); tz = 1.0; zin = false; }
-            else tz = uz - fz;
-            const int cz = (int)fz;
+            double tx, ty, tz;
+            bool xin = true, yin = true, zin;
+            int cx, cy;
+            if (a.periodic) {
+                const double fx = floor(ux), fy = floor(uy);
+                tx = ux - fx;
+                ty = uy - fy;
+                cx = wrap_index(fx, a.gnx, a.ignx);
+                cy = wrap_index(fy, a.gny, a.igny);
+            } else {
+                cx = clamp_cell(ux, a.gnx, tx, xin);
+                cy = clamp_cell(uy, a.gny, ty, yin);
+            }
+            const int cz = clamp_cell(uz, a.gnz, tz, zin);
             const int cx1 = (cx + 1 < a.gnx) ? cx + 1 : 0, cy1 = (cy + 1 < a.gny) ? cy + 1 : 0;
             const size_t pl = (size_t)a.gnx * a.gny;
             const size_t b0 = (size_t)cz * pl, b1 = b0 + pl;
@@ -97,16 +102,17 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
             const float4 v111 = ff[b1 + (size_t)cy1 * a.gnx + cx1];
             const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
             // d/dx, d/dy, d/dz of the trilinear weights (per unit length)
+            const double ihx = xin ? a.ihx : 0.0, ihy = yin ? a.ihy : 0.0;
             const double ihz = zin ? a.ihz : 0.0;
             double J[9];
 #define PPM_JROW(C, r)                                                                          \
     {                                                                                           \
         const double e00 = (double)v100.C - v000.C, e10 = (double)v110.C - v010.C;             \
         const double e01 = (double)v101.C - v001.C, e11 = (double)v111.C - v011.C;             \
-        J[3 * r + 0] = a.ihx * (sy * sz * e00 + ty * sz * e10 + sy * tz * e01 + ty * tz * e11); \
+        J[3 * r + 0] = ihx * (sy * sz * e00 + ty * sz * e10 + sy * tz * e01 + ty * tz * e11);   \
         const double f00 = (double)v010.C - v000.C, f10 = (double)v110.C - v100.C;             \
         const double f01 = (double)v011.C - v001.C, f11 = (double)v111.C - v101.C;             \
-        J[3 * r + 1] = a.ihy * (sx * sz * f00 + tx * sz * f10 + sx * tz * f01 + tx * tz * f11); \
+        J[3 * r + 1] = ihy * (sx * sz * f00 + tx * sz * f10 + sx * tz * f01 + tx * tz * f11);   \
         const double g00 = (double)v001.C - v000.C, g10 = (double)v101.C - v100.C;             \
         const double g01 = (double)v011.C - v010.C, g11 = (double)v111.C - v110.C;             \
         J[3 * r + 2] = ihz * (sx * sy * g00 + tx * sy * g10 + sx * ty * g01 + tx * ty * g11);   \

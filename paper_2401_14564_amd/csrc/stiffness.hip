@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void lateral_stiffness_kernel(const ScanArgs a
     gather8<WIDE>(ff, c, v);
     const double tx = c.tx, ty = c.ty, tz = c.tz;
     const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
+    const double ihx = c.xin ? a.ihx : 0.0, ihy = c.yin ? a.ihy : 0.0;
     const double ihz = c.zin ? a.ihz : 0.0;
     // trilinear Jacobian J[r][s] = dF_r / d x_s
     double J[3][3];
@@ -70,8 +71,8 @@ __global__ __launch_bounds__(256) void lateral_stiffness_kernel(const ScanArgs a
             gy += wxz[e] * db;
             gz += wxy[e] * dc;
         }
-        J[r][0] = gx * a.ihx;
-        J[r][1] = gy * a.ihy;
+        J[r][0] = gx * ihx;
+        J[r][1] = gy * ihy;
         J[r][2] = gz * ihz;
     }
     // spring Jacobian dF^T/dr = -k_R [(1 - R0/|d|) I + R0 d d^T/|d|^3] - diag(kx, ky, 0)

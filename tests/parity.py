@@ -27,6 +27,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from paper_2401_14564_amd import workloads as W
+
 import oracle as orc
 
 FF_RTOL = 1e-5
@@ -128,3 +130,25 @@ def grade_scan(grid, ff64, probe, fire, scan, cols, ores, gpu_pp, gpu_fz, gpu_df
         out.update(df_graded=int(win.sum()), df_total=int(win.size),
                    worst_ddf=float(d[win].max()) if win.any() else 0.0)
     return out
+
+
+def edge_workload(periodic):
+    """Tips over and beyond both x and y edges of the cell (columns from 0.63 A
+    before the first voxel to past the last one), probe heights 6 to 3.6 A above
+    ten atoms spread over the cell.  Open sample: 9.6 x 9.0 A, charged atoms,
+    clamped interpolation.  Periodic sample: 15 x 14 A with a 6.5 A minimum-image
+    cutoff and neutral atoms (a truncated Coulomb term would put steps of
+    ~0.05 eV into the energy at the cutoff sphere; the LJ step there is
+    ~3e-4 eV), wrapped interpolation."""
+    rng = np.random.default_rng(31 + periodic)
+    h = 0.1
+    n = (150, 140, 90) if periodic else (96, 90, 90)
+    L = np.array(n[:2]) * h
+    atoms = W.random_atoms(rng, 10, [0.3, 0.3, -0.3], [L[0] - 0.3, L[1] - 0.3, 0.3])
+    if periodic:
+        atoms.q[:] = 0.0
+    grid = W.Grid((0.0, 0.0, -1.0), (h, h, h), n, periodic, 6.5 if periodic else 0.0)
+    dx, dy = ((0.31, 0.30) if periodic else (0.2, 0.2))
+    scan = W.Scan(-0.63, -0.52, dx, dy, 52, 50, 10.03, 0.1, 25)
+    return W.Workload(f"edges periodic={periodic}", atoms, grid, W.Probe(), W.Fire(), scan,
+                      W.DfParams())

@@ -7,7 +7,7 @@ import torch
 import oracle as orc
 import paper_2401_14564_amd as ppm
 from paper_2401_14564_amd import workloads as W
-from parity import DF_TOL, check_ff, grade_scan
+from parity import DF_TOL, check_ff, edge_workload, grade_scan
 
 pytestmark = pytest.mark.gpu
 
@@ -170,6 +170,32 @@ def test_scan_below_and_above_grid_clamps():
     ff64, ores, g = _scan_both(w, fire)
     grade_scan(grid, ff64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
                label="clamp")
+
+
+@pytest.mark.parametrize("periodic", [0, 1], ids=["open", "periodic"])
+def test_scan_across_xy_edges(periodic):
+    """Tips over and beyond both x and y edges of a small grid.  An open grid is
+    clamped in x and y (the field is continued constantly past its edge
+    voxels); a periodic one wraps.  Trilinear and tricubic scans against the
+    oracle on every column."""
+    w = edge_workload(periodic)
+    grid, scan = w.grid, w.scan
+    fire = W.parity_fire(w.fire)
+    ff64, ores, g = _scan_both(w, fire)
+    info = grade_scan(grid, ff64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+                      label=f"edges periodic={periodic}")
+    print("edges", periodic, info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]
+    E32 = ff64[..., 3].astype(np.float32)
+    E64 = E32.astype(np.float64)
+    res = ppm.relaxed_scan_tricubic(grid, torch.as_tensor(E32, device="cuda"), w.probe, fire, scan)
+    gt = {k: v.cpu().numpy() for k, v in res.items()}
+    otr = orc.relaxed_scan_tricubic(grid, E64, w.probe, fire, scan, polish_tol=1e-12,
+                                    with_lambda=True)
+    info = grade_scan(grid, E64, w.probe, fire, scan, otr["cols"], otr, gt["pp"], gt["fz"],
+                      label=f"tricubic edges periodic={periodic}", residual=orc.residual_tricubic)
+    print("tricubic edges", periodic, info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]
 
 
 # ------------------------------------------------------------------ frequency shift

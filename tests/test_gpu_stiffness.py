@@ -8,7 +8,7 @@ import torch
 import oracle as orc
 import paper_2401_14564_amd as ppm
 from paper_2401_14564_amd import workloads as W
-from parity import LAM_GRADED, POS_TOL, anchors_for
+from parity import LAM_GRADED, POS_TOL, anchors_for, edge_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,17 @@ def test_stiffness_zero_field_is_lateral_springs():
 
 
 def test_stiffness_parity_c0():
-    w = W.config0()
+    _stiffness_parity(W.config0(), "C0")
+
+
+@pytest.mark.parametrize("periodic", [0, 1], ids=["open", "periodic"])
+def test_stiffness_across_xy_edges(periodic):
+    """Tips over and beyond the x and y edges of a small grid: clamped (open
+    grid) or wrapped (periodic grid) Jacobians on both sides."""
+    _stiffness_parity(edge_workload(periodic), f"edges periodic={periodic}")
+
+
+def _stiffness_parity(w, label):
     fire = W.parity_fire(w.fire)
     ref = orc.build_ff(w.grid, w.probe, w.atoms)
     ff32 = ref.astype(np.float32)
@@ -53,5 +63,5 @@ def test_stiffness_parity_c0():
     tol = 1e-4 + 1e-3 * np.abs(ko)
     assert ok.mean() > 0.9
     assert np.all(d[ok] <= tol[ok]), f"{np.sum(d[ok] > tol[ok])} off, worst {d[ok].max():.3e}"
-    print("stiffness graded", int(ok.sum()), "of", ok.size, "worst", float(d[ok].max()),
+    print("stiffness", label, "graded", int(ok.sum()), "of", ok.size, "worst", float(d[ok].max()),
           flush=True)

@@ -176,24 +176,39 @@ def test_trilinear_exact_for_affine_fields():
 
 
 def test_interp_wrap_clamp_and_nodes():
-    """Interpolation returns voxel values at voxels, is periodic in x,y with
-    period n*step, and is constant in z outside the grid."""
+    """Interpolation returns voxel values at voxels; on a periodic grid it is
+    periodic in x,y with period n*step; on an open grid it is constant in x,y
+    beyond the edge voxels; in z it is always constant outside the grid.  A
+    clamped axis contributes nothing to the Jacobian."""
     rng = np.random.default_rng(4)
     n = (5, 4, 6)
-    g = _grid(origin=(0, 0, 0), n=n)
     ff = rng.normal(size=(6, 4, 5, 4))
-    for (ix, iy, iz) in [(0, 0, 0), (4, 3, 5), (2, 1, 3)]:
-        F = orc.interp(ff, g, [ix * 0.1, iy * 0.1, iz * 0.1])
-        np.testing.assert_allclose(F, ff[iz, iy, ix, :3], rtol=1e-14, atol=1e-14)
+    for periodic in (0, 1):
+        g = _grid(origin=(0, 0, 0), n=n, periodic=periodic, cutoff=0.1)
+        for (ix, iy, iz) in [(0, 0, 0), (4, 3, 5), (2, 1, 3)]:
+            F = orc.interp(ff, g, [ix * 0.1, iy * 0.1, iz * 0.1])
+            np.testing.assert_allclose(F, ff[iz, iy, ix, :3], rtol=1e-14, atol=1e-14)
+        below = orc.interp(ff, g, [0.123, 0.257, -0.7])
+        at0 = orc.interp(ff, g, [0.123, 0.257, 0.0])
+        np.testing.assert_allclose(below, at0, atol=1e-14)
+        _, J = orc.interp(ff, g, [0.123, 0.257, 0.9], with_jac=True)
+        assert np.all(J[:, 2] == 0.0)
+    g = _grid(origin=(0, 0, 0), n=n, periodic=1, cutoff=0.1)
     r = np.array([0.123, 0.257, 0.31])
     F0 = orc.interp(ff, g, r)
     np.testing.assert_allclose(orc.interp(ff, g, r + [0.5, 0.0, 0.0]), F0, atol=1e-14)
     np.testing.assert_allclose(orc.interp(ff, g, r + [0.0, -0.4, 0.0]), F0, atol=1e-14)
-    below = orc.interp(ff, g, [0.123, 0.257, -0.7])
-    at0 = orc.interp(ff, g, [0.123, 0.257, 0.0])
-    np.testing.assert_allclose(below, at0, atol=1e-14)
-    _, J = orc.interp(ff, g, [0.123, 0.257, 0.9], with_jac=True)
-    assert np.all(J[:, 2] == 0.0)
+    # the periodic cell between the last and the first voxel interpolates them
+    F = orc.interp(ff, g, [0.45, 0.1, 0.2])
+    np.testing.assert_allclose(F, 0.5 * (ff[2, 1, 4, :3] + ff[2, 1, 0, :3]), atol=1e-14)
+    g = _grid(origin=(0, 0, 0), n=n, periodic=0)      # x in [0, 0.4], y in [0, 0.3]
+    for out_pt, edge_pt, axis in (((-0.3, 0.1, 0.2), (0.0, 0.1, 0.2), 0),
+                                  ((0.7, 0.1, 0.2), (0.4, 0.1, 0.2), 0),
+                                  ((0.2, -0.25, 0.2), (0.2, 0.0, 0.2), 1),
+                                  ((0.2, 0.5, 0.2), (0.2, 0.3, 0.2), 1)):
+        out, J = orc.interp(ff, g, out_pt, with_jac=True)
+        np.testing.assert_allclose(out, orc.interp(ff, g, edge_pt), atol=1e-14)
+        assert np.all(J[:, axis] == 0.0)
 
 
 # ---------------------------------------------------------------- tip springs

@@ -57,7 +57,7 @@ def test_node_values_and_gradient_by_differences():
         assert E == pytest.approx(En[iz, iy, ix], abs=1e-13)
     h = 1e-6
     for _ in range(20):
-        r = rng.uniform([0, 0, 0.15], [0.85, 0.75, 0.5])
+        r = rng.uniform([0.01, 0.01, 0.15], [0.79, 0.69, 0.5])    # inside the open grid
         _, F = orc.interp_tricubic(En, g, r)
         fd = np.array([-(orc.interp_tricubic(En, g, r + h * e)[0] -
                          orc.interp_tricubic(En, g, r - h * e)[0]) / (2 * h) for e in np.eye(3)])
@@ -132,3 +132,35 @@ def test_relaxation_on_quadratic_potential_matches_newton():
                     - np.diag(kk)
                 r = r - np.linalg.solve(Jt - S, G)
             np.testing.assert_allclose(res["r"][c, k], r, atol=1e-10)
+
+
+def test_open_grid_continues_the_force_beyond_its_edges():
+    """On a grid without periodic images the point is clamped to the grid box in
+    x and y (as in z): beyond the first and last voxel the force is the one at
+    the clamped point, so it is continuous across the edge, and it does not
+    change along the clamped axis (that column of -dF/dr is zero).  On a
+    periodic grid the interpolant repeats with period n*step instead."""
+    rng = np.random.default_rng(9)
+    g = _grid((0.0, 0.0, 0.0), (0.1, 0.12, 0.1), (9, 8, 10))
+    En = rng.normal(size=(10, 8, 9))
+    for out_pt, edge_pt, axis in (((-0.35, 0.4, 0.5), (0.0, 0.4, 0.5), 0),
+                                  ((1.3, 0.4, 0.5), (0.8, 0.4, 0.5), 0),
+                                  ((0.41, -0.2, 0.5), (0.41, 0.0, 0.5), 1),
+                                  ((0.41, 1.1, 0.5), (0.41, 0.84, 0.5), 1)):
+        E, F, H = orc.interp_tricubic(En, g, out_pt, with_hessian=True)
+        E0, F0, H0 = orc.interp_tricubic(En, g, edge_pt, with_hessian=True)
+        assert E == pytest.approx(E0, abs=1e-13)
+        np.testing.assert_allclose(F, F0, atol=1e-12)
+        assert np.all(H[:, axis] == 0.0)
+        other = [b for b in range(3) if b != axis]
+        np.testing.assert_allclose(H[:, other], H0[:, other], atol=1e-10)
+        # just inside the edge the force is the same to first order
+        inside = np.array(edge_pt, dtype=float)
+        inside[axis] += -1e-7 if out_pt[axis] > edge_pt[axis] else 1e-7
+        np.testing.assert_allclose(orc.interp_tricubic(En, g, inside)[1], F0, atol=1e-4)
+    gp = W.Grid((0.0, 0.0, 0.0), (0.1, 0.12, 0.1), (9, 8, 10), 1, 0.3)
+    r = np.array([0.23, 0.31, 0.47])
+    a = orc.interp_tricubic(En, gp, r)
+    b = orc.interp_tricubic(En, gp, r + np.array([0.9, -0.96, 0.0]))
+    assert a[0] == pytest.approx(b[0], abs=1e-12)
+    np.testing.assert_allclose(a[1], b[1], atol=1e-11)
