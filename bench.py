@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extr
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -181,56 +182,60 @@ def main():
     atoms = ppm.atoms_to_device(w.atoms)
     nx, ny, nz = w.grid.n
     m = ppm.df_half_width(w.df.A, w.scan.dz)
-    # With --pipeline, two buffers let the force field of step i+1 be built
-    # (stream s_ff) while step i is still scanning (stream s_scan); by default
-    # both stages run in order on one stream.
+    # Two buffers let the force field of step i+1 be built (stream s_ff) while
+    # step i is still scanning (stream s_scan) when pipelined; otherwise both
+    # stages run in order on one stream.
     ffs = [torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev) for _ in range(2)]
     outs = [dict(fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32,
                                 device=dev),
                  df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
                                 device=dev)) for _ in range(2)]
-    if a.pipeline:
-        s_ff, s_scan = torch.cuda.Stream(), torch.cuda.Stream()
-    else:
-        s_ff = s_scan = torch.cuda.current_stream()
-    ff_done = [torch.cuda.Event() for _ in range(2)]
-    scan_done = [torch.cuda.Event() for _ in range(2)]
-    for e in scan_done:
-        e.record(s_scan)
 
-    def step(i, ev=None):
-        b = i % 2
-        with torch.cuda.stream(s_ff):
-            s_ff.wait_event(scan_done[b])          # buffer b is free again
-            if ev is not None:
-                ev[0].record(s_ff)
-            ppm.build_ff(w.grid, w.probe, atoms, out=ffs[b])
-            if ev is not None:
-                ev[1].record(s_ff)
-            ff_done[b].record(s_ff)
-        with torch.cuda.stream(s_scan):
-            s_scan.wait_event(ff_done[b])
-            if ev is not None:
-                ev[2].record(s_scan)
-            ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=False,
-                             pp=False, out=outs[b])
-            if ev is not None:
-                ev[3].record(s_scan)
-            scan_done[b].record(s_scan)
+    def run_steps(pipeline, steps, warmup):
+        if pipeline:
+            s_ff, s_scan = torch.cuda.Stream(), torch.cuda.Stream()
+        else:
+            s_ff = s_scan = torch.cuda.current_stream()
+        ff_done = [torch.cuda.Event() for _ in range(2)]
+        scan_done = [torch.cuda.Event() for _ in range(2)]
+        for e in scan_done:
+            e.record(s_scan)
 
-    for i in range(a.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        step(i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / a.steps
-    ff_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    scan_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+        def step(i, ev=None):
+            b = i % 2
+            with torch.cuda.stream(s_ff):
+                s_ff.wait_event(scan_done[b])          # buffer b is free again
+                if ev is not None:
+                    ev[0].record(s_ff)
+                ppm.build_ff(w.grid, w.probe, atoms, out=ffs[b])
+                if ev is not None:
+                    ev[1].record(s_ff)
+                ff_done[b].record(s_ff)
+            with torch.cuda.stream(s_scan):
+                s_scan.wait_event(ff_done[b])
+                if ev is not None:
+                    ev[2].record(s_scan)
+                ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+                                 pp=False, out=outs[b])
+                if ev is not None:
+                    ev[3].record(s_scan)
+                scan_done[b].record(s_scan)
+
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i, evs[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return ((t1 - t0) * 1e3 / steps,
+                float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                float(np.mean([e[2].elapsed_time(e[3]) for e in evs])))
+
+    ms_per_step, ff_ms, scan_ms = run_steps(a.pipeline, a.steps, a.warmup)
     ff = ffs[0]
 
     # FIRE evaluations per launch (deterministic: same inputs, same iterations)
@@ -239,6 +244,11 @@ def main():
     n_eq = w.scan.n_eq
     evals = float(iters.abs().sum().item()) + n_eq
     nonconv = int((iters < 0).sum().item())
+    # critical path: the scan runs 16 x 16-column blocks of four 64-lane waves
+    # (4 rows of 16 columns each); a wave lasts as long as its slowest column
+    per_col = (iters.abs().sum(0) + w.scan.nz).cpu().numpy()          # [ny, nx]
+    wave_max = max(float(per_col[y0:y0 + 4, x0:x0 + 16].max())
+                   for y0 in range(0, w.scan.ny, 4) for x0 in range(0, w.scan.nx, 16))
     scan_bytes = evals * BYTES_PER_EVAL + n_eq * 4 + (w.scan.nz - 2 * m) * w.scan.nx * w.scan.ny * 4
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
     pairs = w.grid.nvox * w.atoms.n
@@ -285,11 +295,23 @@ def main():
                              "fire_evals_per_relaxation": round(evals / n_eq, 3),
                              "mean_fire_steps": round(float(iters.abs().mean().item()), 3),
                              "not_converged": nonconv,
-                             "algorithmic_bytes": int(scan_bytes)},
+                             "algorithmic_bytes": int(scan_bytes),
+                             "slowest_wave_evals": int(wave_max),
+                             "mean_wave_evals": round(evals / (w.scan.nx * w.scan.ny) , 1),
+                             "us_per_eval_on_critical_path": round(scan_ms * 1e3 / wave_max, 4)},
         },
     }
 
     if not a.no_extra:
+        other = not a.pipeline
+        o_ms, o_ff, o_scan = run_steps(other, a.steps, a.warmup)
+        result["pipelined" if other else "sequential"] = {
+            "pipelining": ("step i+1's force-field build overlaps step i's scan on a second "
+                           "stream (double-buffered grid)") if other else
+                          "none: build then scan, in order, on one stream",
+            "ms_per_step": round(o_ms, 4),
+            "relaxations_per_s": round(n_eq / (o_ms * 1e-3), 1),
+            "ff_ms": round(o_ff, 4), "scan_ms": round(o_scan, 4)}
         result["backward"] = _bench_backward(ppm, W, torch)
         result["batched"] = _bench_batch(ppm, W, torch)
         result["large_periodic"] = _bench_large(ppm, W, torch)
@@ -352,7 +374,6 @@ def _bench_batch(ppm, W, torch, n_mol=256):
     stiffnesses: one captured HIP graph (batched force-field launch + batched
     scan launch) against a plain per-molecule loop of build_ff + 3 scans on one
     stream (no per-molecule synchronisation)."""
-    import dataclasses
     dev = torch.device("cuda:0")
     ws = W.config3(n_mol)
     mols = [(w.atoms, w.grid) for w in ws]
@@ -503,6 +524,11 @@ def _bench_large(ppm, W, torch):
             "scan_gather_gbs": round(scan_bytes / (scan_ms * 1e-3) / 1e9, 1)}
 
 
+FLOP_PER_PAIR_QUAD = 47       # 31 of the point-charge probe + d_z2 term: dz^2 1, kQ/rho^5 3,
+                              # E 4, force factor 5, Fz 3
+# per grid point of the FFT route: 9 axis passes (read + write 16 B), pack (8 + 16), spectral
+# (16 read + 32 written), unpack with accumulation (32 + 16 + 16), max reduction (8)
+HARTREE_BYTES_PER_POINT = 9 * 32 + 24 + 48 + 64 + 8
 FLOP_PER_PAIR_ENERGY = 20     # energy only: d 3, r^2 5, rsq 1, 1/r^2 1, s^2 1, s^6 2,
                               # s^12 1, E_LJ 3, E_C 1, E sum 2
 
@@ -536,7 +562,48 @@ def _bench_next_rows(ppm, W, torch):
     pairs = w.grid.nvox * w.atoms.n
     k_ms, e_ms, s_ms = (float(np.median(x[1:])) for x in (tk, te, ts))
     it = tri["pp"][..., 3]
+    # quadrupolar probe (d_z2, -0.05 e A^2, no monopole): the point-charge force field
+    qprobe = dataclasses.replace(w.probe, q_pp=0.0, q_zz=-0.05)
+    ffq = ppm.build_ff(w.grid, qprobe, atoms)
+    # grid electrostatics: LJ-only grid + FFT cross-correlation with the tip density
+    V = torch.as_tensor(W.hartree_potential(w.atoms, w.grid).astype(np.float32), device="cuda")
+    rho = ppm.tip_density(w.grid, 0.0, -0.05, W.TIP_SIGMA)
+    ws = ppm.hartree_workspace(w.grid)
+    lj_probe = dataclasses.replace(w.probe, q_pp=0.0, q_zz=0.0)
+    ffh = ppm.build_ff(w.grid, lj_probe, atoms)
+    ppm.hartree_ff(w.grid, V, rho, out=ffh, accumulate=True, workspace=ws)
+    hres = ppm.relaxed_scan(w.grid, ffh, lj_probe, w.fire, w.scan, dfp=w.df, pp=False)
+    tq, tl, th, tsc = [], [], [], []
+    for _ in range(4):
+        e[0].record()
+        ppm.build_ff(w.grid, qprobe, atoms, out=ffq)
+        e[1].record()
+        ppm.build_ff(w.grid, lj_probe, atoms, out=ffh)
+        e[2].record()
+        ppm.hartree_ff(w.grid, V, rho, out=ffh, accumulate=True, workspace=ws)
+        e[3].record()
+        ppm.relaxed_scan(w.grid, ffh, lj_probe, w.fire, w.scan, dfp=w.df, pp=False, out=hres)
+        e[4].record()
+        torch.cuda.synchronize()
+        tq.append(e[0].elapsed_time(e[1]))
+        tl.append(e[1].elapsed_time(e[2]))
+        th.append(e[2].elapsed_time(e[3]))
+        tsc.append(e[3].elapsed_time(e[4]))
+    q_ms, l_ms, h_ms, hs_ms = (float(np.median(x[1:])) for x in (tq, tl, th, tsc))
+    nvox = w.grid.nvox
     return {"workload": "paper-scale (60 atoms, 240^3 grid, 240x240x100 scan)",
+            "quadrupole_probe": {"ff_ms": round(q_ms, 3),
+                                 "ff_tflops": round(pairs * FLOP_PER_PAIR_QUAD /
+                                                    (q_ms * 1e-3) / 1e12, 2)},
+            "hartree": {"note": "LJ grid + FFT cross-correlation of the d_z2 tip density "
+                                "(-0.05 e A^2, sigma 0.7 A) with a synthetic periodic potential",
+                        "lj_ff_ms": round(l_ms, 3),
+                        "hartree_ms": round(h_ms, 3),
+                        "hartree_algorithmic_gb": round(nvox * HARTREE_BYTES_PER_POINT / 1e9, 3),
+                        "hartree_gbs": round(nvox * HARTREE_BYTES_PER_POINT / (h_ms * 1e-3) / 1e9,
+                                             1),
+                        "scan_ms": round(hs_ms, 3),
+                        "relaxations_per_s": round(n_eq / ((l_ms + h_ms + hs_ms) * 1e-3), 1)},
             "lateral_stiffness": {"ms": round(k_ms, 3),
                                   "points_per_s": round(n_eq / (k_ms * 1e-3), 1),
                                   "gather_gbs": round(n_eq * (BYTES_PER_EVAL + 16 + 8) /
