@@ -92,7 +92,7 @@ class Probe:
 @dataclass
 class Fire:
     dt0: float = 0.1
-    dt_max: float = 0.5
+    dt_max: float = 1.0                  # 10 dt0, the ratio Bitzek et al. recommend
     f_inc: float = 1.1
     f_dec: float = 0.5
     alpha0: float = 0.1
