@@ -34,19 +34,12 @@ namespace {
 constexpr int kTX = 8, kTY = 8;
 
 // Trilinear interpolation of (Fx, Fy, Fz) in FP64 from FP32 corner values.
-template <bool WIDE>
-__device__ __forceinline__ void interp(const float4 *__restrict__ ff, const Cell &c,
-                                       double &Fx, double &Fy, double &Fz)
+// Trilinear combination of the eight corner values v[i + 2j + 4k] (gather8).
+__device__ __forceinline__ void trilerp(const float3 *v, const Cell &c, double &Fx, double &Fy,
+                                        double &Fz)
 {
-    const uint32_t i0 = c.i000;
-    const float3 v000 = corner<WIDE>(ff, i0);
-    const float3 v100 = corner<WIDE>(ff, i0 + c.dx1);
-    const float3 v010 = corner<WIDE>(ff, i0 + c.dy1);
-    const float3 v110 = corner<WIDE>(ff, i0 + c.dx1 + c.dy1);
-    const float3 v001 = corner<WIDE>(ff, i0 + c.dz1);
-    const float3 v101 = corner<WIDE>(ff, i0 + c.dz1 + c.dx1);
-    const float3 v011 = corner<WIDE>(ff, i0 + c.dz1 + c.dy1);
-    const float3 v111 = corner<WIDE>(ff, i0 + c.dz1 + c.dx1 + c.dy1);
+    const float3 v000 = v[0], v100 = v[1], v010 = v[2], v110 = v[3];
+    const float3 v001 = v[4], v101 = v[5], v011 = v[6], v111 = v[7];
     const double tx = c.tx, ty = c.ty, tz = c.tz;
     const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
     const double w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
@@ -197,12 +190,19 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     while (true) {
         double Sx, Sy, Sz, Tx, Ty, Tz;
         if (INTERP == 0) {
+            // issue the eight gathers, then evaluate the springs (independent of
+            // them) while they are in flight, then interpolate
             const Cell c = locate(a, rx, ry, rz);
-            interp<WIDE>(ff, c, Sx, Sy, Sz);
+            float3 v[8];
+            gather8<WIDE>(ff, c, v);
+            __builtin_amdgcn_sched_barrier(0);   // keep the spring math ahead of the waits
+            tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
+            __builtin_amdgcn_sched_barrier(0);
+            trilerp(v, c, Sx, Sy, Sz);
         } else {
             tricubic_force(a, En, rx, ry, rz, Sx, Sy, Sz);
+            tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
         }
-        tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
         const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
         const double g2 = Gx * Gx + Gy * Gy + Gz * Gz;
         const bool conv = g2 < a.f_conv2;
@@ -248,7 +248,9 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             const bool pos = (it > 0) && (P > 0.0);
             const bool neg = (it > 0) && !(P > 0.0);
             const double vn2 = vx * vx + vy * vy + vz * vz;
-            const double mix = alpha * vn2 * rsqrt_d(vn2 * g2);   // alpha |v| / |G|
+            // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
+            // 1/sqrt (no Newton step) is accurate enough
+            const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
             const double sc = pos ? mix : 0.0;
             const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
             vx = om * vx + sc * Gx;
