@@ -526,9 +526,10 @@ def _bench_large(ppm, W, torch):
 
 FLOP_PER_PAIR_QUAD = 47       # 31 of the point-charge probe + d_z2 term: dz^2 1, kQ/rho^5 3,
                               # E 4, force factor 5, Fz 3
-# per grid point of the FFT route: 9 axis passes (read + write 16 B), pack (8 + 16), spectral
-# (16 read + 32 written), unpack with accumulation (32 + 16 + 16), max reduction (8)
-HARTREE_BYTES_PER_POINT = 9 * 32 + 24 + 48 + 64 + 8
+# per grid point of the FFT route: max reduction (8), first x pass reading V and rho (8 + 16),
+# seven axis passes (16 + 16), spectral product (16 read + 32 written), last z pass reading
+# Fx + i Fy and E + i Fz and adding to the grid (32 + 16 read + 16 written)
+HARTREE_BYTES_PER_POINT = 8 + 24 + 7 * 32 + 48 + 64
 FLOP_PER_PAIR_ENERGY = 20     # energy only: d 3, r^2 5, rsq 1, 1/r^2 1, s^2 1, s^6 2,
                               # s^12 1, E_LJ 3, E_C 1, E sum 2
 

@@ -13,16 +13,17 @@
 // Pipeline (all FP64 complex, the grid taken periodic in x, y and z):
 //   absmax    alpha = 2^(e_V - e_rho), e the binary exponents of max|V|, max|rho|
 //             (two deterministic reduction kernels; no atomics)
-//   pack      Z = V + i alpha rho                (two real fields, one transform;
-//             alpha puts both on one scale, so that splitting the transform into
-//             its Hermitian parts does not bury rho^ under the rounding of V^,
-//             and, being a power of two, changes no digit)
+//   pack      Z = V + i alpha rho, formed by the first x pass as it reads the two
+//             real fields (one transform for both; alpha puts them on one scale,
+//             so that splitting the transform into its Hermitian parts does not
+//             bury rho^ under the rounding of V^, and, being a power of two,
+//             changes no digit)
 //   3 x fft   Z^ (forward), one kernel per axis
 //   spectral  V^ = (Z^[k] + conj Z^[-k]) / 2,  rho^ = (Z^[k] - conj Z^[-k]) / (2i alpha),
 //             A = E^ + i F^_z = (1 + kappa_z) E^,  B = F^_x + i F^_y = (kappa_y - i kappa_x) E^,
 //             with 1/N folded into E^
-//   6 x fft   A, B (inverse)
-//   unpack    ff = (Re B, Im B, Im A, Re A), written or added to the grid
+//   6 x fft   A, B (inverse); the last z pass of B writes
+//             ff = (Re B, Im B, Im A, Re A) to the grid (or adds to it)
 //
 // FFT kernel: a block transforms L lines of one axis in LDS with a mixed-radix
 // (4, 2, 3, 5) Stockham sequence; each stage reads its inputs into registers,
@@ -38,7 +39,8 @@ namespace ppm {
 namespace {
 
 constexpr int kFftThreads = 512;
-constexpr int kFftLdsElems = 4096;       // 64 KiB of double2: data + twiddles
+constexpr int kFftLdsElems = 4096;       // at most 64 KiB of double2: data + twiddles
+constexpr int kFftMaxLines = 16;         // lines per block (runs of 16 x 16 B on y/z)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -88,24 +90,30 @@ __device__ __forceinline__ AxisMap axis_map(int axis, int nx, int ny, int nz, in
     return m;
 }
 
+// x / d for the small indices of the FFT (see FftPlan): rcp = 0 means d = 1.
+__device__ __forceinline__ int fdiv(int x, unsigned rcp)
+{
+    return rcp ? (int)__umulhi((unsigned)x, rcp) : x;
+}
+
 // One Stockham stage of radix P over L lines of length n held in LDS (line
-// stride LS).  m = product of the radices of the previous stages.
+// stride LS).  m = product of the radices of the previous stages; rcp_nb and
+// rcp_m the reciprocals of n/P and m.
 template <int P>
 __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n, int m, int L,
-                                          int LS, bool inverse)
+                                          int LS, bool inverse, unsigned rcp_nb, unsigned rcp_m)
 {
     constexpr int NB = (kFftLdsElems / P + kFftThreads - 1) / kFftThreads;
     const int nb = n / P;
     const int tot = L * nb;
     const int stride = n / (m * P);          // twiddle step of this stage
-    const int root = n / P;                  // table step of the radix-P roots
     double2 y[NB][P];
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
         const int b = threadIdx.x + r * kFftThreads;
         if (b < tot) {
-            const int l = b / nb, j = b - l * nb;
-            const int k = j % m;
+            const int l = fdiv(b, rcp_nb), j = b - l * nb;
+            const int k = j - fdiv(j, rcp_m) * m;
             double2 u[P];
 #pragma unroll
             for (int t = 0; t < P; ++t) {
@@ -124,15 +132,37 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
                 y[r][1] = cadd(b2, id);
                 y[r][2] = csub(a, c);
                 y[r][3] = csub(b2, id);
+            } else if (P == 3) {
+                // w = exp(-+2 pi i / 3): y1,2 = u0 - a/2 -+ i sqrt(3)/2 b
+                const double2 a = cadd(u[1], u[2]), d = csub(u[1], u[2]);
+                const double2 t = make_double2(u[0].x - 0.5 * a.x, u[0].y - 0.5 * a.y);
+                const double h = 0.86602540378443864676;                 // sqrt(3)/2
+                const double2 ib = inverse ? make_double2(-h * d.y, h * d.x)
+                                           : make_double2(h * d.y, -h * d.x);   // -+ i h d
+                y[r][0] = cadd(u[0], a);
+                y[r][1] = cadd(t, ib);
+                y[r][2] = csub(t, ib);
             } else {
-#pragma unroll
-                for (int t = 0; t < P; ++t) {
-                    double2 acc = u[0];
-#pragma unroll
-                    for (int s = 1; s < P; ++s)
-                        acc = cadd(acc, cmul(u[s], cconj_if(tw[((s * t) % P) * root], inverse)));
-                    y[r][t] = acc;
-                }
+                // radix 5 from the symmetric pairs u1 +- u4, u2 +- u3 and the
+                // cosines/sines of 2 pi/5 and 4 pi/5
+                const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+                const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+                const double2 a1 = cadd(u[1], u[4]), b1 = csub(u[1], u[4]);
+                const double2 a2 = cadd(u[2], u[3]), b2 = csub(u[2], u[3]);
+                const double2 t1 = make_double2(u[0].x + c1 * a1.x + c2 * a2.x,
+                                                u[0].y + c1 * a1.y + c2 * a2.y);
+                const double2 t2 = make_double2(u[0].x + c2 * a1.x + c1 * a2.x,
+                                                u[0].y + c2 * a1.y + c1 * a2.y);
+                const double2 t3 = make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+                const double2 t4 = make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+                // forward: y1 = t1 - i t3, y4 = t1 + i t3, y2 = t2 - i t4, y3 = t2 + i t4
+                const double2 i3 = inverse ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+                const double2 i4 = inverse ? make_double2(-t4.y, t4.x) : make_double2(t4.y, -t4.x);
+                y[r][0] = make_double2(u[0].x + a1.x + a2.x, u[0].y + a1.y + a2.y);
+                y[r][1] = cadd(t1, i3);
+                y[r][4] = csub(t1, i3);
+                y[r][2] = cadd(t2, i4);
+                y[r][3] = csub(t2, i4);
             }
         }
     }
@@ -141,9 +171,10 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
     for (int r = 0; r < NB; ++r) {
         const int b = threadIdx.x + r * kFftThreads;
         if (b < tot) {
-            const int l = b / nb, j = b - l * nb;
-            const int k = j % m;
-            const int o = l * LS + (j / m) * m * P + k;
+            const int l = fdiv(b, rcp_nb), j = b - l * nb;
+            const int q = fdiv(j, rcp_m);
+            const int k = j - q * m;
+            const int o = l * LS + q * m * P + k;
 #pragma unroll
             for (int t = 0; t < P; ++t) buf[o + t * m] = y[r][t];
         }
@@ -151,46 +182,91 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
     __syncthreads();
 }
 
-// Transform every line of one axis in place.
+// Inputs and outputs of the passes that absorb the packing and unpacking.
+struct FftIo {
+    const float *V, *rho;         // MODE 1: the real fields packed as V + i alpha rho
+    const double *alpha;
+    const double2 *A;             // MODE 2: finished E + i Fz, read beside Fx + i Fy
+    float4 *ff;                   // MODE 2: output grid
+    int accumulate;
+};
+
+// Transform every line of one axis in place.  MODE 0: data in, data out.
+// MODE 1 (first forward pass): the lines are read from V and rho instead of
+// data.  MODE 2 (last inverse pass of Fx + i Fy): instead of storing the lines,
+// (Fx, Fy, Fz, E) = (Re, Im of the line, Im, Re of A) is written or added to ff.
+template <int MODE>
 __global__ __launch_bounds__(kFftThreads) void fft_axis_kernel(double2 *__restrict__ data,
                                                                FftPlan plan, int axis, int nx,
-                                                               int ny, int nz, int inverse)
+                                                               int ny, int nz, int inverse,
+                                                               FftIo io)
 {
-    __shared__ double2 lds[kFftLdsElems];
+    extern __shared__ double2 lds[];        // n twiddles + L lines of stride n + 1
     const int n = plan.n, L = plan.lines, LS = n + 1;
     double2 *tw = lds;
     double2 *buf = lds + n;
+    const AxisMap am = axis_map(axis, nx, ny, nz, L);
+    // load: l fastest for strided axes (one contiguous run per element row);
+    // all of a thread's loads are issued before the first LDS store
+    constexpr int kPer = kFftLdsElems / kFftThreads;
+    double2 v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int e = threadIdx.x + r * kFftThreads;
+        int l, t;
+        if (axis == 0) { l = fdiv(e, plan.rcp_n); t = e - l * n; }
+        else { t = fdiv(e, plan.rcp_lines); l = e - t * L; }
+        v[r] = make_double2(0.0, 0.0);
+        if (e < L * n && l < am.nl) {
+            const long long g = am.base + l * am.lstride + (long long)t * am.tstride;
+            if (MODE == 1) v[r] = make_double2((double)io.V[g], io.alpha[0] * (double)io.rho[g]);
+            else v[r] = data[g];
+        }
+    }
+    // twiddles while the loads are in flight
     for (int t = threadIdx.x; t < n; t += kFftThreads) {
         double s, c;
         sincospi(-2.0 * t / n, &s, &c);
         tw[t] = make_double2(c, s);
     }
-    const AxisMap am = axis_map(axis, nx, ny, nz, L);
-    // load: l fastest for strided axes (one contiguous run per element row)
-    for (int e = threadIdx.x; e < L * n; e += kFftThreads) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int e = threadIdx.x + r * kFftThreads;
         int l, t;
-        if (axis == 0) { l = e / n; t = e - l * n; }
-        else { t = e / L; l = e - t * L; }
-        double2 v = make_double2(0.0, 0.0);
-        if (l < am.nl) v = data[am.base + l * am.lstride + (long long)t * am.tstride];
-        buf[l * LS + t] = v;
+        if (axis == 0) { l = fdiv(e, plan.rcp_n); t = e - l * n; }
+        else { t = fdiv(e, plan.rcp_lines); l = e - t * L; }
+        if (e < L * n) buf[l * LS + t] = v[r];
     }
     __syncthreads();
     int m = 1;
     const bool inv = inverse != 0;
     for (int s = 0; s < plan.n_stages; ++s) {
         const int P = plan.radix[s];
-        if (P == 4) fft_stage<4>(buf, tw, n, m, L, LS, inv);
-        else if (P == 2) fft_stage<2>(buf, tw, n, m, L, LS, inv);
-        else if (P == 3) fft_stage<3>(buf, tw, n, m, L, LS, inv);
-        else fft_stage<5>(buf, tw, n, m, L, LS, inv);
+        const unsigned rn = plan.rcp_nb[s], rm = plan.rcp_m[s];
+        if (P == 4) fft_stage<4>(buf, tw, n, m, L, LS, inv, rn, rm);
+        else if (P == 2) fft_stage<2>(buf, tw, n, m, L, LS, inv, rn, rm);
+        else if (P == 3) fft_stage<3>(buf, tw, n, m, L, LS, inv, rn, rm);
+        else fft_stage<5>(buf, tw, n, m, L, LS, inv, rn, rm);
         m *= P;
     }
     for (int e = threadIdx.x; e < L * n; e += kFftThreads) {
         int l, t;
-        if (axis == 0) { l = e / n; t = e - l * n; }
-        else { t = e / L; l = e - t * L; }
-        if (l < am.nl) data[am.base + l * am.lstride + (long long)t * am.tstride] = buf[l * LS + t];
+        if (axis == 0) { l = fdiv(e, plan.rcp_n); t = e - l * n; }
+        else { t = fdiv(e, plan.rcp_lines); l = e - t * L; }
+        if (l < am.nl) {
+            const long long g = am.base + l * am.lstride + (long long)t * am.tstride;
+            if (MODE == 2) {
+                const double2 a = io.A[g], b = buf[l * LS + t];
+                float4 o = make_float4((float)b.x, (float)b.y, (float)a.y, (float)a.x);
+                if (io.accumulate) {
+                    const float4 p = io.ff[g];
+                    o = make_float4(p.x + o.x, p.y + o.y, p.z + o.z, p.w + o.w);
+                }
+                io.ff[g] = o;
+            } else {
+                data[g] = buf[l * LS + t];
+            }
+        }
     }
 }
 
@@ -267,15 +343,6 @@ __global__ __launch_bounds__(256) void absmax_final_kernel(const float2 *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ V,
-                                                   const float *__restrict__ rho,
-                                                   const double *__restrict__ alpha,
-                                                   double2 *__restrict__ Z, long long N)
-{
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < N) Z[v] = make_double2((double)V[v], alpha[0] * (double)rho[v]);
-}
-
 __device__ __forceinline__ double wavenumber(int i, int n, double two_pi_over_L)
 {
     if (2 * i == n) return 0.0;
@@ -311,34 +378,29 @@ __global__ __launch_bounds__(256) void spectral_kernel(const double2 *__restrict
     B[v] = make_double2(ky * Eh.x + kx * Eh.y, ky * Eh.y - kx * Eh.x);
 }
 
-__global__ __launch_bounds__(256) void unpack_kernel(const double2 *__restrict__ A,
-                                                     const double2 *__restrict__ B,
-                                                     float4 *__restrict__ ff, long long N,
-                                                     int accumulate)
-{
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= N) return;
-    const double2 a = A[v], b = B[v];
-    float4 o = make_float4((float)b.x, (float)b.y, (float)a.y, (float)a.x);
-    if (accumulate) {
-        const float4 p = ff[v];
-        o = make_float4(p.x + o.x, p.y + o.y, p.z + o.z, p.w + o.w);
-    }
-    ff[v] = o;
-}
-
 unsigned blocks_for(long long N, int T) { return (unsigned)((N + T - 1) / T); }
 
+// 3-D transform: x, y, z passes.  first: MODE of the x pass (1 reads the real
+// inputs); last: MODE of the z pass (2 unpacks into the grid).
 hipError_t launch_fft3(double2 *data, const FftPlan plans[3], int nx, int ny, int nz, int inverse,
-                       hipStream_t stream)
+                       int first, int last, const FftIo &io, hipStream_t stream)
 {
     for (int axis = 0; axis < 3; ++axis) {
         const int L = plans[axis].lines;
         unsigned grid;
         if (axis == 0) grid = blocks_for((long long)ny * nz, L);
         else grid = (unsigned)((nx + L - 1) / L) * (unsigned)(axis == 1 ? nz : ny);
-        hipLaunchKernelGGL(fft_axis_kernel, dim3(grid), dim3(kFftThreads), 0, stream, data,
-                           plans[axis], axis, nx, ny, nz, inverse);
+        const size_t lds = (size_t)(plans[axis].n + L * (plans[axis].n + 1)) * sizeof(double2);
+        const int mode = axis == 0 ? first : (axis == 2 ? last : 0);
+        if (mode == 1)
+            hipLaunchKernelGGL((fft_axis_kernel<1>), dim3(grid), dim3(kFftThreads), lds, stream,
+                               data, plans[axis], axis, nx, ny, nz, inverse, io);
+        else if (mode == 2)
+            hipLaunchKernelGGL((fft_axis_kernel<2>), dim3(grid), dim3(kFftThreads), lds, stream,
+                               data, plans[axis], axis, nx, ny, nz, inverse, io);
+        else
+            hipLaunchKernelGGL((fft_axis_kernel<0>), dim3(grid), dim3(kFftThreads), lds, stream,
+                               data, plans[axis], axis, nx, ny, nz, inverse, io);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -363,11 +425,21 @@ bool fft_plan(int n, FftPlan *p)
         }
     }
     if (r != 1) return false;
+    // multiply-high reciprocals of n/P and of m for each stage
+    int m = 1;
+    for (int s = 0; s < p->n_stages; ++s) {
+        const unsigned nb = (unsigned)(n / p->radix[s]);
+        p->rcp_nb[s] = nb == 1 ? 0u : (unsigned)((1ull << 32) / nb + 1);
+        p->rcp_m[s] = m == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)m + 1);
+        m *= p->radix[s];
+    }
     // lines per block: data (L lines of stride n + 1) plus n twiddles in LDS
     int L = (kFftLdsElems - n) / (n + 1);
-    if (L > 16) L = 16;
+    if (L > kFftMaxLines) L = kFftMaxLines;
     if (L < 1) return false;
     p->lines = L;
+    p->rcp_n = (unsigned)((1ull << 32) / (unsigned)n + 1);               // n >= 2
+    p->rcp_lines = L == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)L + 1);
     return true;
 }
 
@@ -399,19 +471,17 @@ hipError_t launch_hartree(const FftPlan plans[3], int nx, int ny, int nz, double
                        partial);
     hipLaunchKernelGGL(absmax_final_kernel, dim3(1), dim3(256), 0, stream, partial, n_parts,
                        alpha);
-    hipLaunchKernelGGL(pack_kernel, dim3(g), dim3(256), 0, stream, V, rho, alpha, Z, N);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_fft3(Z, plans, nx, ny, nz, 0, stream)) != hipSuccess) return e;
+    FftIo io{V, rho, alpha, A, ff, accumulate};
+    if ((e = launch_fft3(Z, plans, nx, ny, nz, 0, 1, 0, io, stream)) != hipSuccess) return e;
     const double two_pi = 6.283185307179586476925286766559;
     const double scale = hx * hy * hz / (double)N;
     hipLaunchKernelGGL(spectral_kernel, dim3(g), dim3(256), 0, stream, Z, A, B, nx, ny, nz,
                        two_pi / (nx * hx), two_pi / (ny * hy), two_pi / (nz * hz), scale, alpha);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_fft3(A, plans, nx, ny, nz, 1, stream)) != hipSuccess) return e;
-    if ((e = launch_fft3(B, plans, nx, ny, nz, 1, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(unpack_kernel, dim3(g), dim3(256), 0, stream, A, B, ff, N, accumulate);
-    return hipGetLastError();
+    if ((e = launch_fft3(A, plans, nx, ny, nz, 1, 0, 0, io, stream)) != hipSuccess) return e;
+    return launch_fft3(B, plans, nx, ny, nz, 1, 0, 2, io, stream);
 }
 
 }  // namespace ppm

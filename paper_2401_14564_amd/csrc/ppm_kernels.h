@@ -143,12 +143,18 @@ hipError_t launch_df(const float *fz, int nz, int ny, int nx, int m, const DfWei
 constexpr int kMaxFftLength = 1024;      // points per axis
 constexpr int kMaxFftStages = 16;
 
-// Radix sequence of one axis and the number of lines a block transforms.
+// Radix sequence of one axis and the number of lines a block transforms.  For
+// each stage, the divisors the Stockham indexing needs (n/P and the product m of
+// the previous radices) as multiply-high reciprocals: x / d = umulhi(x, M) with
+// M = floor(2^32 / d) + 1, exact for x < 2^13 and d <= 2048 (0 marks d = 1).
 struct FftPlan {
     int n;
     int lines;
     int n_stages;
     int radix[kMaxFftStages];
+    unsigned rcp_nb[kMaxFftStages];
+    unsigned rcp_m[kMaxFftStages];
+    unsigned rcp_n, rcp_lines;     // of n and of lines (load/store index split)
 };
 
 // false if n is not 2^a 3^b 5^c with 2 <= n <= kMaxFftLength
