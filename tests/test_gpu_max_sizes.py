@@ -1,0 +1,94 @@
+"""Maximum sizes.  The largest force-field grid the ABI accepts (just under 2^31
+voxels, 34 GB) is built and checked voxel by voxel against the FP64 oracle; the
+scan's 64-bit corner addressing (grids of 4 GiB and more) is checked on an affine
+sample force, which trilinear interpolation reproduces exactly, so every relaxed
+position is the root of the analytic force balance (Eq. 1), found here by an
+independent Newton iteration."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import paper_2401_14564_amd as ppm
+from paper_2401_14564_amd import workloads as W
+from parity import check_ff
+
+pytestmark = pytest.mark.gpu
+
+
+def test_ff_build_on_the_largest_grid():
+    n = (2048, 1024, 1023)                      # 2,145,386,496 voxels < 2^31
+    grid = W.Grid((0.0, 0.0, -2.0), (0.1, 0.1, 0.1), n)
+    rng = np.random.default_rng(41)
+    atoms = W.random_atoms(rng, 3, [20.0, 20.0, 0.0], [180.0, 80.0, 1.0])
+    got = ppm.build_ff(grid, W.Probe(), atoms)
+    idx = np.stack([rng.integers(0, n[0], 600), rng.integers(0, n[1], 600),
+                    rng.integers(0, n[2], 600)], axis=1)
+    idx = np.concatenate([idx, [[0, 0, 0], [n[0] - 1, n[1] - 1, n[2] - 1], [n[0] - 1, 0, n[2] - 1],
+                                [0, n[1] - 1, 0]]]).astype(np.int32)
+    it = torch.as_tensor(idx, device=got.device, dtype=torch.long)
+    sel = got[it[:, 2], it[:, 1], it[:, 0]].cpu().numpy()
+    del got, it
+    torch.cuda.empty_cache()
+    ref, sc = orc.ff_voxels(grid, W.Probe(), atoms, idx)
+    info = check_ff(sel, ref, sc, "largest grid")
+    print("largest grid", info, flush=True)
+
+
+def _newton(anchor, probe, Amat, b, r0):
+    R0 = np.linalg.norm(probe.d0)
+    d0 = np.array(probe.d0)
+    k = np.array([probe.k_lat[0], probe.k_lat[1], 0.0])
+    r = np.array(r0, float)
+    for _ in range(60):
+        d = r - anchor
+        dn = np.linalg.norm(d)
+        G = -probe.k_rad * (dn - R0) * d / dn - k * (d - d0) + Amat @ r + b
+        Jt = -probe.k_rad * ((1 - R0 / dn) * np.eye(3) + R0 * np.outer(d, d) / dn ** 3) - np.diag(k)
+        r = r - np.linalg.solve(Jt + Amat, G)
+    return r
+
+
+def test_scan_on_a_grid_beyond_4_gib():
+    n = (1024, 512, 520)                        # 16 B x 272,629,760 voxels = 4.36 GB
+    h = 0.1
+    grid = W.Grid((0.0, 0.0, 0.0), (h, h, h), n)
+    rng = np.random.default_rng(42)
+    M = rng.normal(size=(3, 3)) * 0.004
+    Amat = -(M @ M.T) - 0.003 * np.eye(3) + (M - M.T) * 0.5     # stable, not symmetric
+    centre = np.array([80.0, 40.0, 30.0])
+    b = np.array([0.004, -0.003, 0.02]) - Amat @ centre
+    dev = torch.device("cuda")
+    ff = torch.empty((n[2], n[1], n[0], 4), dtype=torch.float32, device=dev)
+    x = torch.arange(n[0], dtype=torch.float64, device=dev) * h
+    y = torch.arange(n[1], dtype=torch.float64, device=dev) * h
+    z = torch.arange(n[2], dtype=torch.float64, device=dev) * h
+    for c in range(3):
+        ff[..., c] = (Amat[c, 0] * x[None, None, :] + Amat[c, 1] * y[None, :, None]
+                      + Amat[c, 2] * z[:, None, None] + b[c]).float()
+    ff[..., 3] = 0.0
+    probe = W.Probe()
+    fire = W.parity_fire(W.Fire())
+    scan = W.Scan(79.63, 39.71, 0.13, 0.17, 8, 8, 36.4, 0.1, 12)
+    res = ppm.relaxed_scan(grid, ff, probe, fire, scan)
+    pp = res["pp"].cpu().numpy()
+    fz = res["fz"].cpu().numpy()
+    del ff, res
+    torch.cuda.empty_cache()
+    assert np.all(pp[..., 3] >= 0)
+    worst = 0.0
+    for iy in range(scan.ny):
+        for ix in range(scan.nx):
+            for k in range(scan.nz):
+                anchor = np.array([scan.x0 + ix * scan.dx, scan.y0 + iy * scan.dy,
+                                   scan.z_top - k * scan.dz])
+                rN = _newton(anchor, probe, Amat, b, anchor + np.array(probe.d0))
+                rg = anchor + np.array(probe.d0) + pp[k, iy, ix, :3]
+                worst = max(worst, float(np.linalg.norm(rg - rN)))
+                # read-out: the radial spring's z force at the Newton equilibrium
+                d = rN - anchor
+                dn = np.linalg.norm(d)
+                fzN = probe.k_rad * (dn - np.linalg.norm(probe.d0)) * d[2] / dn
+                assert abs(fz[k, iy, ix] - fzN) <= 1e-5, (ix, iy, k)
+    assert worst <= 1e-4, worst
+    print("wide grid scan: worst |dr|", worst, flush=True)
