@@ -104,6 +104,10 @@ __device__ __forceinline__ int cubic_clamp_cell(double u, int n, double &t)
 // a 4x4x4 stencil contracted axis by axis in FP64.  x,y wrap on a periodic
 // grid; otherwise, and always for z, the point is clamped to the grid box:
 // outside [0, n-1] the force is continued constantly along that axis.
+// WIDE: the energy grid has 2^30 voxels or more (4 GiB), so the loads need
+// 64-bit offsets; otherwise each of the 64 loads is a 32-bit byte offset (row
+// offset + column offset, both computed once) from the scalar base address.
+template <bool WIDE>
 __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *__restrict__ En,
                                                double x, double y, double z, double &Fx,
                                                double &Fy, double &Fz)
@@ -140,14 +144,41 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
         ys[s] = j;
         zs[s] = k;
     }
+    // issue all 64 loads first, then contract (their latency overlaps)
+    float vals[64];
+    if (WIDE) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float *row = En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) vals[16 * c + 4 * b + i] = row[xs[i]];
+            }
+    } else {
+        const char *base = reinterpret_cast<const char *>(En);
+        uint32_t xo[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xo[i] = (uint32_t)xs[i] * 4u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t ro = (uint32_t)((zs[c] * a.gny + ys[b]) * a.gnx) * 4u;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    vals[16 * c + 4 * b + i] = *reinterpret_cast<const float *>(base + (ro + xo[i]));
+            }
+    }
+    __builtin_amdgcn_sched_barrier(0);
     double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const float *row = En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx;
-            const double v0 = row[xs[0]], v1 = row[xs[1]], v2 = row[xs[2]], v3 = row[xs[3]];
+            const double v0 = vals[16 * c + 4 * b], v1 = vals[16 * c + 4 * b + 1],
+                         v2 = vals[16 * c + 4 * b + 2], v3 = vals[16 * c + 4 * b + 3];
             const double r0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
             const double r1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
             s0 += wy[b] * r0;
@@ -200,7 +231,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             __builtin_amdgcn_sched_barrier(0);
             trilerp(v, c, Sx, Sy, Sz);
         } else {
-            tricubic_force(a, En, rx, ry, rz, Sx, Sy, Sz);
+            tricubic_force<WIDE>(a, En, rx, ry, rz, Sx, Sy, Sz);
             tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
         }
         const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
@@ -450,7 +481,11 @@ hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const floa
 hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w, const float *En,
                                         float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    launch_scan_mode<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
+    const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
+    if (bytes >= 4294967296.0)
+        launch_scan_mode<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
+    else
+        launch_scan_mode<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
     return hipGetLastError();
 }
 

@@ -1,9 +1,9 @@
 """Maximum sizes.  The largest force-field grid the ABI accepts (just under 2^31
 voxels, 34 GB) is built and checked voxel by voxel against the FP64 oracle; the
-scan's 64-bit corner addressing (grids of 4 GiB and more) is checked on an affine
-sample force, which trilinear interpolation reproduces exactly, so every relaxed
-position is the root of the analytic force balance (Eq. 1), found here by an
-independent Newton iteration."""
+scans' 64-bit addressing (grids of 4 GiB and more) is checked on an affine sample
+force (trilinear) and a quadratic potential (tricubic), which the interpolants
+reproduce exactly, so every relaxed position is the root of the analytic force
+balance (Eq. 1), found here by an independent Newton iteration."""
 import numpy as np
 import pytest
 import torch
@@ -92,3 +92,49 @@ def test_scan_on_a_grid_beyond_4_gib():
                 assert abs(fz[k, iy, ix] - fzN) <= 1e-5, (ix, iy, k)
     assert worst <= 1e-4, worst
     print("wide grid scan: worst |dr|", worst, flush=True)
+
+
+def test_tricubic_scan_on_an_energy_grid_beyond_4_gib():
+    """A quadratic potential E = (r-c).S(r-c)/2 + b.(r-c) is reproduced exactly by
+    the Catmull-Rom interpolant, so its force -S(r-c) - b is affine and the
+    relaxed positions are again the Newton roots; 2^30 voxels or more (4 GiB of
+    FP32) take the 64-bit load path."""
+    n = (1024, 1024, 1025)                      # 1,074,790,400 voxels > 2^30
+    h = 0.1
+    grid = W.Grid((0.0, 0.0, 0.0), (h, h, h), n)
+    rng = np.random.default_rng(43)
+    M = rng.normal(size=(3, 3)) * 0.004
+    S = M @ M.T + 0.003 * np.eye(3)                              # symmetric, positive
+    c = np.array([60.0, 50.0, 40.0])
+    bvec = np.array([-0.004, 0.003, -0.02])
+    dev = torch.device("cuda")
+    E = torch.empty((n[2], n[1], n[0]), dtype=torch.float32, device=dev)
+    dx = torch.arange(n[0], dtype=torch.float64, device=dev) * h - c[0]
+    dy = torch.arange(n[1], dtype=torch.float64, device=dev) * h - c[1]
+    for iz in range(n[2]):
+        dz = iz * h - c[2]
+        q = (0.5 * (S[0, 0] * dx[None, :] ** 2 + S[1, 1] * dy[:, None] ** 2 + S[2, 2] * dz * dz)
+             + S[0, 1] * dx[None, :] * dy[:, None] + S[0, 2] * dx[None, :] * dz
+             + S[1, 2] * dy[:, None] * dz + bvec[0] * dx[None, :] + bvec[1] * dy[:, None]
+             + bvec[2] * dz)
+        E[iz] = q.float()
+    probe = W.Probe()
+    fire = W.parity_fire(W.Fire())
+    scan = W.Scan(59.63, 49.71, 0.13, 0.17, 8, 8, 46.4, 0.1, 12)
+    res = ppm.relaxed_scan_tricubic(grid, E, probe, fire, scan)
+    pp = res["pp"].cpu().numpy()
+    del E, res
+    torch.cuda.empty_cache()
+    assert np.all(pp[..., 3] >= 0)
+    Amat, b = -S, S @ c - bvec                                   # F = Amat r + b
+    worst = 0.0
+    for iy in range(scan.ny):
+        for ix in range(scan.nx):
+            for k in range(scan.nz):
+                anchor = np.array([scan.x0 + ix * scan.dx, scan.y0 + iy * scan.dy,
+                                   scan.z_top - k * scan.dz])
+                rN = _newton(anchor, probe, Amat, b, anchor + np.array(probe.d0))
+                rg = anchor + np.array(probe.d0) + pp[k, iy, ix, :3]
+                worst = max(worst, float(np.linalg.norm(rg - rN)))
+    assert worst <= 1e-4, worst
+    print("wide tricubic scan: worst |dr|", worst, flush=True)
