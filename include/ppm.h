@@ -177,6 +177,10 @@ ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_
  * ppm_relaxed_scan -- relaxed scan with optional fused frequency shift
  * (Sec. 2.1 Eq. 1-3, Sec. 5.1.1 step 2).
  * in:  ff[nz][ny][nx][4] from ppm_build_ff (only Fx, Fy, Fz are read).
+ * The probe state and FIRE are FP64.  The trilinear combination of the FP32
+ * corner forces is FP32 when fire->f_conv >= 1e-5 eV/A (its rounding, about
+ * 1e-7 of the force, is then far below the threshold) and FP64 otherwise, so
+ * tight thresholds resolve the force balance below FP32 rounding.
  * out (each may be NULL, at least one must be given):
  *   fz[scan.nz][scan.ny][scan.nx]  tip force Fz_tip = -F^T_z at the relaxed
  *                                   probe position (eV/A)

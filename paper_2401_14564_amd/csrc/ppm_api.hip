@@ -133,6 +133,7 @@ ScanArgs make_scan_args(const ppm_grid *g, const ppm_probe *p, const ppm_fire *f
         a.f_conv2 = f->f_conv * f->f_conv;
         a.n_min = f->n_min;
         a.max_iter = f->max_iter;
+        a.lerp32 = f->f_conv >= kLerp32MinFconv ? 1 : 0;
     }
     return a;
 }

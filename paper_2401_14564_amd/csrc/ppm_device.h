@@ -39,15 +39,16 @@ struct Cell {
 
 // Cell of a grid coordinate along an axis clamped to its first/last cell:
 // index in [0, n-2], t in [0, 1]; outside the grid the field is continued
-// constantly (in = false).  NaN lands in the first cell.
+// constantly (in = false).  The coordinate is clamped to [0, n-1] first (fmax
+// returns the non-NaN operand, so NaN lands at 0, in the first cell), then the
+// cell index to n-2, so u >= n-1 gives the last cell at t = 1.
 __device__ __forceinline__ int clamp_cell(double u, int n, double &t, bool &in)
 {
-    const double f = floor(u);
-    const bool below = !(f >= 0.0);
-    const bool above = f > (double)(n - 2);
-    t = below ? 0.0 : (above ? 1.0 : u - f);
-    in = !(below || above);
-    return below ? 0 : (above ? n - 2 : (int)f);
+    in = (u >= 0.0) && (u < (double)(n - 1));
+    const double uc = fmin(fmax(u, 0.0), (double)(n - 1));
+    const double f = fmin(floor(uc), (double)(n - 2));
+    t = uc - f;
+    return (int)f;
 }
 
 // Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
@@ -68,27 +69,41 @@ __device__ __forceinline__ int periodic_cell(double u, int n, double &t)
     return i;
 }
 
+// Grid geometry of a kernel instance: open (x, y clamped like z), periodic in
+// x and y, or read from ScanArgs::periodic at run time.
+enum GridGeom { kOpen = 0, kPeriodic = 1, kRuntimeGeom = 2 };
+
+template <int GEOM>
 __device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
 {
     Cell c;
     int ix, iy;
-    if (a.periodic) {
+    const bool periodic = GEOM == kRuntimeGeom ? a.periodic != 0 : GEOM == kPeriodic;
+    if (periodic) {
         ix = periodic_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx);
         iy = periodic_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty);
         c.xin = c.yin = true;
+        c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
+        c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
     } else {
-        // a sample without periodic images: x,y clamped like z
+        // a sample without periodic images: x,y clamped like z; the clamped
+        // cell index is at most n-2, so the +x/+y corners never wrap
         ix = clamp_cell(fma(x, a.ihx, a.oxi), a.gnx, c.tx, c.xin);
         iy = clamp_cell(fma(y, a.ihy, a.oyi), a.gny, c.ty, c.yin);
+        c.dx1 = 1;
+        c.dy1 = a.gnx;
     }
     // z is clamped to the first/last cell: outside the grid the field is constant
     const int iz = clamp_cell(fma(z, a.ihz, a.ozi), a.gnz, c.tz, c.zin);
     const int plane = a.gnx * a.gny;
     c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
-    c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
-    c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
     c.dz1 = plane;
     return c;
+}
+
+__device__ __forceinline__ Cell locate(const ScanArgs &a, double x, double y, double z)
+{
+    return locate<kRuntimeGeom>(a, x, y, z);
 }
 
 // Corner load.  WIDE grids (16 B x voxels >= 4 GiB) need 64-bit addressing;
@@ -107,19 +122,42 @@ __device__ __forceinline__ float3 corner(const float4 *__restrict__ ff, uint32_t
 }
 
 // The eight corner values (Fx, Fy, Fz) of a cell: v[i + 2j + 4k] is corner
-// (ix + i, iy + j, iz + k).
-template <bool WIDE>
+// (ix + i, iy + j, iz + k).  XSTEP1: the +x corner is always the next voxel
+// (clamped x), so with 32-bit offsets its 16-byte step folds into the load's
+// immediate offset.
+template <bool WIDE, bool XSTEP1 = false>
 __device__ __forceinline__ void gather8(const float4 *__restrict__ ff, const Cell &c, float3 *v)
 {
-    const uint32_t i0 = c.i000;
-    v[0] = corner<WIDE>(ff, i0);
-    v[1] = corner<WIDE>(ff, i0 + c.dx1);
-    v[2] = corner<WIDE>(ff, i0 + c.dy1);
-    v[3] = corner<WIDE>(ff, i0 + c.dx1 + c.dy1);
-    v[4] = corner<WIDE>(ff, i0 + c.dz1);
-    v[5] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1);
-    v[6] = corner<WIDE>(ff, i0 + c.dz1 + c.dy1);
-    v[7] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1 + c.dy1);
+    if constexpr (!WIDE && XSTEP1) {
+        const char *b = reinterpret_cast<const char *>(ff);
+        const uint32_t o00 = c.i000 * 16u;
+        const uint32_t o10 = o00 + (uint32_t)c.dy1 * 16u;
+        const uint32_t o01 = o00 + (uint32_t)c.dz1 * 16u;
+        const uint32_t o11 = o01 + (uint32_t)c.dy1 * 16u;
+        const char *p00 = b + o00, *p10 = b + o10, *p01 = b + o01, *p11 = b + o11;
+        auto ld = [](const char *p) {
+            const float4 *q = reinterpret_cast<const float4 *>(p);
+            return make_float3(q->x, q->y, q->z);
+        };
+        v[0] = ld(p00);
+        v[1] = ld(p00 + 16);
+        v[2] = ld(p10);
+        v[3] = ld(p10 + 16);
+        v[4] = ld(p01);
+        v[5] = ld(p01 + 16);
+        v[6] = ld(p11);
+        v[7] = ld(p11 + 16);
+    } else {
+        const uint32_t i0 = c.i000;
+        v[0] = corner<WIDE>(ff, i0);
+        v[1] = corner<WIDE>(ff, i0 + c.dx1);
+        v[2] = corner<WIDE>(ff, i0 + c.dy1);
+        v[3] = corner<WIDE>(ff, i0 + c.dx1 + c.dy1);
+        v[4] = corner<WIDE>(ff, i0 + c.dz1);
+        v[5] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1);
+        v[6] = corner<WIDE>(ff, i0 + c.dz1 + c.dy1);
+        v[7] = corner<WIDE>(ff, i0 + c.dz1 + c.dx1 + c.dy1);
+    }
 }
 
 }  // namespace ppm

@@ -33,24 +33,43 @@ namespace {
 
 constexpr int kTX = 8, kTY = 8;
 
-// Trilinear interpolation of (Fx, Fy, Fz) in FP64 from FP32 corner values.
 // Trilinear combination of the eight corner values v[i + 2j + 4k] (gather8).
+// LERP32: combine in FP32.  The corners are FP32, so FP32 weights and sums add
+// rounding of the size the grid values already carry (about 1e-7 of the force)
+// and save the 24 FP32 -> FP64 conversions of the FP64 combination on the
+// critical path; used when the convergence threshold is far above that
+// rounding (kLerp32MinFconv).
+template <bool LERP32>
 __device__ __forceinline__ void trilerp(const float3 *v, const Cell &c, double &Fx, double &Fy,
                                         double &Fz)
 {
     const float3 v000 = v[0], v100 = v[1], v010 = v[2], v110 = v[3];
     const float3 v001 = v[4], v101 = v[5], v011 = v[6], v111 = v[7];
-    const double tx = c.tx, ty = c.ty, tz = c.tz;
-    const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
-    const double w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
-    const double w000 = sx * w00, w100 = tx * w00, w010 = sx * w10, w110 = tx * w10;
-    const double w001 = sx * w01, w101 = tx * w01, w011 = sx * w11, w111 = tx * w11;
-    Fx = w000 * v000.x + w100 * v100.x + w010 * v010.x + w110 * v110.x +
-         w001 * v001.x + w101 * v101.x + w011 * v011.x + w111 * v111.x;
-    Fy = w000 * v000.y + w100 * v100.y + w010 * v010.y + w110 * v110.y +
-         w001 * v001.y + w101 * v101.y + w011 * v011.y + w111 * v111.y;
-    Fz = w000 * v000.z + w100 * v100.z + w010 * v010.z + w110 * v110.z +
-         w001 * v001.z + w101 * v101.z + w011 * v011.z + w111 * v111.z;
+    if constexpr (LERP32) {
+        const float tx = (float)c.tx, ty = (float)c.ty, tz = (float)c.tz;
+        const float sx = 1.0f - tx, sy = 1.0f - ty, sz = 1.0f - tz;
+        const float w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
+        const float w000 = sx * w00, w100 = tx * w00, w010 = sx * w10, w110 = tx * w10;
+        const float w001 = sx * w01, w101 = tx * w01, w011 = sx * w11, w111 = tx * w11;
+        Fx = (double)(w000 * v000.x + w100 * v100.x + w010 * v010.x + w110 * v110.x +
+                      w001 * v001.x + w101 * v101.x + w011 * v011.x + w111 * v111.x);
+        Fy = (double)(w000 * v000.y + w100 * v100.y + w010 * v010.y + w110 * v110.y +
+                      w001 * v001.y + w101 * v101.y + w011 * v011.y + w111 * v111.y);
+        Fz = (double)(w000 * v000.z + w100 * v100.z + w010 * v010.z + w110 * v110.z +
+                      w001 * v001.z + w101 * v101.z + w011 * v011.z + w111 * v111.z);
+    } else {
+        const double tx = c.tx, ty = c.ty, tz = c.tz;
+        const double sx = 1.0 - tx, sy = 1.0 - ty, sz = 1.0 - tz;
+        const double w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
+        const double w000 = sx * w00, w100 = tx * w00, w010 = sx * w10, w110 = tx * w10;
+        const double w001 = sx * w01, w101 = tx * w01, w011 = sx * w11, w111 = tx * w11;
+        Fx = w000 * v000.x + w100 * v100.x + w010 * v010.x + w110 * v110.x +
+             w001 * v001.x + w101 * v101.x + w011 * v011.x + w111 * v111.x;
+        Fy = w000 * v000.y + w100 * v100.y + w010 * v010.y + w110 * v110.y +
+             w001 * v001.y + w101 * v101.y + w011 * v011.y + w111 * v111.y;
+        Fz = w000 * v000.z + w100 * v100.z + w010 * v010.z + w110 * v110.z +
+             w001 * v001.z + w101 * v101.z + w011 * v011.z + w111 * v111.z;
+    }
 }
 
 // Tip springs, Eq. 2: F^T = -k_R (|d| - R0) d/|d| - k_xy (.) (d - d0),
@@ -65,12 +84,6 @@ __device__ __forceinline__ void tip_force(const ScanArgs &a, double dx, double d
     Fz = fr * dz;
 }
 
-// DFMODE 0: no frequency shift; 1: each lane keeps its column's Fz in LDS and
-// evaluates the frequency shift after its last height; 2: same, reading the
-// column back from the caller's fz output (used when the column does not fit
-// in LDS).  Either way the per-step loop only pays a store per finished height:
-// with lanes converging at different steps, some lane of a wave changes height
-// on almost every step, so anything on that path is paid on every step.
 // Catmull-Rom (Keys, a = -1/2) weights of the stencil offsets -1, 0, 1, 2 and
 // their derivatives with respect to the fraction t.
 __device__ __forceinline__ void cr_weights(double t, double *w, double *dw)
@@ -194,11 +207,17 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
     Fz = -gz * a.ihz;
 }
 
-// One tip column (ix, iy): all heights, then (DFMODE != 0) its frequency shift.
-// NL = lanes per block (the stride of the per-lane Fz columns in LDS).
+// One tip column (ix, iy): all heights, then its fz output and (df_out != null)
+// its frequency shift.  NL = lanes per block (the stride of the per-lane Fz
+// columns in LDS).  STAGE: each finished height's Fz goes to the lane's LDS
+// column s_col[k][lane] and the column is written out after the last height;
+// the loop then issues no global store (on gfx950 the gathers' vmcnt waits
+// also wait for earlier stores).  Otherwise Fz is stored to fz_out as each
+// height finishes and the frequency shift re-reads it.
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
-// from the energy grid En.
-template <int DFMODE, bool WIDE, int NL, int INTERP = 0>
+// from the energy grid En.  GEOM: grid geometry of the trilinear lookup
+// (GridGeom).  LERP32: FP32 trilinear combination (trilerp).
+template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
                                             float *__restrict__ fz_out,
@@ -218,18 +237,25 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     double u1x = 0.0, u1y = 0.0, u1z = 0.0;      // relaxed displacement of the previous height
     int npos = 0, it = 0;
 
+    // One loop iteration = one force evaluation of every lane.  A lane whose
+    // probe has converged (or hit max_iter) records the height and starts its
+    // next height in the same iteration; the others take a FIRE step.  Both
+    // successor states are computed by every lane and merged by selects, so the
+    // loop has a single back edge: with a conditional `continue` the compiler
+    // splits it into a per-height inner loop, and every lane then waits at each
+    // height for the slowest lane of its wave.
     while (true) {
         double Sx, Sy, Sz, Tx, Ty, Tz;
         if (INTERP == 0) {
             // issue the eight gathers, then evaluate the springs (independent of
             // them) while they are in flight, then interpolate
-            const Cell c = locate(a, rx, ry, rz);
+            const Cell c = locate<GEOM>(a, rx, ry, rz);
             float3 v[8];
-            gather8<WIDE>(ff, c, v);
+            gather8<WIDE, GEOM == kOpen>(ff, c, v);
             __builtin_amdgcn_sched_barrier(0);   // keep the spring math ahead of the waits
             tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
             __builtin_amdgcn_sched_barrier(0);
-            trilerp(v, c, Sx, Sy, Sz);
+            trilerp<LERP32>(v, c, Sx, Sy, Sz);
         } else {
             tricubic_force<WIDE>(a, En, rx, ry, rz, Sx, Sy, Sz);
             tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
@@ -237,80 +263,86 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
         const double g2 = Gx * Gx + Gy * Gy + Gz * Gz;
         const bool conv = g2 < a.f_conv2;
-        if (conv || it >= a.max_iter) {
-            // record this height
+        const bool done = conv || it >= a.max_iter;
+        if (done) {
+            // record this height (stores only)
             const float fzv = (float)(-Tz);
             const size_t o = (size_t)k * plane + col;
-            if (fz_out) fz_out[o] = fzv;
-            if (DFMODE == 1) s_col[k * NL + lane] = fzv;
+            if (STAGE) s_col[k * NL + lane] = fzv;
+            else if (fz_out) fz_out[o] = fzv;
             if (pp_out)
                 pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
                                         (float)(rz - az - a.d0z), conv ? (float)it : -(float)it);
-            if (k + 1 >= a.snz) break;
-            // warm start: the next height starts from its anchor plus the relaxed
-            // displacement extrapolated linearly from this height and the
-            // previous one (just the displacement after the first height);
-            // v and alpha restart, dt carries over (not below dt0)
-            const double ux = rx - ax, uy = ry - ay, uz = rz - az;
-            const bool lin = k >= 1;
-            const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
-                         ez = lin ? uz - u1z : 0.0;
-            u1x = ux;
-            u1y = uy;
-            u1z = uz;
-            ++k;
-            az = a.z_top - k * a.sdz;
-            rx = ax + (ux + ex);
-            ry = ay + (uy + ey);
-            rz = az + (uz + ez);
-            vx = vy = vz = 0.0;
-            dt = fmax(dt, a.dt0);
-            alpha = a.alpha0;
-            npos = 0;
-            it = 0;
-            continue;
         }
-        {
-            // FIRE velocity update, branch-free (lanes of a wave disagree on the
-            // sign of P): from the second step on, P > 0 mixes v towards G and,
-            // after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
-            // the particle, shrinks dt and resets alpha.
-            const double P = Gx * vx + Gy * vy + Gz * vz;
-            const bool pos = (it > 0) && (P > 0.0);
-            const bool neg = (it > 0) && !(P > 0.0);
-            const double vn2 = vx * vx + vy * vy + vz * vz;
-            // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
-            // 1/sqrt (no Newton step) is accurate enough
-            const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
-            const double sc = pos ? mix : 0.0;
-            const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
-            vx = om * vx + sc * Gx;
-            vy = om * vy + sc * Gy;
-            vz = om * vz + sc * Gz;
-            npos = pos ? npos + 1 : (neg ? 0 : npos);
-            const bool grow = pos && npos > a.n_min;
-            dt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
-            alpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
-        }
-        const double h = dt * a.inv_mass;
-        vx += Gx * h;
-        vy += Gy * h;
-        vz += Gz * h;
-        rx += vx * dt;
-        ry += vy * dt;
-        rz += vz * dt;
-        ++it;
+        if (done && k + 1 >= a.snz) break;
+
+        // (a) FIRE step.  Velocity update, branch-free (lanes of a wave disagree
+        // on the sign of P): from the second step on, P > 0 mixes v towards G
+        // and, after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
+        // the particle, shrinks dt and resets alpha.
+        const double P = Gx * vx + Gy * vy + Gz * vz;
+        const bool pos = (it > 0) && (P > 0.0);
+        const bool neg = (it > 0) && !(P > 0.0);
+        const double vn2 = vx * vx + vy * vy + vz * vz;
+        // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
+        // 1/sqrt (no Newton step) is accurate enough
+        const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
+        const double sc = pos ? mix : 0.0;
+        const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
+        double fvx = om * vx + sc * Gx;
+        double fvy = om * vy + sc * Gy;
+        double fvz = om * vz + sc * Gz;
+        const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
+        const bool grow = pos && fnpos > a.n_min;
+        const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
+        const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
+        const double h = fdt * a.inv_mass;
+        fvx += Gx * h;
+        fvy += Gy * h;
+        fvz += Gz * h;
+        const double frx = rx + fvx * fdt, fry = ry + fvy * fdt, frz = rz + fvz * fdt;
+
+        // (b) next height.  Warm start: the next height starts from its anchor
+        // plus the relaxed displacement extrapolated linearly from this height
+        // and the previous one (just the displacement after the first height);
+        // v and alpha restart, dt carries over (not below dt0).
+        const double ux = rx - ax, uy = ry - ay, uz = rz - az;
+        const bool lin = k >= 1;
+        const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
+                     ez = lin ? uz - u1z : 0.0;
+        const int kn = k + 1;
+        const double azn = a.z_top - kn * a.sdz;
+
+        // merge
+        rx = done ? ax + (ux + ex) : frx;
+        ry = done ? ay + (uy + ey) : fry;
+        rz = done ? azn + (uz + ez) : frz;
+        vx = done ? 0.0 : fvx;
+        vy = done ? 0.0 : fvy;
+        vz = done ? 0.0 : fvz;
+        dt = done ? fmax(dt, a.dt0) : fdt;
+        alpha = done ? a.alpha0 : falpha;
+        npos = done ? 0 : fnpos;
+        it = done ? 0 : it + 1;
+        u1x = done ? ux : u1x;
+        u1y = done ? uy : u1y;
+        u1z = done ? uz : u1z;
+        az = done ? azn : az;
+        k = done ? kn : k;
     }
 
-    if (DFMODE != 0) {
+    if (STAGE && fz_out) {
+        for (int kk = 0; kk < a.snz; ++kk) fz_out[(size_t)kk * plane + col] = s_col[kk * NL + lane];
+    }
+    if (df_out) {
         // Eq. 3 over the finished column: output o uses samples o .. o + 2m,
         // wts.w[j] weighting sample o + j.
         const int m2 = 2 * a.m;
         for (int o = 0; o + m2 < a.snz; ++o) {
             float s = 0.0f;
             for (int j = 0; j <= m2; ++j) {
-                const float f = (DFMODE == 1) ? s_col[(o + j) * NL + lane]
-                                              : fz_out[(size_t)(o + j) * plane + col];
+                const float f = STAGE ? s_col[(o + j) * NL + lane]
+                                      : fz_out[(size_t)(o + j) * plane + col];
                 s = fmaf(wts.w[j], f, s);
             }
             df_out[(size_t)o * plane + col] = s;
@@ -318,12 +350,12 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     }
 }
 
-template <int TX, int TY, int DFMODE, bool WIDE, int INTERP>
+template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32>
 __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
     const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, const float *__restrict__ En,
     float *__restrict__ fz_out, float4 *__restrict__ pp_out, float *__restrict__ df_out)
 {
-    extern __shared__ float s_col[];   // DFMODE 1: [snz][TX * TY]
+    extern __shared__ float s_col[];   // STAGE: [snz][TX * TY]
     // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
     // contiguous range of tiles.
     const int nb = gridDim.x;
@@ -341,15 +373,15 @@ __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
     const int ix = (tile % tiles_x) * TX + (int)threadIdx.x;
     const int iy = (tile / tiles_x) * TY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<DFMODE, WIDE, TX * TY, INTERP>(a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out,
-                                               s_col, En);
+    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32>(a, wts, ix, iy, lane, ff, fz_out,
+                                                            pp_out, df_out, s_col, En);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
 // job of a tile is found by a binary search over tile_begin (wave-uniform);
 // the job's probe and tip lattice, its molecule's grid and the arena offsets
 // come from the tables; FIRE and frequency-shift settings are shared.
-template <int DFMODE, bool WIDE>
+template <bool STAGE, bool WIDE, bool LERP32>
 __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const ScanArgs proto, const DfWeights wts, const ppm_batch_mol *__restrict__ mols,
     const ppm_batch_scan *__restrict__ jobs, int n_jobs, const float4 *__restrict__ arena,
@@ -374,9 +406,9 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
     const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<DFMODE, WIDE, kTX * kTY>(a, wts, ix, iy, lane, arena + M.ff_offset,
-                              fz_arena ? fz_arena + J.fz_offset : nullptr, nullptr,
-                              df_arena ? df_arena + J.df_offset : nullptr, s_col);
+    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32>(
+        a, wts, ix, iy, lane, arena + M.ff_offset, fz_arena ? fz_arena + J.fz_offset : nullptr,
+        nullptr, df_arena ? df_arena + J.df_offset : nullptr, s_col);
 }
 
 // Standalone frequency shift: one lane per (x, y) column sliding along z.
@@ -426,44 +458,94 @@ DfWeights repad(const DfWeights &w, int m, int M)
 
 }  // namespace
 
-template <int TX, int TY, bool WIDE, int INTERP>
-void launch_scan_tiles(const ScanArgs &b, int dfmode, const DfWeights &w, const float4 *ff,
-                       const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
+// Largest dynamic LDS allocation of one block on the current device (bytes).
+size_t max_block_lds()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = 65536;
+        cache[dev] = v;
+    }
+    return (size_t)cache[dev];
+}
+
+// Opt a kernel in to more than 64 KiB of dynamic LDS.  A refusal is cleared
+// here; the launch that follows then reports the error.
+template <typename Kernel>
+void allow_lds(Kernel kernel, size_t bytes)
+{
+    if (bytes <= 65536) return;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        (void)hipGetLastError();
+}
+
+template <int TX, int TY, bool WIDE, int INTERP, int GEOM, bool LERP32>
+void launch_scan_geom(const ScanArgs &b, bool stage, const DfWeights &w, const float4 *ff,
+                      const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
 {
     dim3 block(TX, TY, 1);
     dim3 grid((unsigned)(((b.snx + TX - 1) / TX) * ((b.sny + TY - 1) / TY)), 1, 1);
-    if (dfmode == 0) {
-        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 0, WIDE, INTERP>), grid, block, 0, stream,
-                           b, w, ff, En, fz, pp, nullptr);
-    } else if (dfmode == 1) {
+    if (stage) {
         const size_t lds = (size_t)b.snz * TX * TY * sizeof(float);
-        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 1, WIDE, INTERP>), grid, block, lds,
-                           stream, b, sample_weights(w, b.m), ff, En, fz, pp, df);
+        auto kernel = relaxed_scan_kernel<TX, TY, true, WIDE, INTERP, GEOM, LERP32>;
+        allow_lds(kernel, lds);
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, b, w, ff, En, fz, pp, df);
     } else {
-        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, 2, WIDE, INTERP>), grid, block, 0, stream,
-                           b, sample_weights(w, b.m), ff, En, fz, pp, df);
+        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, false, WIDE, INTERP, GEOM, LERP32>), grid,
+                           block, 0, stream, b, w, ff, En, fz, pp, df);
     }
 }
 
 // Block shape: 16 x 16 lanes (four waves, one per SIMD of the CU that runs the
 // block).  The kernel's time is the serial FIRE chain of its hardest columns,
 // so those must not share a SIMD; one-wave blocks leave the pairing of waves on
-// SIMDs to the dispatcher.  The fused frequency shift keeps each lane's Fz
-// column in LDS when it fits (64 heights for 256 lanes), else re-reads the fz
-// output; without fz and with more heights, 8 x 8 blocks hold up to 256 heights.
-template <bool WIDE, int INTERP>
+// SIMDs to the dispatcher.  Fz is staged in LDS when the block's columns fit
+// (up to 160 heights in gfx950's 160 KiB); beyond that the fz output is
+// written directly (and re-read for the frequency shift), or, without fz,
+// 8 x 8 blocks stage up to 256 heights.
+template <bool WIDE, int INTERP, int GEOM, bool LERP32>
 void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, const float *En,
                       float *fz, float4 *pp, float *df, hipStream_t stream)
 {
     const bool want_df = b.m != 0 && df;
-    if (!want_df) {
-        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 0, w, ff, En, fz, pp, df, stream);
-    } else if (b.snz * 256 * (int)sizeof(float) <= 65536) {
-        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 1, w, ff, En, fz, pp, df, stream);
-    } else if (fz) {
-        launch_scan_tiles<16, 16, WIDE, INTERP>(b, 2, w, ff, En, fz, pp, df, stream);
+    const DfWeights sw = want_df ? sample_weights(w, b.m) : w;
+    float *dfo = want_df ? df : nullptr;
+    const size_t column = (size_t)b.snz * sizeof(float);
+    if (!fz && !want_df)
+        launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, false, sw, ff, En, fz, pp, dfo,
+                                                             stream);
+    else if (column * 256 <= max_block_lds())
+        launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, true, sw, ff, En, fz, pp, dfo,
+                                                             stream);
+    else if (fz)
+        launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, false, sw, ff, En, fz, pp, dfo,
+                                                             stream);
+    else
+        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, true, sw, ff, En, fz, pp, dfo,
+                                                               stream);
+}
+
+// The trilinear lookup is compiled per grid geometry (open grids have constant
+// +x/+y corner offsets) and combination precision; the tricubic stencil reads
+// the geometry at run time.
+template <bool WIDE, int INTERP>
+void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff,
+                         const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
+{
+    if constexpr (INTERP != 0) {
+        launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream);
+    } else if (b.periodic) {
+        if (b.lerp32) launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream);
+        else launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream);
     } else {
-        launch_scan_tiles<kTX, kTY, WIDE, INTERP>(b, 1, w, ff, En, fz, pp, df, stream);
+        if (b.lerp32) launch_scan_mode<WIDE, 0, kOpen, true>(b, w, ff, En, fz, pp, df, stream);
+        else launch_scan_mode<WIDE, 0, kOpen, false>(b, w, ff, En, fz, pp, df, stream);
     }
 }
 
@@ -472,9 +554,9 @@ hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const floa
 {
     const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
-        launch_scan_mode<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
+        launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
     else
-        launch_scan_mode<false, 0>(a, w, ff, nullptr, fz, pp, df, stream);
+        launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream);
     return hipGetLastError();
 }
 
@@ -483,9 +565,9 @@ hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w, c
 {
     const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
-        launch_scan_mode<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
+        launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
     else
-        launch_scan_mode<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
+        launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
     return hipGetLastError();
 }
 
@@ -494,22 +576,22 @@ long long scan_tile_count(int nx, int ny)
     return (long long)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
 }
 
-template <bool WIDE>
+template <bool WIDE, bool LERP32>
 void launch_scan_batch_mode(const ScanArgs &proto, const DfWeights &w, const ppm_batch_mol *mols,
                             const ppm_batch_scan *jobs, int n_jobs, dim3 grid, int max_nz,
                             const float4 *arena, float *fz, float *df, hipStream_t stream)
 {
     dim3 block(kTX, kTY, 1);
-    if (proto.m == 0 || !df) {
-        hipLaunchKernelGGL((relaxed_scan_batch_kernel<0, WIDE>), grid, block, 0, stream, proto, w,
-                           mols, jobs, n_jobs, arena, fz, nullptr);
-    } else if (max_nz <= kMaxScanLdsHeights) {
+    const bool want_df = proto.m != 0 && df;
+    const DfWeights sw = want_df ? sample_weights(w, proto.m) : w;
+    float *dfo = want_df ? df : nullptr;
+    if ((fz || want_df) && max_nz <= kMaxScanLdsHeights) {
         const size_t lds = (size_t)max_nz * kTX * kTY * sizeof(float);
-        hipLaunchKernelGGL((relaxed_scan_batch_kernel<1, WIDE>), grid, block, lds, stream, proto,
-                           sample_weights(w, proto.m), mols, jobs, n_jobs, arena, fz, df);
+        hipLaunchKernelGGL((relaxed_scan_batch_kernel<true, WIDE, LERP32>), grid, block, lds,
+                           stream, proto, sw, mols, jobs, n_jobs, arena, fz, dfo);
     } else {
-        hipLaunchKernelGGL((relaxed_scan_batch_kernel<2, WIDE>), grid, block, 0, stream, proto,
-                           sample_weights(w, proto.m), mols, jobs, n_jobs, arena, fz, df);
+        hipLaunchKernelGGL((relaxed_scan_batch_kernel<false, WIDE, LERP32>), grid, block, 0,
+                           stream, proto, sw, mols, jobs, n_jobs, arena, fz, dfo);
     }
 }
 
@@ -524,12 +606,21 @@ hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
     const long long gx = n_tiles < 65536 ? n_tiles : 65536;
     const long long gy = (n_tiles + gx - 1) / gx;
     dim3 grid((unsigned)gx, (unsigned)gy, 1);
-    if (wide)
-        launch_scan_batch_mode<true>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz, arena,
-                                     fz_arena, df_arena, stream);
-    else
-        launch_scan_batch_mode<false>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz, arena,
-                                      fz_arena, df_arena, stream);
+    if (wide) {
+        if (proto.lerp32)
+            launch_scan_batch_mode<true, true>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz,
+                                               arena, fz_arena, df_arena, stream);
+        else
+            launch_scan_batch_mode<true, false>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz,
+                                                arena, fz_arena, df_arena, stream);
+    } else {
+        if (proto.lerp32)
+            launch_scan_batch_mode<false, true>(proto, w, mols_dev, jobs_dev, n_jobs, grid, max_nz,
+                                                arena, fz_arena, df_arena, stream);
+        else
+            launch_scan_batch_mode<false, false>(proto, w, mols_dev, jobs_dev, n_jobs, grid,
+                                                 max_nz, arena, fz_arena, df_arena, stream);
+    }
     return hipGetLastError();
 }
 
