@@ -24,6 +24,12 @@
 //    force balance can be resolved far below the FP32 rounding of absolute
 //    coordinates.  The grid itself is FP32 (16 B per voxel, one float4 gather
 //    per corner).
+//  * Multiply-adds are fused only within one expression (contract(on), placed
+//    before the includes so it also covers the device helpers): the kernel
+//    instances (tile shape, geometry, drift bound, batched or single) differ in
+//    control flow, and cross-statement fusion would then round differently in
+//    each, while a batched scan must reproduce single scans bit for bit.
+#pragma clang fp contract(on)
 #include "ppm.h"
 #include "ppm_device.h"
 #include "ppm_kernels.h"
@@ -32,6 +38,15 @@ namespace ppm {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
+
+// Drift bound of the scan loop (heights a lane may lead the lowest unfinished
+// height of its wave) where it is compiled in: the tricubic scan (64 loads per
+// evaluation) and the throughput-bound batched scan, which gain more from
+// coalesced gathers than they lose to waiting lanes.  The trilinear single scan
+// is latency-bound by its hardest wave and runs unbounded, without the
+// bookkeeping.  Measured on the paper-scale workload and a 64-molecule batch:
+// bound 1 beats 0 (height-synchronous), 2, 4 and unbounded on both.
+constexpr int kDrift = 1;
 
 // Trilinear combination of the eight corner values v[i + 2j + 4k] (gather8).
 // LERP32: combine in FP32.  The corners are FP32, so FP32 weights and sums add
@@ -216,8 +231,9 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
 // height finishes and the frequency shift re-reads it.
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
 // from the energy grid En.  GEOM: grid geometry of the trilinear lookup
-// (GridGeom).  LERP32: FP32 trilinear combination (trilerp).
-template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32>
+// (GridGeom).  LERP32: FP32 trilinear combination (trilerp).  BOUNDED: lanes
+// keep within a.drift heights of the wave's lowest unfinished height.
+template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32, bool BOUNDED>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
                                             float *__restrict__ fz_out,
@@ -237,98 +253,120 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     double u1x = 0.0, u1y = 0.0, u1z = 0.0;      // relaxed displacement of the previous height
     int npos = 0, it = 0;
 
-    // One loop iteration = one force evaluation of every lane.  A lane whose
-    // probe has converged (or hit max_iter) records the height and starts its
-    // next height in the same iteration; the others take a FIRE step.  Both
-    // successor states are computed by every lane and merged by selects, so the
-    // loop has a single back edge: with a conditional `continue` the compiler
-    // splits it into a per-height inner loop, and every lane then waits at each
-    // height for the slowest lane of its wave.
+    // One loop iteration = one force evaluation of every working lane.  A lane
+    // whose probe has converged (or hit max_iter) records the height and starts
+    // its next height in the same iteration; the others take a FIRE step.  Both
+    // successor states are computed and merged by selects, so the loop has a
+    // single back edge: with a conditional `continue` the compiler splits it
+    // into a per-height inner loop, and every lane then waits at each height
+    // for the slowest lane of its wave.
+    // Drift bound (BOUNDED): a lane may start height k+1 only while k+1 <= kmin + drift,
+    // kmin being the lowest height still in progress in the wave; until then it
+    // is held (no force evaluation, state unchanged).  Lanes then gather from at
+    // most drift+1 z-planes, which keeps the wave's loads coalesced and in L1;
+    // drift 0 is height-synchronous.  The bound changes only the schedule, never
+    // a lane's own sequence of evaluations.
+    bool done = false, held = false;
+    int kmin = 0;
     while (true) {
-        double Sx, Sy, Sz, Tx, Ty, Tz;
-        if (INTERP == 0) {
-            // issue the eight gathers, then evaluate the springs (independent of
-            // them) while they are in flight, then interpolate
-            const Cell c = locate<GEOM>(a, rx, ry, rz);
-            float3 v[8];
-            gather8<WIDE, GEOM == kOpen>(ff, c, v);
-            __builtin_amdgcn_sched_barrier(0);   // keep the spring math ahead of the waits
-            tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
-            __builtin_amdgcn_sched_barrier(0);
-            trilerp<LERP32>(v, c, Sx, Sy, Sz);
-        } else {
-            tricubic_force<WIDE>(a, En, rx, ry, rz, Sx, Sy, Sz);
-            tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
-        }
-        const double Gx = Tx + Sx, Gy = Ty + Sy, Gz = Tz + Sz;
-        const double g2 = Gx * Gx + Gy * Gy + Gz * Gz;
-        const bool conv = g2 < a.f_conv2;
-        const bool done = conv || it >= a.max_iter;
-        if (done) {
-            // record this height (stores only)
-            const float fzv = (float)(-Tz);
-            const size_t o = (size_t)k * plane + col;
-            if (STAGE) s_col[k * NL + lane] = fzv;
-            else if (fz_out) fz_out[o] = fzv;
-            if (pp_out)
-                pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
-                                        (float)(rz - az - a.d0z), conv ? (float)it : -(float)it);
+        double Gx = 0.0, Gy = 0.0, Gz = 0.0, g2 = 0.0;
+        if (!BOUNDED || !held) {
+            double Sx, Sy, Sz, Tx, Ty, Tz;
+            if (INTERP == 0) {
+                // issue the eight gathers, then evaluate the springs (independent
+                // of them) while they are in flight, then interpolate
+                const Cell c = locate<GEOM>(a, rx, ry, rz);
+                float3 v[8];
+                gather8<WIDE, GEOM == kOpen>(ff, c, v);
+                __builtin_amdgcn_sched_barrier(0);   // keep the spring math ahead of the waits
+                tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
+                __builtin_amdgcn_sched_barrier(0);
+                trilerp<LERP32>(v, c, Sx, Sy, Sz);
+            } else {
+                tricubic_force<WIDE>(a, En, rx, ry, rz, Sx, Sy, Sz);
+                tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
+            }
+            Gx = Tx + Sx;
+            Gy = Ty + Sy;
+            Gz = Tz + Sz;
+            g2 = Gx * Gx + Gy * Gy + Gz * Gz;
+            const bool conv = g2 < a.f_conv2;
+            done = conv || it >= a.max_iter;
+            if (done) {
+                // record this height (stores only)
+                const float fzv = (float)(-Tz);
+                const size_t o = (size_t)k * plane + col;
+                if (STAGE) s_col[k * NL + lane] = fzv;
+                else if (fz_out) fz_out[o] = fzv;
+                if (pp_out)
+                    pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
+                                            (float)(rz - az - a.d0z),
+                                            conv ? (float)it : -(float)it);
+            }
         }
         if (done && k + 1 >= a.snz) break;
+        // lowest height still in progress among the wave's remaining lanes (a
+        // lane's level k + done never decreases, so kmin only moves up)
+        if constexpr (BOUNDED) {
+            const int level = k + (done ? 1 : 0);
+            while (__ballot(level == kmin) == 0) ++kmin;
+            held = done && k + 1 > kmin + a.drift;
+        }
+        if (!BOUNDED || !held) {
+            // (a) FIRE step.  Velocity update, branch-free (lanes of a wave disagree
+            // on the sign of P): from the second step on, P > 0 mixes v towards G
+            // and, after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
+            // the particle, shrinks dt and resets alpha.
+            const double P = Gx * vx + Gy * vy + Gz * vz;
+            const bool pos = (it > 0) && (P > 0.0);
+            const bool neg = (it > 0) && !(P > 0.0);
+            const double vn2 = vx * vx + vy * vy + vz * vz;
+            // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
+            // 1/sqrt (no Newton step) is accurate enough
+            const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
+            const double sc = pos ? mix : 0.0;
+            const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
+            double fvx = om * vx + sc * Gx;
+            double fvy = om * vy + sc * Gy;
+            double fvz = om * vz + sc * Gz;
+            const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
+            const bool grow = pos && fnpos > a.n_min;
+            const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
+            const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
+            const double h = fdt * a.inv_mass;
+            fvx += Gx * h;
+            fvy += Gy * h;
+            fvz += Gz * h;
+            const double frx = rx + fvx * fdt, fry = ry + fvy * fdt, frz = rz + fvz * fdt;
 
-        // (a) FIRE step.  Velocity update, branch-free (lanes of a wave disagree
-        // on the sign of P): from the second step on, P > 0 mixes v towards G
-        // and, after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
-        // the particle, shrinks dt and resets alpha.
-        const double P = Gx * vx + Gy * vy + Gz * vz;
-        const bool pos = (it > 0) && (P > 0.0);
-        const bool neg = (it > 0) && !(P > 0.0);
-        const double vn2 = vx * vx + vy * vy + vz * vz;
-        // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
-        // 1/sqrt (no Newton step) is accurate enough
-        const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
-        const double sc = pos ? mix : 0.0;
-        const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
-        double fvx = om * vx + sc * Gx;
-        double fvy = om * vy + sc * Gy;
-        double fvz = om * vz + sc * Gz;
-        const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
-        const bool grow = pos && fnpos > a.n_min;
-        const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
-        const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
-        const double h = fdt * a.inv_mass;
-        fvx += Gx * h;
-        fvy += Gy * h;
-        fvz += Gz * h;
-        const double frx = rx + fvx * fdt, fry = ry + fvy * fdt, frz = rz + fvz * fdt;
+            // (b) next height.  Warm start: the next height starts from its anchor
+            // plus the relaxed displacement extrapolated linearly from this height
+            // and the previous one (just the displacement after the first height);
+            // v and alpha restart, dt carries over (not below dt0).
+            const double ux = rx - ax, uy = ry - ay, uz = rz - az;
+            const bool lin = k >= 1;
+            const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
+                         ez = lin ? uz - u1z : 0.0;
+            const int kn = k + 1;
+            const double azn = a.z_top - kn * a.sdz;
 
-        // (b) next height.  Warm start: the next height starts from its anchor
-        // plus the relaxed displacement extrapolated linearly from this height
-        // and the previous one (just the displacement after the first height);
-        // v and alpha restart, dt carries over (not below dt0).
-        const double ux = rx - ax, uy = ry - ay, uz = rz - az;
-        const bool lin = k >= 1;
-        const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
-                     ez = lin ? uz - u1z : 0.0;
-        const int kn = k + 1;
-        const double azn = a.z_top - kn * a.sdz;
-
-        // merge
-        rx = done ? ax + (ux + ex) : frx;
-        ry = done ? ay + (uy + ey) : fry;
-        rz = done ? azn + (uz + ez) : frz;
-        vx = done ? 0.0 : fvx;
-        vy = done ? 0.0 : fvy;
-        vz = done ? 0.0 : fvz;
-        dt = done ? fmax(dt, a.dt0) : fdt;
-        alpha = done ? a.alpha0 : falpha;
-        npos = done ? 0 : fnpos;
-        it = done ? 0 : it + 1;
-        u1x = done ? ux : u1x;
-        u1y = done ? uy : u1y;
-        u1z = done ? uz : u1z;
-        az = done ? azn : az;
-        k = done ? kn : k;
+            // merge
+            rx = done ? ax + (ux + ex) : frx;
+            ry = done ? ay + (uy + ey) : fry;
+            rz = done ? azn + (uz + ez) : frz;
+            vx = done ? 0.0 : fvx;
+            vy = done ? 0.0 : fvy;
+            vz = done ? 0.0 : fvz;
+            dt = done ? fmax(dt, a.dt0) : fdt;
+            alpha = done ? a.alpha0 : falpha;
+            npos = done ? 0 : fnpos;
+            it = done ? 0 : it + 1;
+            u1x = done ? ux : u1x;
+            u1y = done ? uy : u1y;
+            u1z = done ? uz : u1z;
+            az = done ? azn : az;
+            k = done ? kn : k;
+        }
     }
 
     if (STAGE && fz_out) {
@@ -373,8 +411,8 @@ __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
     const int ix = (tile % tiles_x) * TX + (int)threadIdx.x;
     const int iy = (tile / tiles_x) * TY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32>(a, wts, ix, iy, lane, ff, fz_out,
-                                                            pp_out, df_out, s_col, En);
+    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32, INTERP != 0>(
+        a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col, En);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
@@ -406,7 +444,7 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
     const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32>(
+    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32, true>(
         a, wts, ix, iy, lane, arena + M.ff_offset, fz_arena ? fz_arena + J.fz_offset : nullptr,
         nullptr, df_arena ? df_arena + J.df_offset : nullptr, s_col);
 }
@@ -549,9 +587,11 @@ void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff
     }
 }
 
-hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
+hipError_t launch_relaxed_scan(const ScanArgs &args, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream)
 {
+    ScanArgs a = args;
+    a.drift = 0;   // unbounded (no bookkeeping compiled in)
     const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
         launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
@@ -560,9 +600,12 @@ hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const floa
     return hipGetLastError();
 }
 
-hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w, const float *En,
-                                        float *fz, float4 *pp, float *df, hipStream_t stream)
+hipError_t launch_relaxed_scan_tricubic(const ScanArgs &args, const DfWeights &w,
+                                        const float *En, float *fz, float4 *pp, float *df,
+                                        hipStream_t stream)
 {
+    ScanArgs a = args;
+    a.drift = kDrift;
     const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
         launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
@@ -595,7 +638,7 @@ void launch_scan_batch_mode(const ScanArgs &proto, const DfWeights &w, const ppm
     }
 }
 
-hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
+hipError_t launch_relaxed_scan_batch(const ScanArgs &args, const DfWeights &w,
                                      const ppm_batch_mol *mols_dev,
                                      const ppm_batch_scan *jobs_dev, int n_jobs,
                                      long long n_tiles, int max_nz, bool wide,
@@ -603,6 +646,8 @@ hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
                                      hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
+    ScanArgs proto = args;
+    proto.drift = kDrift;
     const long long gx = n_tiles < 65536 ? n_tiles : 65536;
     const long long gy = (n_tiles + gx - 1) / gx;
     dim3 grid((unsigned)gx, (unsigned)gy, 1);
