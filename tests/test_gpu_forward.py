@@ -159,6 +159,26 @@ def test_scan_ragged_shapes(shape):
                label=f"ragged {shape}")
 
 
+@pytest.mark.parametrize("nz", [100, 200])
+def test_scan_output_routes_agree(nz):
+    """The scan stages Fz in LDS (16x16 blocks up to 160 heights, 8x8 blocks for
+    a frequency shift without fz up to 256) or stores it as each height
+    finishes; every route, and the fused frequency shift against the
+    standalone one, gives the same bits."""
+    w = W.config0()
+    scan = W.Scan(7.1, 7.3, 0.13, 0.11, 19, 6, 10.2, 0.1, nz)
+    ff = ppm.build_ff(w.grid, w.probe, ppm.atoms_to_device(w.atoms))
+    run = lambda **kw: ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, scan, **kw)
+    full = run(dfp=w.df, fz=True, pp=True)
+    df_only = run(dfp=w.df, fz=False, pp=False)
+    fz_only = run(fz=True, pp=False)
+    pp_only = run(fz=False, pp=True)
+    assert torch.equal(full["fz"], fz_only["fz"])
+    assert torch.equal(full["df"], df_only["df"])
+    assert torch.equal(full["pp"], pp_only["pp"])
+    assert torch.equal(ppm.df(full["fz"], scan.dz, w.df), full["df"])
+
+
 def test_scan_below_and_above_grid_clamps():
     """Probe heights outside the grid see the field of the nearest z-layer (the
     grid is clamped in z); both sides agree there too."""
