@@ -99,19 +99,24 @@ __device__ __forceinline__ void tip_force(const ScanArgs &a, double dx, double d
     Fz = fr * dz;
 }
 
+// Arithmetic type of an interpolation: FP32 when LERP32, else FP64.
+template <bool LERP32> struct InterpReal { using type = double; };
+template <> struct InterpReal<true> { using type = float; };
+
 // Catmull-Rom (Keys, a = -1/2) weights of the stencil offsets -1, 0, 1, 2 and
 // their derivatives with respect to the fraction t.
-__device__ __forceinline__ void cr_weights(double t, double *w, double *dw)
+template <typename T>
+__device__ __forceinline__ void cr_weights(T t, T *w, T *dw)
 {
-    const double t2 = t * t, t3 = t2 * t;
-    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3] = 0.5 * (t3 - t2);
-    dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
-    dw[1] = 0.5 * (9.0 * t2 - 10.0 * t);
-    dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
-    dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
+    const T t2 = t * t, t3 = t2 * t;
+    w[0] = T(0.5) * (-t3 + T(2) * t2 - t);
+    w[1] = T(0.5) * (T(3) * t3 - T(5) * t2 + T(2));
+    w[2] = T(0.5) * (T(-3) * t3 + T(4) * t2 + t);
+    w[3] = T(0.5) * (t3 - t2);
+    dw[0] = T(0.5) * (T(-3) * t2 + T(4) * t - T(1));
+    dw[1] = T(0.5) * (T(9) * t2 - T(10) * t);
+    dw[2] = T(0.5) * (T(-9) * t2 + T(8) * t + T(1));
+    dw[3] = T(0.5) * (T(3) * t2 - T(2) * t);
 }
 
 // Cell of the cubic stencil along a clamped axis: the coordinate is clamped to
@@ -129,17 +134,20 @@ __device__ __forceinline__ int cubic_clamp_cell(double u, int n, double &t)
 
 // Sample force from the tricubic interpolant of the energy grid En[nz][ny][nx]
 // (the paper's experimental variant of Sec. 5.1.1 step 2): F = -grad E_int,
-// a 4x4x4 stencil contracted axis by axis in FP64.  x,y wrap on a periodic
+// a 4x4x4 stencil contracted axis by axis, in FP64, or in FP32 when LERP32
+// (the same threshold rule as the trilinear combination; FP32 saves the 64
+// FP32 -> FP64 conversions per evaluation).  x,y wrap on a periodic
 // grid; otherwise, and always for z, the point is clamped to the grid box:
 // outside [0, n-1] the force is continued constantly along that axis.
 // WIDE: the energy grid has 2^30 voxels or more (4 GiB), so the loads need
 // 64-bit offsets; otherwise each of the 64 loads is a 32-bit byte offset (row
 // offset + column offset, both computed once) from the scalar base address.
-template <bool WIDE>
+template <bool WIDE, bool LERP32>
 __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *__restrict__ En,
                                                double x, double y, double z, double &Fx,
                                                double &Fy, double &Fz)
 {
+    using T = typename InterpReal<LERP32>::type;
     double tx, ty, tz;
     int ix, iy;
     if (a.periodic) {
@@ -150,10 +158,10 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
         iy = cubic_clamp_cell(fma(y, a.ihy, a.oyi), a.gny, ty);
     }
     const int iz = cubic_clamp_cell(fma(z, a.ihz, a.ozi), a.gnz, tz);
-    double wx[4], dwx[4], wy[4], dwy[4], wz[4], dwz[4];
-    cr_weights(tx, wx, dwx);
-    cr_weights(ty, wy, dwy);
-    cr_weights(tz, wz, dwz);
+    T wx[4], dwx[4], wy[4], dwy[4], wz[4], dwz[4];
+    cr_weights<T>((T)tx, wx, dwx);
+    cr_weights<T>((T)ty, wy, dwy);
+    cr_weights<T>((T)tz, wz, dwz);
     int xs[4], ys[4], zs[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -199,16 +207,16 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
             }
     }
     __builtin_amdgcn_sched_barrier(0);
-    double gx = 0.0, gy = 0.0, gz = 0.0;
+    T gx = 0, gy = 0, gz = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const double v0 = vals[16 * c + 4 * b], v1 = vals[16 * c + 4 * b + 1],
-                         v2 = vals[16 * c + 4 * b + 2], v3 = vals[16 * c + 4 * b + 3];
-            const double r0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
-            const double r1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
+            const T v0 = vals[16 * c + 4 * b], v1 = vals[16 * c + 4 * b + 1],
+                    v2 = vals[16 * c + 4 * b + 2], v3 = vals[16 * c + 4 * b + 3];
+            const T r0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
+            const T r1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
             s0 += wy[b] * r0;
             s1 += dwy[b] * r0;
             s2 += wy[b] * r1;
@@ -217,9 +225,9 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
         gy += wz[c] * s1;
         gz += dwz[c] * s0;
     }
-    Fx = -gx * a.ihx;
-    Fy = -gy * a.ihy;
-    Fz = -gz * a.ihz;
+    Fx = -(double)gx * a.ihx;
+    Fy = -(double)gy * a.ihy;
+    Fz = -(double)gz * a.ihz;
 }
 
 // One tip column (ix, iy): all heights, then its fz output and (df_out != null)
@@ -231,7 +239,7 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
 // height finishes and the frequency shift re-reads it.
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
 // from the energy grid En.  GEOM: grid geometry of the trilinear lookup
-// (GridGeom).  LERP32: FP32 trilinear combination (trilerp).  BOUNDED: lanes
+// (GridGeom).  LERP32: FP32 interpolation arithmetic.  BOUNDED: lanes
 // keep within a.drift heights of the wave's lowest unfinished height.
 template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32, bool BOUNDED>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
@@ -283,7 +291,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
                 __builtin_amdgcn_sched_barrier(0);
                 trilerp<LERP32>(v, c, Sx, Sy, Sz);
             } else {
-                tricubic_force<WIDE>(a, En, rx, ry, rz, Sx, Sy, Sz);
+                tricubic_force<WIDE, LERP32>(a, En, rx, ry, rz, Sx, Sy, Sz);
                 tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
             }
             Gx = Tx + Sx;
@@ -577,7 +585,10 @@ void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff
                          const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
 {
     if constexpr (INTERP != 0) {
-        launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream);
+        if (b.lerp32)
+            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, true>(b, w, ff, En, fz, pp, df, stream);
+        else
+            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream);
     } else if (b.periodic) {
         if (b.lerp32) launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream);
         else launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream);

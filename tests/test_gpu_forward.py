@@ -137,6 +137,43 @@ def test_scan_throughput_tolerance_certificates_c0():
           int(np.sum(lam <= 0)), flush=True)
 
 
+def test_scan_throughput_tolerance_certificates_c1_sampled():
+    """The paper-scale scans exactly as the benchmark runs them (threshold 1e-4
+    eV/A, FP32 interpolation arithmetic), trilinear and tricubic: 4,000 seeded
+    relaxed points each, checked against FIRE's stopping rule under the
+    oracle's FP64 force balance on the same FP32 grid.  The margin beyond
+    f_conv covers the FP32 arithmetic (below 1e-6 eV/A here)."""
+    w = W.config1()
+    ff32 = orc.build_ff(w.grid, w.probe, w.atoms).astype(np.float32)
+    res = ppm.relaxed_scan(w.grid, torch.as_tensor(ff32, device="cuda"), w.probe, w.fire,
+                           w.scan, dfp=w.df)
+    pp = res["pp"].cpu().numpy()
+    assert np.all(pp[..., 3] >= 0)                   # every point converged
+    rng = np.random.default_rng(2024)
+    n = 4000
+    ix, iy = rng.integers(0, w.scan.nx, n), rng.integers(0, w.scan.ny, n)
+    k = rng.integers(0, w.scan.nz, n)
+    from parity import anchors_for
+    A = anchors_for(w.scan, np.stack([ix, iy], axis=1))        # [n][nz][3]
+    A = A[np.arange(n), k]
+    r = A + np.asarray(w.probe.d0) + pp[k, iy, ix, :3]
+    gn, _ = orc.residual(w.grid, ff32.astype(np.float64), w.probe, A, r)
+    excess = float((gn - w.fire.f_conv).max())
+    print("C1 certificate: max |G| - f_conv", excess, flush=True)
+    assert np.all(gn < w.fire.f_conv + 2e-6)
+    # the tricubic scan on the energy channel, FP32 stencil contraction
+    E32 = np.ascontiguousarray(ff32[..., 3])
+    tri = ppm.relaxed_scan_tricubic(w.grid, torch.as_tensor(E32, device="cuda"), w.probe,
+                                    w.fire, w.scan)
+    pt = tri["pp"].cpu().numpy()
+    assert np.all(pt[..., 3] >= 0)
+    rt = A + np.asarray(w.probe.d0) + pt[k, iy, ix, :3]
+    gt, _ = orc.residual_tricubic(w.grid, E32.astype(np.float64), w.probe, A, rt)
+    excess = float((gt - w.fire.f_conv).max())
+    print("C1 tricubic certificate: max |G| - f_conv", excess, flush=True)
+    assert np.all(gt < w.fire.f_conv + 2e-6)
+
+
 def test_scan_zero_field_exact_rest():
     grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (30, 30, 90))
     ff = torch.zeros((90, 30, 30, 4), dtype=torch.float32, device="cuda")
