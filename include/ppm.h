@@ -217,6 +217,8 @@ ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_
  * stencil i-1..i+2; F = -grad of the interpolant.  x,y wrap on a periodic
  * grid; otherwise, and always in z, the point is clamped to the grid box:
  * outside [0, n-1] the force is continued constantly along that axis.
+ * The stencil weights and contraction are FP32 when fire->f_conv >= 1e-5 eV/A
+ * and FP64 otherwise, as for the trilinear combination of ppm_relaxed_scan.
  * in:  E[nz][ny][nx] from ppm_build_energy.  Outputs, errors: as ppm_relaxed_scan.
  */
 ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,
