@@ -316,8 +316,11 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         // lowest height still in progress among the wave's remaining lanes (a
         // lane's level k + done never decreases, so kmin only moves up)
         if constexpr (BOUNDED) {
+            // An active lane has level <= snz - 1 (a lane done at the last
+            // height has left), so the search stops at the wave's minimum; the
+            // bound also ends it if no lane is active here.
             const int level = k + (done ? 1 : 0);
-            while (__ballot(level == kmin) == 0) ++kmin;
+            while (kmin < a.snz && __ballot(level == kmin) == 0) ++kmin;
             held = done && k + 1 > kmin + a.drift;
         }
         if (!BOUNDED || !held) {
