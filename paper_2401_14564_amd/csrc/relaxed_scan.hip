@@ -30,6 +30,8 @@
 //    control flow, and cross-statement fusion would then round differently in
 //    each, while a batched scan must reproduce single scans bit for bit.
 #pragma clang fp contract(on)
+#include <atomic>
+
 #include "ppm.h"
 #include "ppm_device.h"
 #include "ppm_kernels.h"
@@ -507,20 +509,21 @@ DfWeights repad(const DfWeights &w, int m, int M)
 
 }  // namespace
 
-// Largest dynamic LDS allocation of one block on the current device (bytes).
+// Largest dynamic LDS allocation of one block on the current device (bytes),
+// queried once per device; concurrent first calls store the same value.
 size_t max_block_lds()
 {
-    static int cache[64];
+    static std::atomic<int> cache[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
-    if (cache[dev] == 0) {
-        int v = 0;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
                 hipSuccess || v <= 0)
             v = 65536;
-        cache[dev] = v;
+        cache[dev].store(v, std::memory_order_relaxed);
     }
-    return (size_t)cache[dev];
+    return (size_t)v;
 }
 
 // Opt a kernel in to more than 64 KiB of dynamic LDS.  A refusal is cleared
