@@ -278,6 +278,11 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     // a lane's own sequence of evaluations.
     bool done = false, held = false;
     int kmin = 0;
+    // corner forces of the lane's current cell, reloaded only when the probe
+    // enters another cell (most FIRE steps stay inside one voxel), so a wave's
+    // gathers carry only the lanes that moved
+    float3 cv[8];
+    uint32_t cell = 0xffffffffu;
     while (true) {
         double Gx = 0.0, Gy = 0.0, Gz = 0.0, g2 = 0.0;
         if (!BOUNDED || !held) {
@@ -286,12 +291,14 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
                 // issue the eight gathers, then evaluate the springs (independent
                 // of them) while they are in flight, then interpolate
                 const Cell c = locate<GEOM>(a, rx, ry, rz);
-                float3 v[8];
-                gather8<WIDE, GEOM == kOpen>(ff, c, v);
+                if (c.i000 != cell) {
+                    gather8<WIDE, GEOM == kOpen>(ff, c, cv);
+                    cell = c.i000;
+                }
                 __builtin_amdgcn_sched_barrier(0);   // keep the spring math ahead of the waits
                 tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
                 __builtin_amdgcn_sched_barrier(0);
-                trilerp<LERP32>(v, c, Sx, Sy, Sz);
+                trilerp<LERP32>(cv, c, Sx, Sy, Sz);
             } else {
                 tricubic_force<WIDE, LERP32>(a, En, rx, ry, rz, Sx, Sy, Sz);
                 tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
