@@ -69,7 +69,6 @@ struct ScanArgs {
     double dt0, dt_max, f_inc, f_dec, alpha0, f_alpha, inv_mass, f_conv2;
     int n_min, max_iter;
     int lerp32;               // 1: trilinear combination in FP32 (f_conv >= kLerp32MinFconv)
-    int drift;                // heights a lane may lead its wave's lowest unfinished height
     // tip lattice
     double x0, y0, sdx, sdy, z_top, sdz;
     int snx, sny, snz;

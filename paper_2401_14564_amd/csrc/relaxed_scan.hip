@@ -26,7 +26,7 @@
 //    per corner).
 //  * Multiply-adds are fused only within one expression (contract(on), placed
 //    before the includes so it also covers the device helpers): the kernel
-//    instances (tile shape, geometry, drift bound, batched or single) differ in
+//    instances (tile shape, geometry, precision, batched or single) differ in
 //    control flow, and cross-statement fusion would then round differently in
 //    each, while a batched scan must reproduce single scans bit for bit.
 #pragma clang fp contract(on)
@@ -40,15 +40,6 @@ namespace ppm {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
-
-// Drift bound of the scan loop (heights a lane may lead the lowest unfinished
-// height of its wave) where it is compiled in: the tricubic scan (64 loads per
-// evaluation) and the throughput-bound batched scan, which gain more from
-// coalesced gathers than they lose to waiting lanes.  The trilinear single scan
-// is latency-bound by its hardest wave and runs unbounded, without the
-// bookkeeping.  Measured on the paper-scale workload and a 64-molecule batch:
-// bound 1 beats 0 (height-synchronous), 2, 4 and unbounded on both.
-constexpr int kDrift = 1;
 
 // Trilinear combination of the eight corner values v[i + 2j + 4k] (gather8).
 // LERP32: combine in FP32.  The corners are FP32, so FP32 weights and sums add
@@ -144,10 +135,13 @@ __device__ __forceinline__ int cubic_clamp_cell(double u, int n, double &t)
 // WIDE: the energy grid has 2^30 voxels or more (4 GiB), so the loads need
 // 64-bit offsets; otherwise each of the 64 loads is a 32-bit byte offset (row
 // offset + column offset, both computed once) from the scalar base address.
+// vals/key: the stencil values of the lane's previous evaluation and the flat
+// index of their cell; the 64 values are reloaded only when the cell changes.
 template <bool WIDE, bool LERP32>
 __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *__restrict__ En,
-                                               double x, double y, double z, double &Fx,
-                                               double &Fy, double &Fz)
+                                               double x, double y, double z, float *vals,
+                                               uint32_t &key, double &Fx, double &Fy,
+                                               double &Fz)
 {
     using T = typename InterpReal<LERP32>::type;
     double tx, ty, tz;
@@ -164,49 +158,53 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
     cr_weights<T>((T)tx, wx, dwx);
     cr_weights<T>((T)ty, wy, dwy);
     cr_weights<T>((T)tz, wz, dwz);
-    int xs[4], ys[4], zs[4];
+    const uint32_t cell = (uint32_t)((iz * a.gny + iy) * a.gnx + ix);   // < 2^31 voxels
+    if (cell != key) {
+        key = cell;
+        int xs[4], ys[4], zs[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        int i = ix + s - 1, j = iy + s - 1, k = iz + s - 1;
-        if (a.periodic) {
-            i += (i < 0) ? a.gnx : 0;
-            i -= (i >= a.gnx) ? a.gnx : 0;
-            j += (j < 0) ? a.gny : 0;
-            j -= (j >= a.gny) ? a.gny : 0;
-        } else {
-            i = i < 0 ? 0 : (i > a.gnx - 1 ? a.gnx - 1 : i);
-            j = j < 0 ? 0 : (j > a.gny - 1 ? a.gny - 1 : j);
+        for (int s = 0; s < 4; ++s) {
+            int i = ix + s - 1, j = iy + s - 1, k = iz + s - 1;
+            if (a.periodic) {
+                i += (i < 0) ? a.gnx : 0;
+                i -= (i >= a.gnx) ? a.gnx : 0;
+                j += (j < 0) ? a.gny : 0;
+                j -= (j >= a.gny) ? a.gny : 0;
+            } else {
+                i = i < 0 ? 0 : (i > a.gnx - 1 ? a.gnx - 1 : i);
+                j = j < 0 ? 0 : (j > a.gny - 1 ? a.gny - 1 : j);
+            }
+            k = k < 0 ? 0 : (k > a.gnz - 1 ? a.gnz - 1 : k);
+            xs[s] = i;
+            ys[s] = j;
+            zs[s] = k;
         }
-        k = k < 0 ? 0 : (k > a.gnz - 1 ? a.gnz - 1 : k);
-        xs[s] = i;
-        ys[s] = j;
-        zs[s] = k;
-    }
-    // issue all 64 loads first, then contract (their latency overlaps)
-    float vals[64];
-    if (WIDE) {
+        // issue all 64 loads first, then contract (their latency overlaps)
+        if (WIDE) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const float *row = En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx;
+                for (int b = 0; b < 4; ++b) {
+                    const float *row = En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) vals[16 * c + 4 * b + i] = row[xs[i]];
-            }
-    } else {
-        const char *base = reinterpret_cast<const char *>(En);
-        uint32_t xo[4];
+                    for (int i = 0; i < 4; ++i) vals[16 * c + 4 * b + i] = row[xs[i]];
+                }
+        } else {
+            const char *base = reinterpret_cast<const char *>(En);
+            uint32_t xo[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) xo[i] = (uint32_t)xs[i] * 4u;
+            for (int i = 0; i < 4; ++i) xo[i] = (uint32_t)xs[i] * 4u;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t ro = (uint32_t)((zs[c] * a.gny + ys[b]) * a.gnx) * 4u;
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t ro = (uint32_t)((zs[c] * a.gny + ys[b]) * a.gnx) * 4u;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    vals[16 * c + 4 * b + i] = *reinterpret_cast<const float *>(base + (ro + xo[i]));
-            }
+                    for (int i = 0; i < 4; ++i)
+                        vals[16 * c + 4 * b + i] =
+                            *reinterpret_cast<const float *>(base + (ro + xo[i]));
+                }
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
     T gx = 0, gy = 0, gz = 0;
@@ -241,9 +239,8 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
 // height finishes and the frequency shift re-reads it.
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
 // from the energy grid En.  GEOM: grid geometry of the trilinear lookup
-// (GridGeom).  LERP32: FP32 interpolation arithmetic.  BOUNDED: lanes
-// keep within a.drift heights of the wave's lowest unfinished height.
-template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32, bool BOUNDED>
+// (GridGeom).  LERP32: FP32 interpolation arithmetic.
+template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
                                             float *__restrict__ fz_out,
@@ -263,29 +260,24 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     double u1x = 0.0, u1y = 0.0, u1z = 0.0;      // relaxed displacement of the previous height
     int npos = 0, it = 0;
 
-    // One loop iteration = one force evaluation of every working lane.  A lane
-    // whose probe has converged (or hit max_iter) records the height and starts
-    // its next height in the same iteration; the others take a FIRE step.  Both
+    // One loop iteration = one force evaluation of every lane.  A lane whose
+    // probe has converged (or hit max_iter) records the height and starts its
+    // next height in the same iteration; the others take a FIRE step.  Both
     // successor states are computed and merged by selects, so the loop has a
     // single back edge: with a conditional `continue` the compiler splits it
     // into a per-height inner loop, and every lane then waits at each height
     // for the slowest lane of its wave.
-    // Drift bound (BOUNDED): a lane may start height k+1 only while k+1 <= kmin + drift,
-    // kmin being the lowest height still in progress in the wave; until then it
-    // is held (no force evaluation, state unchanged).  Lanes then gather from at
-    // most drift+1 z-planes, which keeps the wave's loads coalesced and in L1;
-    // drift 0 is height-synchronous.  The bound changes only the schedule, never
-    // a lane's own sequence of evaluations.
-    bool done = false, held = false;
-    int kmin = 0;
-    // corner forces of the lane's current cell, reloaded only when the probe
-    // enters another cell (most FIRE steps stay inside one voxel), so a wave's
-    // gathers carry only the lanes that moved
+    // corner forces (trilinear) or stencil energies (tricubic) of the lane's
+    // current cell, reloaded only when the probe enters another cell (most
+    // FIRE steps stay inside one voxel), so a wave's gathers carry only the
+    // lanes that moved
     float3 cv[8];
+    float tv[INTERP == 0 ? 1 : 64];
     uint32_t cell = 0xffffffffu;
     while (true) {
-        double Gx = 0.0, Gy = 0.0, Gz = 0.0, g2 = 0.0;
-        if (!BOUNDED || !held) {
+        double Gx, Gy, Gz, g2;
+        bool done;
+        {
             double Sx, Sy, Sz, Tx, Ty, Tz;
             if (INTERP == 0) {
                 // issue the eight gathers, then evaluate the springs (independent
@@ -300,7 +292,7 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
                 __builtin_amdgcn_sched_barrier(0);
                 trilerp<LERP32>(cv, c, Sx, Sy, Sz);
             } else {
-                tricubic_force<WIDE, LERP32>(a, En, rx, ry, rz, Sx, Sy, Sz);
+                tricubic_force<WIDE, LERP32>(a, En, rx, ry, rz, tv, cell, Sx, Sy, Sz);
                 tip_force(a, rx - ax, ry - ay, rz - az, Tx, Ty, Tz);
             }
             Gx = Tx + Sx;
@@ -322,71 +314,59 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             }
         }
         if (done && k + 1 >= a.snz) break;
-        // lowest height still in progress among the wave's remaining lanes (a
-        // lane's level k + done never decreases, so kmin only moves up)
-        if constexpr (BOUNDED) {
-            // An active lane has level <= snz - 1 (a lane done at the last
-            // height has left), so the search stops at the wave's minimum; the
-            // bound also ends it if no lane is active here.
-            const int level = k + (done ? 1 : 0);
-            while (kmin < a.snz && __ballot(level == kmin) == 0) ++kmin;
-            held = done && k + 1 > kmin + a.drift;
-        }
-        if (!BOUNDED || !held) {
-            // (a) FIRE step.  Velocity update, branch-free (lanes of a wave disagree
-            // on the sign of P): from the second step on, P > 0 mixes v towards G
-            // and, after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
-            // the particle, shrinks dt and resets alpha.
-            const double P = Gx * vx + Gy * vy + Gz * vz;
-            const bool pos = (it > 0) && (P > 0.0);
-            const bool neg = (it > 0) && !(P > 0.0);
-            const double vn2 = vx * vx + vy * vy + vz * vz;
-            // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
-            // 1/sqrt (no Newton step) is accurate enough
-            const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
-            const double sc = pos ? mix : 0.0;
-            const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
-            double fvx = om * vx + sc * Gx;
-            double fvy = om * vy + sc * Gy;
-            double fvz = om * vz + sc * Gz;
-            const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
-            const bool grow = pos && fnpos > a.n_min;
-            const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
-            const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
-            const double h = fdt * a.inv_mass;
-            fvx += Gx * h;
-            fvy += Gy * h;
-            fvz += Gz * h;
-            const double frx = rx + fvx * fdt, fry = ry + fvy * fdt, frz = rz + fvz * fdt;
+        // (a) FIRE step.  Velocity update, branch-free (lanes of a wave disagree
+        // on the sign of P): from the second step on, P > 0 mixes v towards G
+        // and, after n_min such steps, grows dt and shrinks alpha; P <= 0 stops
+        // the particle, shrinks dt and resets alpha.
+        const double P = Gx * vx + Gy * vy + Gz * vz;
+        const bool pos = (it > 0) && (P > 0.0);
+        const bool neg = (it > 0) && !(P > 0.0);
+        const double vn2 = vx * vx + vy * vy + vz * vz;
+        // alpha |v| / |G|: a step-size heuristic, so the hardware estimate of
+        // 1/sqrt (no Newton step) is accurate enough
+        const double mix = alpha * vn2 * __builtin_amdgcn_rsq(vn2 * g2);
+        const double sc = pos ? mix : 0.0;
+        const double om = pos ? 1.0 - alpha : (neg ? 0.0 : 1.0);
+        double fvx = om * vx + sc * Gx;
+        double fvy = om * vy + sc * Gy;
+        double fvz = om * vz + sc * Gz;
+        const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
+        const bool grow = pos && fnpos > a.n_min;
+        const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
+        const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
+        const double h = fdt * a.inv_mass;
+        fvx += Gx * h;
+        fvy += Gy * h;
+        fvz += Gz * h;
+        const double frx = rx + fvx * fdt, fry = ry + fvy * fdt, frz = rz + fvz * fdt;
 
-            // (b) next height.  Warm start: the next height starts from its anchor
-            // plus the relaxed displacement extrapolated linearly from this height
-            // and the previous one (just the displacement after the first height);
-            // v and alpha restart, dt carries over (not below dt0).
-            const double ux = rx - ax, uy = ry - ay, uz = rz - az;
-            const bool lin = k >= 1;
-            const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
-                         ez = lin ? uz - u1z : 0.0;
-            const int kn = k + 1;
-            const double azn = a.z_top - kn * a.sdz;
+        // (b) next height.  Warm start: the next height starts from its anchor
+        // plus the relaxed displacement extrapolated linearly from this height
+        // and the previous one (just the displacement after the first height);
+        // v and alpha restart, dt carries over (not below dt0).
+        const double ux = rx - ax, uy = ry - ay, uz = rz - az;
+        const bool lin = k >= 1;
+        const double ex = lin ? ux - u1x : 0.0, ey = lin ? uy - u1y : 0.0,
+                     ez = lin ? uz - u1z : 0.0;
+        const int kn = k + 1;
+        const double azn = a.z_top - kn * a.sdz;
 
-            // merge
-            rx = done ? ax + (ux + ex) : frx;
-            ry = done ? ay + (uy + ey) : fry;
-            rz = done ? azn + (uz + ez) : frz;
-            vx = done ? 0.0 : fvx;
-            vy = done ? 0.0 : fvy;
-            vz = done ? 0.0 : fvz;
-            dt = done ? fmax(dt, a.dt0) : fdt;
-            alpha = done ? a.alpha0 : falpha;
-            npos = done ? 0 : fnpos;
-            it = done ? 0 : it + 1;
-            u1x = done ? ux : u1x;
-            u1y = done ? uy : u1y;
-            u1z = done ? uz : u1z;
-            az = done ? azn : az;
-            k = done ? kn : k;
-        }
+        // merge
+        rx = done ? ax + (ux + ex) : frx;
+        ry = done ? ay + (uy + ey) : fry;
+        rz = done ? azn + (uz + ez) : frz;
+        vx = done ? 0.0 : fvx;
+        vy = done ? 0.0 : fvy;
+        vz = done ? 0.0 : fvz;
+        dt = done ? fmax(dt, a.dt0) : fdt;
+        alpha = done ? a.alpha0 : falpha;
+        npos = done ? 0 : fnpos;
+        it = done ? 0 : it + 1;
+        u1x = done ? ux : u1x;
+        u1y = done ? uy : u1y;
+        u1z = done ? uz : u1z;
+        az = done ? azn : az;
+        k = done ? kn : k;
     }
 
     if (STAGE && fz_out) {
@@ -410,8 +390,9 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
 
 template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32>
 __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
-    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff, const float *__restrict__ En,
-    float *__restrict__ fz_out, float4 *__restrict__ pp_out, float *__restrict__ df_out)
+    const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff,
+    const float *__restrict__ En, float *__restrict__ fz_out, float4 *__restrict__ pp_out,
+    float *__restrict__ df_out)
 {
     extern __shared__ float s_col[];   // STAGE: [snz][TX * TY]
     // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
@@ -431,8 +412,8 @@ __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
     const int ix = (tile % tiles_x) * TX + (int)threadIdx.x;
     const int iy = (tile / tiles_x) * TY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32, INTERP != 0>(
-        a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col, En);
+    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32>(a, wts, ix, iy, lane, ff, fz_out,
+                                                            pp_out, df_out, s_col, En);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
@@ -464,7 +445,7 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
     const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32, true>(
+    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32>(
         a, wts, ix, iy, lane, arena + M.ff_offset, fz_arena ? fz_arena + J.fz_offset : nullptr,
         nullptr, df_arena ? df_arena + J.df_offset : nullptr, s_col);
 }
@@ -611,11 +592,9 @@ void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff
     }
 }
 
-hipError_t launch_relaxed_scan(const ScanArgs &args, const DfWeights &w, const float4 *ff,
+hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    ScanArgs a = args;
-    a.drift = 0;   // unbounded (no bookkeeping compiled in)
     const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
         launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
@@ -624,12 +603,10 @@ hipError_t launch_relaxed_scan(const ScanArgs &args, const DfWeights &w, const f
     return hipGetLastError();
 }
 
-hipError_t launch_relaxed_scan_tricubic(const ScanArgs &args, const DfWeights &w,
+hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w,
                                         const float *En, float *fz, float4 *pp, float *df,
                                         hipStream_t stream)
 {
-    ScanArgs a = args;
-    a.drift = kDrift;
     const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
         launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
@@ -662,7 +639,7 @@ void launch_scan_batch_mode(const ScanArgs &proto, const DfWeights &w, const ppm
     }
 }
 
-hipError_t launch_relaxed_scan_batch(const ScanArgs &args, const DfWeights &w,
+hipError_t launch_relaxed_scan_batch(const ScanArgs &proto, const DfWeights &w,
                                      const ppm_batch_mol *mols_dev,
                                      const ppm_batch_scan *jobs_dev, int n_jobs,
                                      long long n_tiles, int max_nz, bool wide,
@@ -670,8 +647,6 @@ hipError_t launch_relaxed_scan_batch(const ScanArgs &args, const DfWeights &w,
                                      hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
-    ScanArgs proto = args;
-    proto.drift = kDrift;
     const long long gx = n_tiles < 65536 ? n_tiles : 65536;
     const long long gy = (n_tiles + gx - 1) / gx;
     dim3 grid((unsigned)gx, (unsigned)gy, 1);
