@@ -120,10 +120,10 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
                 const double2 x = buf[l * LS + j + t * nb];
                 u[t] = (t == 0) ? x : cmul(x, cconj_if(tw[k * t * stride], inverse));
             }
-            if (P == 2) {
+            if constexpr (P == 2) {
                 y[r][0] = cadd(u[0], u[1]);
                 y[r][1] = csub(u[0], u[1]);
-            } else if (P == 4) {
+            } else if constexpr (P == 4) {
                 // (sign i)^(s t): forward sign -1, inverse +1
                 const double2 a = cadd(u[0], u[2]), b2 = csub(u[0], u[2]);
                 const double2 c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
@@ -132,7 +132,7 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
                 y[r][1] = cadd(b2, id);
                 y[r][2] = csub(a, c);
                 y[r][3] = csub(b2, id);
-            } else if (P == 3) {
+            } else if constexpr (P == 3) {
                 // w = exp(-+2 pi i / 3): y1,2 = u0 - a/2 -+ i sqrt(3)/2 b
                 const double2 a = cadd(u[1], u[2]), d = csub(u[1], u[2]);
                 const double2 t = make_double2(u[0].x - 0.5 * a.x, u[0].y - 0.5 * a.y);

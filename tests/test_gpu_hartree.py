@@ -51,10 +51,11 @@ def test_tip_density_matches_oracle():
         assert np.all(d <= 2.0 ** -23 * np.abs(ref) + 1e-30 * np.abs(ref).max()), (q_pp, q_zz, s)
 
 
-@pytest.mark.parametrize("n", [(24, 20, 18), (9, 25, 16), (1000, 3, 2), (2, 2, 2), (5, 48, 27)])
+@pytest.mark.parametrize("n", [(24, 20, 18), (9, 25, 16), (1000, 3, 2), (2, 2, 2), (5, 48, 27),
+                               (6, 2, 1000), (3, 9, 5)])
 def test_hartree_full_grid_against_oracle(n):
-    """Mixed radices (4, 2, 3, 5), a 1000-point axis (three lines per block), the
-    smallest grid, and odd lengths."""
+    """Mixed radices (4, 2, 3, 5), 1000-point axes along x and z (three lines per
+    block), the smallest grid, odd lengths on every axis, and ny = 2."""
     g = W.Grid((0.3, -0.1, -2.0), (0.31, 0.29, 0.33), n)
     V, rho = _inputs(g, seed=sum(n))
     ref = orc.hartree_ff(g, rho, V)
