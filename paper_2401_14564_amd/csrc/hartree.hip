@@ -26,7 +26,8 @@
 //             ff = (Re B, Im B, Im A, Re A) to the grid (or adds to it)
 //
 // FFT kernel: a block transforms L lines of one axis in LDS with a mixed-radix
-// (4, 2, 3, 5) Stockham sequence; each stage reads its inputs into registers,
+// (16, 15, 4, 2, 3, 5) Stockham sequence, radix 16 and 15 computed in registers
+// as 4 x 4 and 3 x 5; each stage reads its inputs into registers,
 // synchronises, and writes its outputs back (one LDS buffer plus a table of
 // the n twiddles exp(-2 pi i t / n), made with sincospi).  x-lines are
 // contiguous; y- and z-lines are loaded L at a time from L consecutive
@@ -96,6 +97,86 @@ __device__ __forceinline__ int fdiv(int x, unsigned rcp)
     return rcp ? (int)__umulhi((unsigned)x, rcp) : x;
 }
 
+// In-place DFT of u[0 .. P-1] (forward sign -1, inverse +1), natural order in
+// and out.  P = 2, 3, 4, 5: butterflies on exact constants.  P = 16 = 4 x 4 and
+// P = 15 = 3 x 5: Cooley-Tukey in registers, X[k1 + N1 k2] =
+// sum_b W_P^(b k1) W_N2^(b k2) sum_a u[N2 a + b] W_N1^(a k1), the internal
+// twiddles W_P^j read from the line's twiddle table (tw[j n / P]).
+template <int P>
+__device__ __forceinline__ void dft(double2 *u, bool inverse, const double2 *tw, int n)
+{
+    if constexpr (P == 2) {
+        const double2 a = u[0], b = u[1];
+        u[0] = cadd(a, b);
+        u[1] = csub(a, b);
+    } else if constexpr (P == 4) {
+        // (sign i)^(s t): forward sign -1, inverse +1
+        const double2 a = cadd(u[0], u[2]), b2 = csub(u[0], u[2]);
+        const double2 c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
+        const double2 id = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+        u[0] = cadd(a, c);
+        u[1] = cadd(b2, id);
+        u[2] = csub(a, c);
+        u[3] = csub(b2, id);
+    } else if constexpr (P == 3) {
+        // w = exp(-+2 pi i / 3): y1,2 = u0 - a/2 -+ i sqrt(3)/2 b
+        const double2 a = cadd(u[1], u[2]), d = csub(u[1], u[2]);
+        const double2 t = make_double2(u[0].x - 0.5 * a.x, u[0].y - 0.5 * a.y);
+        const double h = 0.86602540378443864676;                 // sqrt(3)/2
+        const double2 ib = inverse ? make_double2(-h * d.y, h * d.x)
+                                   : make_double2(h * d.y, -h * d.x);   // -+ i h d
+        u[0] = cadd(u[0], a);
+        u[1] = cadd(t, ib);
+        u[2] = csub(t, ib);
+    } else if constexpr (P == 5) {
+        // radix 5 from the symmetric pairs u1 +- u4, u2 +- u3 and the
+        // cosines/sines of 2 pi/5 and 4 pi/5
+        const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+        const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+        const double2 a1 = cadd(u[1], u[4]), b1 = csub(u[1], u[4]);
+        const double2 a2 = cadd(u[2], u[3]), b2 = csub(u[2], u[3]);
+        const double2 t1 = make_double2(u[0].x + c1 * a1.x + c2 * a2.x,
+                                        u[0].y + c1 * a1.y + c2 * a2.y);
+        const double2 t2 = make_double2(u[0].x + c2 * a1.x + c1 * a2.x,
+                                        u[0].y + c2 * a1.y + c1 * a2.y);
+        const double2 t3 = make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+        const double2 t4 = make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+        // forward: y1 = t1 - i t3, y4 = t1 + i t3, y2 = t2 - i t4, y3 = t2 + i t4
+        const double2 i3 = inverse ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
+        const double2 i4 = inverse ? make_double2(-t4.y, t4.x) : make_double2(t4.y, -t4.x);
+        u[0] = make_double2(u[0].x + a1.x + a2.x, u[0].y + a1.y + a2.y);
+        u[1] = cadd(t1, i3);
+        u[4] = csub(t1, i3);
+        u[2] = cadd(t2, i4);
+        u[3] = csub(t2, i4);
+    } else {
+        static_assert(P == 16 || P == 15, "radix");
+        constexpr int N1 = P == 16 ? 4 : 3, N2 = P == 16 ? 4 : 5;
+        const int step = n / P;
+        double2 y[N2][N1];
+#pragma unroll
+        for (int b = 0; b < N2; ++b) {
+            double2 v[N1];
+#pragma unroll
+            for (int a = 0; a < N1; ++a) v[a] = u[N2 * a + b];
+            dft<N1>(v, inverse, tw, n);
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1)
+                y[b][k1] = (b == 0 || k1 == 0)
+                               ? v[k1] : cmul(v[k1], cconj_if(tw[b * k1 * step], inverse));
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+            double2 z[N2];
+#pragma unroll
+            for (int b = 0; b < N2; ++b) z[b] = y[b][k1];
+            dft<N2>(z, inverse, tw, n);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) u[k1 + N1 * k2] = z[k2];
+        }
+    }
+}
+
 // One Stockham stage of radix P over L lines of length n held in LDS (line
 // stride LS).  m = product of the radices of the previous stages; rcp_nb and
 // rcp_m the reciprocals of n/P and m.
@@ -120,50 +201,9 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int n
                 const double2 x = buf[l * LS + j + t * nb];
                 u[t] = (t == 0) ? x : cmul(x, cconj_if(tw[k * t * stride], inverse));
             }
-            if constexpr (P == 2) {
-                y[r][0] = cadd(u[0], u[1]);
-                y[r][1] = csub(u[0], u[1]);
-            } else if constexpr (P == 4) {
-                // (sign i)^(s t): forward sign -1, inverse +1
-                const double2 a = cadd(u[0], u[2]), b2 = csub(u[0], u[2]);
-                const double2 c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
-                const double2 id = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
-                y[r][0] = cadd(a, c);
-                y[r][1] = cadd(b2, id);
-                y[r][2] = csub(a, c);
-                y[r][3] = csub(b2, id);
-            } else if constexpr (P == 3) {
-                // w = exp(-+2 pi i / 3): y1,2 = u0 - a/2 -+ i sqrt(3)/2 b
-                const double2 a = cadd(u[1], u[2]), d = csub(u[1], u[2]);
-                const double2 t = make_double2(u[0].x - 0.5 * a.x, u[0].y - 0.5 * a.y);
-                const double h = 0.86602540378443864676;                 // sqrt(3)/2
-                const double2 ib = inverse ? make_double2(-h * d.y, h * d.x)
-                                           : make_double2(h * d.y, -h * d.x);   // -+ i h d
-                y[r][0] = cadd(u[0], a);
-                y[r][1] = cadd(t, ib);
-                y[r][2] = csub(t, ib);
-            } else {
-                // radix 5 from the symmetric pairs u1 +- u4, u2 +- u3 and the
-                // cosines/sines of 2 pi/5 and 4 pi/5
-                const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-                const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-                const double2 a1 = cadd(u[1], u[4]), b1 = csub(u[1], u[4]);
-                const double2 a2 = cadd(u[2], u[3]), b2 = csub(u[2], u[3]);
-                const double2 t1 = make_double2(u[0].x + c1 * a1.x + c2 * a2.x,
-                                                u[0].y + c1 * a1.y + c2 * a2.y);
-                const double2 t2 = make_double2(u[0].x + c2 * a1.x + c1 * a2.x,
-                                                u[0].y + c2 * a1.y + c1 * a2.y);
-                const double2 t3 = make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
-                const double2 t4 = make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
-                // forward: y1 = t1 - i t3, y4 = t1 + i t3, y2 = t2 - i t4, y3 = t2 + i t4
-                const double2 i3 = inverse ? make_double2(-t3.y, t3.x) : make_double2(t3.y, -t3.x);
-                const double2 i4 = inverse ? make_double2(-t4.y, t4.x) : make_double2(t4.y, -t4.x);
-                y[r][0] = make_double2(u[0].x + a1.x + a2.x, u[0].y + a1.y + a2.y);
-                y[r][1] = cadd(t1, i3);
-                y[r][4] = csub(t1, i3);
-                y[r][2] = cadd(t2, i4);
-                y[r][3] = csub(t2, i4);
-            }
+            dft<P>(u, inverse, tw, n);
+#pragma unroll
+            for (int t = 0; t < P; ++t) y[r][t] = u[t];
         }
     }
     __syncthreads();
@@ -243,7 +283,9 @@ __global__ __launch_bounds__(kFftThreads) void fft_axis_kernel(double2 *__restri
     for (int s = 0; s < plan.n_stages; ++s) {
         const int P = plan.radix[s];
         const unsigned rn = plan.rcp_nb[s], rm = plan.rcp_m[s];
-        if (P == 4) fft_stage<4>(buf, tw, n, m, L, LS, inv, rn, rm);
+        if (P == 16) fft_stage<16>(buf, tw, n, m, L, LS, inv, rn, rm);
+        else if (P == 15) fft_stage<15>(buf, tw, n, m, L, LS, inv, rn, rm);
+        else if (P == 4) fft_stage<4>(buf, tw, n, m, L, LS, inv, rn, rm);
         else if (P == 2) fft_stage<2>(buf, tw, n, m, L, LS, inv, rn, rm);
         else if (P == 3) fft_stage<3>(buf, tw, n, m, L, LS, inv, rn, rm);
         else fft_stage<5>(buf, tw, n, m, L, LS, inv, rn, rm);
@@ -415,8 +457,10 @@ bool fft_plan(int n, FftPlan *p)
     p->n = n;
     p->n_stages = 0;
     int r = n;
-    const int radices[4] = {4, 2, 3, 5};
-    for (int k = 0; k < 4; ++k) {
+    // 16 = 4 x 4 and 15 = 3 x 5 first: each is one LDS round trip for what would
+    // be two stages (a 240-point line takes two stages instead of four)
+    const int radices[6] = {16, 15, 4, 2, 3, 5};
+    for (int k = 0; k < 6; ++k) {
         const int P = radices[k];
         while (r % P == 0) {
             if (p->n_stages >= kMaxFftStages) return false;
