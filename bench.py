@@ -277,7 +277,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 grid / f64 relaxation",
+        "dtype": "f32 grid and interpolation / f64 relaxation",
         "data": "synthetic (seeded 60-atom molecule, random-free tip lattice)",
         "config": {"workload": "paper-scale plain method: 60 atoms, grid 240^3 at 0.1 A, "
                                "scan 240x240 tips x 100 heights, FIRE f_conv 1e-4 eV/A, "
