@@ -11,7 +11,11 @@
 // Design:
 //  * One lane per tip column; a block covers a compact tile of columns (16 x 16,
 //    four waves, for single scans; 8 x 8 for batches) so its gathers touch
-//    neighbouring voxels.  Tiles are
+//    neighbouring voxels.  Single scans of open grids add a fifth, helper wave
+//    that loads the planes the block's probes are about to enter into L2 (the
+//    block publishes its per-lane progress in LDS): a gather instruction waits
+//    for the slowest of the cache lines it touches, and a first touch of a
+//    plane otherwise goes past L2.  Tiles are
 //    assigned so that consecutive tiles land on the same XCD (the hardware
 //    deals blocks round-robin over 8 XCDs), which keeps a tile neighbourhood's
 //    force-field band in one L2.
@@ -240,13 +244,14 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
 // from the energy grid En.  GEOM: grid geometry of the trilinear lookup
 // (GridGeom).  LERP32: FP32 interpolation arithmetic.
-template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32>
+template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32, bool PROG = false>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
                                             float *__restrict__ fz_out,
                                             float4 *__restrict__ pp_out,
                                             float *__restrict__ df_out, float *s_col,
-                                            const float *__restrict__ En = nullptr)
+                                            const float *__restrict__ En = nullptr,
+                                            int *s_prog = nullptr)
 {
     const size_t plane = (size_t)a.snx * a.sny;
     const size_t col = (size_t)iy * a.snx + ix;
@@ -307,6 +312,9 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
                 const size_t o = (size_t)k * plane + col;
                 if (STAGE) s_col[k * NL + lane] = fzv;
                 else if (fz_out) fz_out[o] = fzv;
+                if (PROG)
+                    __hip_atomic_store(s_prog + lane, k + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (pp_out)
                     pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
                                             (float)(rz - az - a.d0z),
@@ -388,8 +396,82 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
     }
 }
 
-template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32>
-__global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
+// Grid prefetch by one extra wave per block (single scans of open grids): the
+// heights ahead of the block's fastest lane whose planes are loaded, the
+// lateral and vertical margins (Angstrom) around the tile's probe rest
+// positions, and a bound on the polls so that the wave always ends.
+constexpr int kPfAhead = 3;
+constexpr double kPfHalo = 1.0, kPfZMargin = 0.5;
+constexpr int kPfMaxPolls = 1 << 22;
+
+// The helper wave reads the block's progress (s_prog[lane]: the height the lane
+// works on, snz once its column is done) and loads one word of every 64-byte
+// segment of the planes the probes will reach next, with device scope (they
+// bypass the CU's L1 and stay in L2), so that the compute waves' gathers find
+// them in L2.  The values are not used.  hl: the helper's lane, 0..63.
+template <int TX, int TY, typename T>
+__device__ void prefetch_planes(const ScanArgs &a, const T *__restrict__ grid, int tx0,
+                                int ty0, const int *s_prog, int hl)
+{
+    constexpr int kSeg = 64 / (int)sizeof(T);   // voxels per 64-byte segment
+    auto vox = [](double u, int n) { return (int)floor(fmin(fmax(u, 0.0), (double)(n - 1))); };
+    const double xl = a.x0 + tx0 * a.sdx + a.d0x, xh = xl + (TX - 1) * a.sdx;
+    const double yl = a.y0 + ty0 * a.sdy + a.d0y, yh = yl + (TY - 1) * a.sdy;
+    const int ix0 = vox(fma(xl - kPfHalo, a.ihx, a.oxi), a.gnx) & ~(kSeg - 1);
+    const int ix1 = min(vox(fma(xh + kPfHalo, a.ihx, a.oxi), a.gnx) + 1, a.gnx - 1);
+    const int iy0 = vox(fma(yl - kPfHalo, a.ihy, a.oyi), a.gny);
+    const int iy1 = min(vox(fma(yh + kPfHalo, a.ihy, a.oyi), a.gny) + 1, a.gny - 1);
+    const int nseg = (ix1 - ix0) / kSeg + 1;
+    const int per_plane = nseg * (iy1 - iy0 + 1);
+    int zlo = min(vox(fma(a.z_top + a.d0z + kPfZMargin, a.ihz, a.ozi), a.gnz) + 1, a.gnz - 1) + 1;
+    unsigned acc = 0;
+    for (int poll = 0; poll < kPfMaxPolls; ++poll) {
+        int kmin = a.snz, kmax = 0;
+        for (int j = hl; j < TX * TY; j += 64) {
+            const int p = __hip_atomic_load(s_prog + j, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            kmin = min(kmin, p);
+            kmax = max(kmax, p);
+        }
+        for (int o = 32; o; o >>= 1) {
+            kmin = min(kmin, __shfl_xor(kmin, o));
+            kmax = max(kmax, __shfl_xor(kmax, o));
+        }
+        if (kmin >= a.snz) break;
+        const int target = min(kmax + kPfAhead, a.snz - 1);
+        const int izl =
+            vox(fma(a.z_top - target * a.sdz + a.d0z - kPfZMargin, a.ihz, a.ozi), a.gnz);
+        if (izl < zlo) {
+            const int total = (zlo - izl) * per_plane;
+            for (int t0 = 0; t0 < total; t0 += 8 * 64) {
+                unsigned v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int t = t0 + j * 64 + hl;
+                    v[j] = 0;
+                    if (t < total) {
+                        const int iz = zlo - 1 - t / per_plane;
+                        const int r = t % per_plane;
+                        const int y = iy0 + r / nseg;
+                        const int x = min(ix0 + kSeg * (r % nseg), a.gnx - 1);
+                        const size_t idx = ((size_t)iz * a.gny + y) * a.gnx + x;
+                        v[j] = __hip_atomic_load(reinterpret_cast<const unsigned *>(grid + idx),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc += v[j];
+            }
+            zlo = izl;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    asm volatile("" ::"v"(acc));
+}
+
+template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32,
+          bool PF = false>
+__global__ __launch_bounds__(TX * TY + (PF ? 64 : 0)) void relaxed_scan_kernel(
     const ScanArgs a, const DfWeights wts, const float4 *__restrict__ ff,
     const float *__restrict__ En, float *__restrict__ fz_out, float4 *__restrict__ pp_out,
     float *__restrict__ df_out)
@@ -411,9 +493,24 @@ __global__ __launch_bounds__(TX * TY) void relaxed_scan_kernel(
     const int tiles_x = (a.snx + TX - 1) / TX;
     const int ix = (tile % tiles_x) * TX + (int)threadIdx.x;
     const int iy = (tile / tiles_x) * TY + (int)threadIdx.y;
+    int *s_prog = reinterpret_cast<int *>(s_col + (STAGE ? (size_t)a.snz * TX * TY : 0));
+    if constexpr (PF) {
+        // threads with threadIdx.y >= TY form the helper wave; s_prog[lane] is
+        // the height lane works on (snz for lanes without a column)
+        if (lane < TX * TY) s_prog[lane] = (ix < a.snx && iy < a.sny) ? 0 : a.snz;
+        __syncthreads();
+        if ((int)threadIdx.y >= TY) {
+            const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
+            if constexpr (INTERP == 0)
+                prefetch_planes<TX, TY>(a, ff, tx0, ty0, s_prog, lane - TX * TY);
+            else
+                prefetch_planes<TX, TY>(a, En, tx0, ty0, s_prog, lane - TX * TY);
+            return;
+        }
+    }
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32>(a, wts, ix, iy, lane, ff, fz_out,
-                                                            pp_out, df_out, s_col, En);
+    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32, PF>(
+        a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col, En, s_prog);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
@@ -525,28 +622,46 @@ void allow_lds(Kernel kernel, size_t bytes)
         (void)hipGetLastError();
 }
 
+template <int TX, int TY, bool WIDE, int INTERP, int GEOM, bool LERP32, bool PF>
+void launch_scan_tile(const ScanArgs &b, bool stage, const DfWeights &w, const float4 *ff,
+                      const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
+{
+    dim3 block(TX, TY + (PF ? 64 / TX : 0), 1);
+    dim3 grid((unsigned)(((b.snx + TX - 1) / TX) * ((b.sny + TY - 1) / TY)), 1, 1);
+    const size_t prog = PF ? (size_t)TX * TY * sizeof(int) : 0;
+    if (stage) {
+        const size_t lds = (size_t)b.snz * TX * TY * sizeof(float) + prog;
+        auto kernel = relaxed_scan_kernel<TX, TY, true, WIDE, INTERP, GEOM, LERP32, PF>;
+        allow_lds(kernel, lds);
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, b, w, ff, En, fz, pp, df);
+    } else {
+        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, false, WIDE, INTERP, GEOM, LERP32, PF>),
+                           grid, block, prog, stream, b, w, ff, En, fz, pp, df);
+    }
+}
+
+// The helper wave's plane windows assume an open grid (no wrap in x, y).
 template <int TX, int TY, bool WIDE, int INTERP, int GEOM, bool LERP32>
 void launch_scan_geom(const ScanArgs &b, bool stage, const DfWeights &w, const float4 *ff,
                       const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
 {
-    dim3 block(TX, TY, 1);
-    dim3 grid((unsigned)(((b.snx + TX - 1) / TX) * ((b.sny + TY - 1) / TY)), 1, 1);
-    if (stage) {
-        const size_t lds = (size_t)b.snz * TX * TY * sizeof(float);
-        auto kernel = relaxed_scan_kernel<TX, TY, true, WIDE, INTERP, GEOM, LERP32>;
-        allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, grid, block, lds, stream, b, w, ff, En, fz, pp, df);
-    } else {
-        hipLaunchKernelGGL((relaxed_scan_kernel<TX, TY, false, WIDE, INTERP, GEOM, LERP32>), grid,
-                           block, 0, stream, b, w, ff, En, fz, pp, df);
+    if constexpr (GEOM == kOpen || (INTERP != 0 && GEOM == kRuntimeGeom)) {
+        if (!b.periodic) {
+            launch_scan_tile<TX, TY, WIDE, INTERP, GEOM, LERP32, true>(b, stage, w, ff, En, fz,
+                                                                        pp, df, stream);
+            return;
+        }
     }
+    launch_scan_tile<TX, TY, WIDE, INTERP, GEOM, LERP32, false>(b, stage, w, ff, En, fz, pp, df,
+                                                                 stream);
 }
 
 // Block shape: 16 x 16 lanes (four waves, one per SIMD of the CU that runs the
-// block).  The kernel's time is the serial FIRE chain of its hardest columns,
-// so those must not share a SIMD; one-wave blocks leave the pairing of waves on
-// SIMDs to the dispatcher.  Fz is staged in LDS when the block's columns fit
-// (up to 160 heights in gfx950's 160 KiB); beyond that the fz output is
+// block, plus the helper wave on open grids).  The kernel's time is the serial
+// FIRE chain of its hardest columns, so those must not share a SIMD; one-wave
+// blocks leave the pairing of waves on SIMDs to the dispatcher.  Fz is staged in
+// LDS when the block's columns fit (up to 159 heights in gfx950's 160 KiB beside
+// the progress array); beyond that the fz output is
 // written directly (and re-read for the frequency shift), or, without fz,
 // 8 x 8 blocks stage up to 256 heights.
 template <bool WIDE, int INTERP, int GEOM, bool LERP32>
@@ -560,7 +675,7 @@ void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, c
     if (!fz && !want_df)
         launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, false, sw, ff, En, fz, pp, dfo,
                                                              stream);
-    else if (column * 256 <= max_block_lds())
+    else if ((column + sizeof(int)) * 256 <= max_block_lds())
         launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, true, sw, ff, En, fz, pp, dfo,
                                                              stream);
     else if (fz)
