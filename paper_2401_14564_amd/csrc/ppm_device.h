@@ -38,17 +38,20 @@ struct Cell {
 };
 
 // Cell of a grid coordinate along an axis clamped to its first/last cell:
-// index in [0, n-2], t in [0, 1]; outside the grid the field is continued
-// constantly (in = false).  The coordinate is clamped to [0, n-1] first (fmax
-// returns the non-NaN operand, so NaN lands at 0, in the first cell), then the
-// cell index to n-2, so u >= n-1 gives the last cell at t = 1.
+// index in [0, n-2], t in [0, 1); outside the grid the field is continued
+// constantly (in = false).  The coordinate is clamped to [0, top] first, top
+// the largest double below n-1 (fmax returns the non-NaN operand, so NaN lands
+// at 0, in the first cell); then the truncation is the floor and at most n-2,
+// and u >= n-1 gives the last cell at t = 1 - ulp(n-1), within 1e-13 of the
+// edge value.
 __device__ __forceinline__ int clamp_cell(double u, int n, double &t, bool &in)
 {
     in = (u >= 0.0) && (u < (double)(n - 1));
-    const double uc = fmin(fmax(u, 0.0), (double)(n - 1));
-    const double f = fmin(floor(uc), (double)(n - 2));
-    t = uc - f;
-    return (int)f;
+    const double top =
+        __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, (double)(n - 1)) - 1u);
+    const double uc = fmin(fmax(u, 0.0), top);
+    t = __builtin_amdgcn_fract(uc);
+    return (int)uc;
 }
 
 // Cell of a grid coordinate along a periodic axis: floor(u) mod n and u - floor(u).
