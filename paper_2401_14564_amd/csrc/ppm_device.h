@@ -150,6 +150,24 @@ __device__ __forceinline__ void gather8(const float4 *__restrict__ ff, const Cel
         v[5] = ld(p01 + 16);
         v[6] = ld(p11);
         v[7] = ld(p11 + 16);
+        // keep the offsets live past the loads: a load whose destination is the
+        // address register of the load before it costs a wait state on gfx950,
+        // which the register allocator would otherwise create
+        asm volatile("" ::"v"(o00), "v"(o10), "v"(o01), "v"(o11));
+    } else if constexpr (!WIDE) {
+        const char *b = reinterpret_cast<const char *>(ff);
+        uint32_t o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            o[k] = (c.i000 + ((k & 1) ? (uint32_t)c.dx1 : 0u) + ((k & 2) ? (uint32_t)c.dy1 : 0u) +
+                    ((k & 4) ? (uint32_t)c.dz1 : 0u)) * 16u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float4 *q = reinterpret_cast<const float4 *>(b + o[k]);
+            v[k] = make_float3(q->x, q->y, q->z);
+        }
+        asm volatile("" ::"v"(o[0]), "v"(o[1]), "v"(o[2]), "v"(o[3]), "v"(o[4]), "v"(o[5]),
+                     "v"(o[6]), "v"(o[7]));
     } else {
         const uint32_t i0 = c.i000;
         v[0] = corner<WIDE>(ff, i0);
