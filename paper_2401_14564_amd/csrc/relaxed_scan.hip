@@ -163,6 +163,12 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
     cr_weights<T>((T)ty, wy, dwy);
     cr_weights<T>((T)tz, wz, dwz);
     const uint32_t cell = (uint32_t)((iz * a.gny + iy) * a.gnx + ix);   // < 2^31 voxels
+    // open x axis with n >= 4: every stencil row is read as four contiguous voxels
+    // from bx = clamp(ix - 1, 0, n - 4), one 16-byte load per row; at the two edge
+    // cells the clamped stencil repeats an edge voxel, which is folded into the
+    // x weights below (shift = -1: nodes 0,0,1,2; +1: nodes n-3,n-2,n-1,n-1)
+    const bool rows = !a.periodic && a.gnx >= 4;
+    const int bx = min(max(ix - 1, 0), a.gnx - 4);
     if (cell != key) {
         key = cell;
         int xs[4], ys[4], zs[4];
@@ -183,8 +189,41 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
             ys[s] = j;
             zs[s] = k;
         }
-        // issue all 64 loads first, then contract (their latency overlaps)
-        if (WIDE) {
+        // issue all loads first, then contract (their latency overlaps)
+        if (rows) {
+            struct alignas(4) Row4 { float v[4]; };
+            if (WIDE) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const Row4 r = *reinterpret_cast<const Row4 *>(
+                            En + ((size_t)zs[c] * a.gny + ys[b]) * a.gnx + bx);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) vals[16 * c + 4 * b + i] = r.v[i];
+                    }
+            } else {
+                const char *base = reinterpret_cast<const char *>(En);
+                uint32_t ro[16];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        ro[4 * c + b] = (uint32_t)((zs[c] * a.gny + ys[b]) * a.gnx + bx) * 4u;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const Row4 v = *reinterpret_cast<const Row4 *>(base + ro[r]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) vals[4 * r + i] = v.v[i];
+                }
+                // offsets stay live past the loads (no load then overwrites the
+                // address register of the load before it: a wait state on gfx950)
+                asm volatile("" ::"v"(ro[0]), "v"(ro[1]), "v"(ro[2]), "v"(ro[3]), "v"(ro[4]),
+                             "v"(ro[5]), "v"(ro[6]), "v"(ro[7]), "v"(ro[8]), "v"(ro[9]),
+                             "v"(ro[10]), "v"(ro[11]), "v"(ro[12]), "v"(ro[13]), "v"(ro[14]),
+                             "v"(ro[15]));
+            }
+        } else if (WIDE) {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -211,6 +250,19 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
         }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if (rows) {
+        const int shift = (ix - 1) - bx;
+        const bool lo = shift < 0, hi = shift > 0;
+        auto fold = [lo, hi](T *w) {
+            const T w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+            w[0] = lo ? w0 + w1 : (hi ? T(0) : w0);
+            w[1] = lo ? w2 : (hi ? w0 : w1);
+            w[2] = lo ? w3 : (hi ? w1 : w2);
+            w[3] = lo ? T(0) : (hi ? w2 + w3 : w3);
+        };
+        fold(wx);
+        fold(dwx);
+    }
     T gx = 0, gy = 0, gz = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
