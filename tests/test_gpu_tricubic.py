@@ -54,3 +54,29 @@ def test_tricubic_scan_parity_c0(shape):
                       g.get("df"), dfp, label=f"tricubic {shape}", residual=orc.residual_tricubic)
     print("tricubic scan", info, flush=True)
     assert info["graded"] > 0.9 * info["points"]
+
+
+@pytest.mark.parametrize("nx", [3, 4, 5])
+def test_tricubic_scan_narrow_x(nx):
+    """Grids 3 to 5 voxels wide in x, tips running past both x edges.  From
+    four voxels on, the library reads each stencil row as four contiguous
+    voxels and folds the clamped stencil's repeated edge voxel into the x
+    weights (at nx = 4 the middle cell is the only one without a fold); with
+    three it issues single loads.  Graded against the polished oracle."""
+    w = W.config0()
+    cx, cy = 8.0, 8.0                       # centre of the tiny molecule's patch
+    grid = W.Grid((cx - 0.1, cy - 1.2, -2.0), (0.1, 0.1, 0.1), (nx, 24, 110))
+    scan = W.Scan(cx - 0.35, cy - 0.5, 0.07, 0.1, 11, 6, 9.0, 0.1, 20)   # probe 5 -> 3.1 A
+    fire = W.parity_fire(w.fire)
+    E32 = orc.build_ff(grid, w.probe, w.atoms)[..., 3].astype(np.float32)
+    E64 = E32.astype(np.float64)
+    print(f"narrow tricubic nx {nx}", flush=True)
+    res = ppm.relaxed_scan_tricubic(grid, torch.as_tensor(E32, device="cuda"), w.probe, fire,
+                                    scan, dfp=w.df)
+    g = {k: v.cpu().numpy() for k, v in res.items()}
+    ores = orc.relaxed_scan_tricubic(grid, E64, w.probe, fire, scan, polish_tol=1e-12,
+                                     with_lambda=True)
+    info = grade_scan(grid, E64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+                      g.get("df"), w.df, label=f"tricubic nx {nx}", residual=orc.residual_tricubic)
+    print("narrow tricubic", nx, info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]
