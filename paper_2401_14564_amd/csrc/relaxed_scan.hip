@@ -576,7 +576,14 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     float *__restrict__ fz_arena, float *__restrict__ df_arena)
 {
     extern __shared__ float s_col[];
-    const long long t = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    // XCD-aware order (as for single scans): hardware block b runs on XCD b % 8,
+    // each XCD takes a contiguous range of tiles, so a job's neighbouring tiles
+    // share one L2
+    const long long nb = (long long)gridDim.x * gridDim.y;
+    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    const long long per = (nb + 7) / 8, rem = nb % 8, xcd = b % 8, loc = b / 8;
+    const long long t = (rem == 0 || xcd < rem) ? xcd * per + loc
+                                                : rem * per + (xcd - rem) * (per - 1) + loc;
     int lo = 0, hi = n_jobs - 1;              // last job with tile_begin <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
