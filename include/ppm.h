@@ -177,10 +177,11 @@ ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_
  * ppm_relaxed_scan -- relaxed scan with optional fused frequency shift
  * (Sec. 2.1 Eq. 1-3, Sec. 5.1.1 step 2).
  * in:  ff[nz][ny][nx][4] from ppm_build_ff (only Fx, Fy, Fz are read).
- * The probe state and FIRE are FP64.  The trilinear combination of the FP32
- * corner forces is FP32 when fire->f_conv >= 1e-5 eV/A (its rounding, about
- * 1e-7 of the force, is then far below the threshold) and FP64 otherwise, so
- * tight thresholds resolve the force balance below FP32 rounding.
+ * The probe state and FIRE are FP64.  When fire->f_conv >= 1e-5 eV/A the
+ * trilinear combination of the FP32 corner forces is FP32 and the spring's
+ * 1/|d| is the hardware estimate (both err at about 1e-7 of the force, far
+ * below the threshold); otherwise both are FP64, so tight thresholds resolve
+ * the force balance below FP32 rounding.
  * out (each may be NULL, at least one must be given):
  *   fz[scan.nz][scan.ny][scan.nx]  tip force Fz_tip = -F^T_z at the relaxed
  *                                   probe position (eV/A)
@@ -217,8 +218,9 @@ ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_
  * stencil i-1..i+2; F = -grad of the interpolant.  x,y wrap on a periodic
  * grid; otherwise, and always in z, the point is clamped to the grid box:
  * outside [0, n-1] the force is continued constantly along that axis.
- * The stencil weights and contraction are FP32 when fire->f_conv >= 1e-5 eV/A
- * and FP64 otherwise, as for the trilinear combination of ppm_relaxed_scan.
+ * The stencil weights and contraction are FP32 (and the spring's 1/|d| the
+ * hardware estimate) when fire->f_conv >= 1e-5 eV/A and FP64 otherwise, as for
+ * ppm_relaxed_scan.
  * in:  E[nz][ny][nx] from ppm_build_energy.  Outputs, errors: as ppm_relaxed_scan.
  */
 ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,

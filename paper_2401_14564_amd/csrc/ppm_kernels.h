@@ -48,10 +48,11 @@ hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
 
 // ------------------------------------------------------------ relaxed scan
 // Smallest convergence threshold (eV/A) for which the scan combines the eight
-// FP32 corner forces in FP32: the combination then rounds at about 1e-7 of the
-// force, at least two orders of magnitude below the threshold for forces up to
-// ~10 eV/A.  Tighter thresholds combine in FP64, so the force balance can be
-// resolved below FP32 rounding (differentiation, finite-difference checks).
+// FP32 corner forces in FP32 and takes the spring's 1/|d| from the hardware
+// estimate: both then err at about 1e-7 of the force, at least two orders of
+// magnitude below the threshold for forces up to ~10 eV/A.  Tighter thresholds
+// use FP64 throughout, so the force balance can be resolved below FP32 rounding
+// (differentiation, finite-difference checks).
 constexpr double kLerp32MinFconv = 1e-5;
 
 struct ScanArgs {
@@ -68,7 +69,7 @@ struct ScanArgs {
     // FIRE
     double dt0, dt_max, f_inc, f_dec, alpha0, f_alpha, inv_mass, f_conv2;
     int n_min, max_iter;
-    int lerp32;               // 1: trilinear combination in FP32 (f_conv >= kLerp32MinFconv)
+    int lerp32;               // 1: FP32-level interpolation and spring arithmetic (f_conv >= kLerp32MinFconv)
     // tip lattice
     double x0, y0, sdx, sdy, z_top, sdz;
     int snx, sny, snz;
