@@ -529,7 +529,7 @@ __device__ void prefetch_planes(const ScanArgs &a, const T *__restrict__ grid, i
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    asm volatile("" ::"v"(acc));   // the loads' only use: keeps them from being dropped
+    asm volatile("" ::"v"(acc));
 }
 
 template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32,
