@@ -6,7 +6,8 @@
 // with the tip springs F^T of Eq. 2 and F^S_h the trilinear interpolation of the
 // force-field grid.  The tip force is read out as -F^T_z at the relaxed
 // position (text after Eq. 2) and fed into the Giessibl frequency shift
-// (Eq. 3), evaluated as a sliding dot product over a register ring.
+// (Eq. 3), evaluated from the lane's finished Fz column (the standalone
+// df_kernel slides a register ring over a stored stack instead).
 //
 // Design:
 //  * One lane per tip column; a block covers a compact tile of columns (16 x 16,
@@ -25,12 +26,13 @@
 //  * Heights progress per lane: a lane that converges moves to its next height
 //    in the same loop, so a wave runs for the largest per-column total of FIRE
 //    steps rather than the sum of per-height maxima.
-//  * Probe state (position, velocity, FIRE scalars) and the interpolation are
-//    FP64: on gfx950 FP64 FMA issues at the same rate as unpacked FP32, and the
-//    scan is bound by gather latency, so FP64 costs nothing measurable while the
-//    force balance can be resolved far below the FP32 rounding of absolute
-//    coordinates.  The grid itself is FP32 (16 B per voxel, one float4 gather
-//    per corner).
+//  * Probe state (position, velocity, FIRE scalars) and the springs are FP64:
+//    on gfx950 FP64 FMA issues at the same rate as unpacked FP32, and the
+//    force balance must be resolved far below the FP32 rounding of absolute
+//    coordinates.  The grid is FP32 (16 B per voxel, one float4 gather per
+//    corner); the interpolation is FP32 and the spring's 1/|d| the hardware
+//    estimate when the convergence threshold is far above their rounding
+//    (kLerp32MinFconv), FP64 otherwise.
 //  * Multiply-adds are fused only within one expression (contract(on), placed
 //    before the includes so it also covers the device helpers): the kernel
 //    instances (tile shape, geometry, precision, batched or single) differ in
@@ -529,7 +531,7 @@ __device__ void prefetch_planes(const ScanArgs &a, const T *__restrict__ grid, i
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    asm volatile("" ::"v"(acc));
+    asm volatile("" ::"v"(acc));   // the loads' only use: keeps them from being dropped
 }
 
 template <int TX, int TY, bool STAGE, bool WIDE, int INTERP, int GEOM, bool LERP32,
