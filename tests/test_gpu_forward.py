@@ -196,12 +196,13 @@ def test_scan_ragged_shapes(shape):
                label=f"ragged {shape}")
 
 
-@pytest.mark.parametrize("nz", [100, 200])
+@pytest.mark.parametrize("nz", [100, 159, 160, 200])
 def test_scan_output_routes_agree(nz):
-    """The scan stages Fz in LDS (16x16 blocks up to 160 heights, 8x8 blocks for
-    a frequency shift without fz up to 256) or stores it as each height
-    finishes; every route, and the fused frequency shift against the
-    standalone one, gives the same bits."""
+    """The scan stages Fz in LDS (16x16 blocks up to 159 heights beside the
+    helper wave's progress array, 8x8 blocks for a frequency shift without fz
+    up to 256) or stores it as each height finishes; every route, and the fused
+    frequency shift against the standalone one, gives the same bits (159 and
+    160 straddle the 16x16 staging limit)."""
     w = W.config0()
     scan = W.Scan(7.1, 7.3, 0.13, 0.11, 19, 6, 10.2, 0.1, nz)
     ff = ppm.build_ff(w.grid, w.probe, ppm.atoms_to_device(w.atoms))
