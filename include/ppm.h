@@ -387,8 +387,8 @@ ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
  * launch.  mols_host/mols_dev: the planned table in host and device memory
  * (same content); probe: the probe's LJ parameters and charge; pos/q/R/eps:
  * concatenated atoms (device, FP64); ff_arena: device, totals[0] x 4 floats.
- * All molecules use 64 x 4 x 8-voxel bricks here, so a periodic molecule needs
- * cutoff + (half-diagonal of that brick, 3.17 A at 0.1 A) < min(Lx, Ly)/2.
+ * Bricks are 16 x 16 x 8 voxels (as in ppm_build_ff), so a periodic molecule
+ * needs cutoff + (half-diagonal of that brick, 1.12 A at 0.1 A) < min(Lx, Ly)/2.
  */
 ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
                               const ppm_batch_mol *mols_dev, const ppm_probe *probe,

@@ -11,9 +11,8 @@
 // Design:
 //  * A block of BX x BY threads owns a brick of BX x BY x NZB voxels; each
 //    thread owns NZB voxels of one z-column, so dx, dy and dx^2+dy^2 are shared
-//    by NZB pairs (register blocking along z).  Threads of a wave cover 64
-//    consecutive x-voxels, so the float4 stores of a wave are one contiguous
-//    1 KiB run.
+//    by NZB pairs (register blocking along z).  A wave covers 16 x 4 columns,
+//    so its float4 stores are four contiguous 256-byte runs.
 //  * Atoms are staged through LDS in chunks of BX*BY.  While staging, each atom's
 //    mixing rules are applied once (R_iP = R_i + R_PP, e_iP = sqrt(e_i e_PP),
 //    kq_i = k_e q_i q_PP) and its position is made brick-local in FP64 before
@@ -184,8 +183,12 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     }
 }
 
+// At most four waves per SIMD: the register budget (up to 128 VGPRs) lets the
+// compiler put independent work after each v_rsq_f32 instead of its consumer,
+// which on gfx950 costs a wait state per pair (72 VGPRs, seven waves per SIMD:
+// 0.35 ms at 240^3; four: 0.32 ms).
 template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY, bool QUAD>
-__global__ __launch_bounds__(BX * BY) void ff_build_kernel(
+__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(1, 4))) void ff_build_kernel(
     const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
     const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
 {
@@ -247,11 +250,13 @@ __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
     }
 }
 
-// Open samples: 64 x 4 x 8 bricks (a wave's stores are one 1 KiB run).  Periodic
-// samples: 16 x 16 x 8 bricks, whose small half-diagonal keeps the per-brick
-// cull sphere (cutoff + half-diagonal) close to the cutoff sphere.
-constexpr int kBX = 64, kBY = 4, kNZB = 8;
-constexpr int kPBX = 16, kPBY = 16;
+// 16 x 16 x 8 bricks for every sample.  Grid extents are usually multiples of
+// 16 voxels (240 at the paper's scale) or close to one, so few threads of the
+// last brick of a row idle (64-wide bricks left a quarter of them idle on a
+// 240-voxel row: 0.38 against 0.35 ms); the small half-diagonal keeps a
+// periodic brick's cull sphere (cutoff + half-diagonal) close to the cutoff
+// sphere and the brick-local coordinates small.
+constexpr int kBX = 16, kBY = 16, kNZB = 8;
 
 }  // namespace
 
@@ -259,10 +264,10 @@ constexpr int kPBX = 16, kPBY = 16;
 // against its half-diagonal).
 double ff_brick_half_diagonal(double hx, double hy, double hz)
 {
-    return ff_brick_half_diagonal_dev<kPBX, kPBY, kNZB>(hx, hy, hz);
+    return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
 }
 
-// The batched build uses the open-sample brick for every molecule.
+// The batched build uses the same brick for every molecule.
 double ff_batch_brick_half_diagonal(double hx, double hy, double hz)
 {
     return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
@@ -278,9 +283,9 @@ void launch_build(const FFArgs &a, const double *pos, const double *q, const dou
                   const double *eps, float4 *out, hipStream_t stream)
 {
     if (a.Lx > 0.0) {
-        dim3 block(kPBX, kPBY, 1);
-        dim3 grid((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kPBX, kPBY, kNZB, true, EONLY, QUAD>), grid, block, 0,
+        dim3 block(kBX, kBY, 1);
+        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, true, EONLY, QUAD>), grid, block, 0,
                            stream, a, pos, q, R, eps, out);
     } else {
         dim3 block(kBX, kBY, 1);

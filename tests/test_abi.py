@@ -160,7 +160,7 @@ def test_batch_plan_offsets_on_host():
     vox = [w.grid.nvox for w in ws]
     assert [m.ff_offset for m in mols] == [0, vox[0], vox[0] + vox[1]]
     assert totals[0] == sum(vox)
-    bricks = [((w.grid.n[0] + 63) // 64) * ((w.grid.n[1] + 3) // 4) * ((w.grid.n[2] + 7) // 8)
+    bricks = [((w.grid.n[0] + 15) // 16) * ((w.grid.n[1] + 15) // 16) * ((w.grid.n[2] + 7) // 8)
               for w in ws]
     assert [m.brick_begin for m in mols] == [0, bricks[0], bricks[0] + bricks[1]]
     assert totals[1] == sum(bricks)
