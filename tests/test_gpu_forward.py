@@ -280,3 +280,30 @@ def test_df_standalone_random_stacks(A, dz, nz):
     ref = orc.df(fz.astype(np.float64), dz, dfp)
     assert got.shape == ref.shape
     np.testing.assert_allclose(got, ref, atol=2e-5 * np.abs(ref).max() + 1e-6)
+
+
+@pytest.mark.parametrize("nz", [1, 2])
+def test_scan_single_column(nz):
+    """A lattice of one column: its block has one active lane beside 255 idle
+    ones and the helper wave, which must end once that lane is done; one or two
+    heights (the shortest warm-start histories).  Trilinear and tricubic scans
+    against the polished oracle; every point must agree."""
+    w0 = W.config0()
+    scan = W.Scan(8.03, 7.96, 0.1, 0.1, 1, 1, 9.0, 0.1, nz)   # probe from 5 A above the plane
+    w = W.Workload("one column", w0.atoms, w0.grid, w0.probe, w0.fire, scan, w0.df)
+    fire = W.parity_fire(w.fire)
+    print(f"single column, {nz} heights", flush=True)
+    ff64, ores, g = _scan_both(w, fire)
+    info = grade_scan(w.grid, ff64, w.probe, fire, scan, ores["cols"], ores, g["pp"], g["fz"],
+                      label=f"one column nz {nz}")
+    assert info["graded"] == info["points"], info
+    E32 = np.ascontiguousarray(ff64[..., 3]).astype(np.float32)
+    E64 = E32.astype(np.float64)
+    tri = ppm.relaxed_scan_tricubic(w.grid, torch.as_tensor(E32, device="cuda"), w.probe, fire,
+                                    scan)
+    gt = {k: v.cpu().numpy() for k, v in tri.items()}
+    otr = orc.relaxed_scan_tricubic(w.grid, E64, w.probe, fire, scan, polish_tol=1e-12,
+                                    with_lambda=True)
+    info = grade_scan(w.grid, E64, w.probe, fire, scan, otr["cols"], otr, gt["pp"], gt["fz"],
+                      label=f"one column tricubic nz {nz}", residual=orc.residual_tricubic)
+    assert info["graded"] == info["points"], info
