@@ -126,17 +126,15 @@ __device__ __forceinline__ void cr_weights(T t, T *w, T *dw)
     dw[3] = T(0.5) * (T(3) * t2 - T(2) * t);
 }
 
-// Cell of the cubic stencil along a clamped axis: the coordinate is clamped to
-// [0, n-1] (NaN counts as below), the cell index to [0, n-2], so the top node
-// is the last cell at t = 1.
+// Cell of the cubic stencil along a clamped axis: the trilinear lookup's
+// clamp_cell (coordinate clamped to the grid box, NaN to 0; cell index at most
+// n-2, so the top node is the last cell at t = 1 - ulp), written branch-free,
+// so the lookup issues no compare/select chains (each costs wait states on
+// gfx950).
 __device__ __forceinline__ int cubic_clamp_cell(double u, int n, double &t)
 {
-    const bool below = !(u >= 0.0);
-    const bool above = u > (double)(n - 1);
-    u = below ? 0.0 : (above ? (double)(n - 1) : u);
-    const double f = fmin(floor(u), (double)(n - 2));
-    t = u - f;
-    return (int)f;
+    bool in;
+    return clamp_cell(u, n, t, in);
 }
 
 // Sample force from the tricubic interpolant of the energy grid En[nz][ny][nx]
@@ -191,10 +189,11 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
                 j += (j < 0) ? a.gny : 0;
                 j -= (j >= a.gny) ? a.gny : 0;
             } else {
-                i = i < 0 ? 0 : (i > a.gnx - 1 ? a.gnx - 1 : i);
-                j = j < 0 ? 0 : (j > a.gny - 1 ? a.gny - 1 : j);
+                // min/max rather than compare-and-select (no vcc, no wait states)
+                i = min(max(i, 0), a.gnx - 1);
+                j = min(max(j, 0), a.gny - 1);
             }
-            k = k < 0 ? 0 : (k > a.gnz - 1 ? a.gnz - 1 : k);
+            k = min(max(k, 0), a.gnz - 1);
             xs[s] = i;
             ys[s] = j;
             zs[s] = k;
