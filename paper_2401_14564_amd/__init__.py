@@ -40,6 +40,47 @@ def _device():
     return torch.device("cuda")
 
 
+def _need(t, shape, name, dtype=torch.float32):
+    """Raise before any launch unless t is a contiguous tensor of exactly this
+    shape and dtype: the C ABI takes bare pointers and cannot check sizes.  That
+    it lives on the device is checked when its pointer is taken (_lib.ptr)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    shape = tuple(int(v) for v in shape)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {shape}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
+def _grid_shape(grid, *tail):
+    nx, ny, nz = (int(v) for v in grid.n)
+    return (nz, ny, nx) + tuple(tail)
+
+
+def _scan_shape(scan, *tail):
+    return (int(scan.nz), int(scan.ny), int(scan.nx)) + tuple(tail)
+
+
+def _df_shape(scan, dfp):
+    m = df_half_width(dfp.A, scan.dz)
+    return (max(int(scan.nz) - 2 * m, 0), int(scan.ny), int(scan.nx))
+
+
+def _check_scan_out(out, scan, dfp):
+    if out.get("fz") is not None:
+        _need(out["fz"], _scan_shape(scan), "out['fz']")
+    if out.get("pp") is not None:
+        _need(out["pp"], _scan_shape(scan, 4), "out['pp']")
+    if out.get("df") is not None:
+        if dfp is None:
+            raise ValueError("out['df'] given without frequency-shift parameters")
+        _need(out["df"], _df_shape(scan, dfp), "out['df']")
+
+
 def atoms_to_device(atoms, device=None):
     """(pos, q, R, eps) as contiguous float64 device tensors."""
     device = device or _device()
@@ -50,7 +91,12 @@ def atoms_to_device(atoms, device=None):
 
     def t(x):
         return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
-    return t(pos).reshape(-1, 3), t(q).reshape(-1), t(R).reshape(-1), t(eps).reshape(-1)
+    pos, q, R, eps = t(pos).reshape(-1, 3), t(q).reshape(-1), t(R).reshape(-1), t(eps).reshape(-1)
+    n = int(q.numel())
+    if pos.shape[0] != n or R.numel() != n or eps.numel() != n:
+        raise ValueError(f"atoms: {pos.shape[0]} positions, {n} charges, {R.numel()} radii, "
+                         f"{eps.numel()} depths")
+    return pos, q, R, eps
 
 
 def df_half_width(A: float, dz: float) -> int:
@@ -64,7 +110,7 @@ def build_ff(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tenso
     nx, ny, nz = (int(v) for v in grid.n)
     if out is None:
         out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=pos.device)
-    assert out.shape == (nz, ny, nx, 4) and out.dtype == torch.float32 and out.is_contiguous()
+    _need(out, (nz, ny, nx, 4), "out")
     st = L.ppm_build_ff(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
                         _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps), _lib.ptr(out),
                         _stream())
@@ -78,9 +124,11 @@ def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: boo
     [nz,ny,nx,4] (probe displacement from rest and FIRE steps, negative if not
     converged) and 'df' [nz-2m,ny,nx] (Hz, when dfp is given)."""
     L = _lib.lib()
+    _need(ff, _grid_shape(grid, 4), "ff")
     dev = ff.device
     nz, ny, nx = int(scan.nz), int(scan.ny), int(scan.nx)
     out = dict(out or {})
+    _check_scan_out(out, scan, dfp)
     if fz and "fz" not in out:
         out["fz"] = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
     if pp and "pp" not in out:
@@ -104,7 +152,7 @@ def build_energy(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.T
     nx, ny, nz = (int(v) for v in grid.n)
     if out is None:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device=pos.device)
-    assert out.shape == (nz, ny, nx) and out.dtype == torch.float32 and out.is_contiguous()
+    _need(out, (nz, ny, nx), "out")
     st = L.ppm_build_energy(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
                             _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps), _lib.ptr(out),
                             _stream())
@@ -117,9 +165,11 @@ def relaxed_scan_tricubic(grid, E, probe, fire, scan, dfp=None, fz: bool = True,
     """Relaxed scan on the tricubic interpolant of the energy grid E; outputs as
     relaxed_scan."""
     L = _lib.lib()
+    _need(E, _grid_shape(grid), "E")
     dev = E.device
     nz, ny, nx = int(scan.nz), int(scan.ny), int(scan.nx)
     out = dict(out or {})
+    _check_scan_out(out, scan, dfp)
     if fz and "fz" not in out:
         out["fz"] = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
     if pp and "pp" not in out:
@@ -139,11 +189,15 @@ def relaxed_scan_tricubic(grid, E, probe, fire, scan, dfp=None, fz: bool = True,
 def df(fz: torch.Tensor, dz: float, dfp, out: torch.Tensor | None = None) -> torch.Tensor:
     """Frequency shift of an Fz stack [nz, ny, nx] (scan-index order)."""
     L = _lib.lib()
-    nz, ny, nx = fz.shape
+    if fz.dim() != 3:
+        raise ValueError(f"fz: expected [nz, ny, nx], got shape {tuple(fz.shape)}")
+    nz, ny, nx = (int(v) for v in fz.shape)
+    _need(fz, (nz, ny, nx), "fz")
     m = df_half_width(dfp.A, dz)
     if out is None:
         out = torch.empty((max(nz - 2 * m, 0), ny, nx), dtype=torch.float32, device=fz.device)
-    st = L.ppm_df(_lib.ptr(fz.contiguous()), nz, ny, nx, float(dz), _lib.df_struct(dfp),
+    _need(out, (max(nz - 2 * m, 0), ny, nx), "out")
+    st = L.ppm_df(_lib.ptr(fz), nz, ny, nx, float(dz), _lib.df_struct(dfp),
                   _lib.ptr(out), _stream())
     _lib.check(st, "ppm_df")
     return out
@@ -154,15 +208,20 @@ def relaxed_scan_backward(grid, ff, probe, scan, dfp, atoms, pp, grad_df,
     """Gradient of sum(grad_df * df) w.r.t. atom positions, charges, R and eps
     (float64 device tensors)."""
     L = _lib.lib()
+    _need(pp, _scan_shape(scan, 4), "pp")
+    _need(ff, _grid_shape(grid, 4), "ff")
+    if tuple(grad_df.shape) != _df_shape(scan, dfp):
+        raise ValueError(f"grad_df: shape {tuple(grad_df.shape)}, expected {_df_shape(scan, dfp)}")
     pos, q, R, eps = atoms_to_device(atoms)
     n = int(q.numel())
     sc = _lib.scan_struct(scan)
     nbytes = int(L.ppm_backward_workspace_bytes(sc, n))
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=ff.device)
+    _need(workspace, (workspace.numel(),), "workspace", torch.uint8)
     g = {k: torch.empty(s, dtype=torch.float64, device=ff.device)
          for k, s in (("pos", (n, 3)), ("q", (n,)), ("R", (n,)), ("eps", (n,)))}
-    gdf = grad_df.to(torch.float32).contiguous()
+    gdf = _need(grad_df.to(torch.float32).contiguous(), _df_shape(scan, dfp), "grad_df")
     st = L.ppm_relaxed_scan_backward(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
                                      sc, _lib.df_struct(dfp), n, _lib.ptr(pos), _lib.ptr(q),
                                      _lib.ptr(R), _lib.ptr(eps), _lib.ptr(pp), _lib.ptr(gdf),
@@ -177,9 +236,12 @@ def lateral_stiffness(grid, ff, probe, scan, pp, out: torch.Tensor | None = None
     """Two smallest eigenvalues of the symmetric stiffness matrix -dG/dr at every
     relaxed point (eV/A^2), [nz, ny, nx, 2]; NaN where not converged."""
     L = _lib.lib()
+    _need(pp, _scan_shape(scan, 4), "pp")
+    _need(ff, _grid_shape(grid, 4), "ff")
     if out is None:
         out = torch.empty((int(scan.nz), int(scan.ny), int(scan.nx), 2), dtype=torch.float32,
                           device=ff.device)
+    _need(out, _scan_shape(scan, 2), "out")
     st = L.ppm_lateral_stiffness(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
                                  _lib.scan_struct(scan), _lib.ptr(pp), _lib.ptr(out), _stream())
     _lib.check(st, "ppm_lateral_stiffness")
@@ -194,7 +256,7 @@ def tip_density(grid, q_pp: float, q_zz: float, sigma: float,
     nx, ny, nz = (int(v) for v in grid.n)
     if out is None:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device=_device())
-    assert out.shape == (nz, ny, nx) and out.dtype == torch.float32 and out.is_contiguous()
+    _need(out, (nz, ny, nx), "out")
     st = L.ppm_tip_density(_lib.grid_struct(grid), float(q_pp), float(q_zz), float(sigma),
                            _lib.ptr(out), _stream())
     _lib.check(st, "ppm_tip_density")
@@ -216,14 +278,16 @@ def hartree_ff(grid, V: torch.Tensor, rho: torch.Tensor, out: torch.Tensor | Non
     `out` when accumulate is set."""
     L = _lib.lib()
     nx, ny, nz = (int(v) for v in grid.n)
-    for t in (V, rho):
-        assert t.shape == (nz, ny, nx) and t.dtype == torch.float32 and t.is_contiguous()
+    _need(V, (nz, ny, nx), "V")
+    _need(rho, (nz, ny, nx), "rho")
     if out is None:
-        assert not accumulate
+        if accumulate:
+            raise ValueError("accumulate=True needs an existing out grid")
         out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=V.device)
-    assert out.shape == (nz, ny, nx, 4) and out.dtype == torch.float32 and out.is_contiguous()
+    _need(out, (nz, ny, nx, 4), "out")
     if workspace is None:
         workspace = hartree_workspace(grid, V.device)
+    _need(workspace, (workspace.numel(),), "workspace", torch.uint8)
     st = L.ppm_hartree_ff(_lib.grid_struct(grid), _lib.ptr(V), _lib.ptr(rho), int(accumulate),
                           _lib.ptr(out), _lib.ptr(workspace), workspace.numel(), _stream())
     _lib.check(st, "ppm_hartree_ff")

@@ -171,5 +171,10 @@ def df_struct(d) -> DfParams:
 
 
 def ptr(t):
-    """Device pointer of a tensor (None -> NULL)."""
-    return None if t is None else ct.c_void_p(t.data_ptr())
+    """Device pointer of a tensor (None -> NULL); raises for a host tensor, whose
+    address a kernel cannot use."""
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError(f"expected a device tensor, got one on {t.device}")
+    return ct.c_void_p(t.data_ptr())

@@ -192,3 +192,45 @@ def test_hartree_sizes_and_bad_arguments():
     assert L.ppm_tip_density(g, 0.0, -0.05, 0.0, FAKE, None) == E
     assert L.ppm_tip_density(g, float("nan"), -0.05, 0.7, FAKE, None) == E
     assert L.ppm_tip_density(g, 0.0, -0.05, 0.7, None, None) == E
+
+
+def test_python_wrappers_reject_bad_buffers_before_launch():
+    """The bindings pass bare pointers, so every wrapper checks shape, dtype,
+    contiguity and device of each buffer against the grid and scan it is called
+    with and raises before the library is called.  CPU tensors of the right
+    shape reach the device check, which is the last one."""
+    import torch
+    import paper_2401_14564_amd as ppm
+    grid = W.Grid((0.0, 0.0, 0.0), (0.1, 0.1, 0.1), (8, 6, 10))
+    scan = W.Scan(0.1, 0.1, 0.1, 0.1, 3, 2, 4.0, 0.1, 12)
+    probe, fire, dfp = W.Probe(), W.Fire(), W.DfParams()
+    good_ff = torch.zeros((10, 6, 8, 4))
+    short_ff = torch.zeros((9, 6, 8, 4))
+    with pytest.raises(ValueError, match="shape"):
+        ppm.relaxed_scan(grid, short_ff, probe, fire, scan)
+    with pytest.raises(ValueError, match="dtype"):
+        ppm.relaxed_scan(grid, good_ff.double(), probe, fire, scan)
+    with pytest.raises(ValueError, match="contiguous"):
+        ppm.relaxed_scan(grid, torch.zeros((8, 6, 10, 4)).permute(2, 1, 0, 3), probe, fire, scan)
+    with pytest.raises(ValueError, match="device"):
+        ppm.relaxed_scan(grid, good_ff, probe, fire, scan)
+    with pytest.raises(ValueError, match="shape"):
+        ppm.relaxed_scan_tricubic(grid, torch.zeros((10, 6, 9)), probe, fire, scan)
+    with pytest.raises(ValueError, match="shape"):
+        ppm.lateral_stiffness(grid, short_ff, probe, scan, torch.zeros((12, 2, 3, 4)))
+    with pytest.raises(ValueError, match="pp"):
+        ppm.lateral_stiffness(grid, good_ff, probe, scan, torch.zeros((12, 2, 4, 4)))
+    with pytest.raises(ValueError, match="dtype"):
+        ppm.df(torch.zeros((12, 2, 3), dtype=torch.float64), 0.1, dfp)
+    with pytest.raises(ValueError, match="device"):
+        ppm.df(torch.zeros((12, 2, 3)), 0.1, dfp)
+    atoms = (torch.zeros((2, 3), dtype=torch.float64), torch.zeros(3, dtype=torch.float64),
+             torch.zeros(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="atoms"):
+        ppm.atoms_to_device(atoms, device="cpu")
+    with pytest.raises(ValueError, match="grad_df"):
+        ppm.relaxed_scan_backward(grid, good_ff, probe, scan, dfp, atoms, torch.zeros((12, 2, 3, 4)),
+                                  torch.zeros((12, 2, 3)))
+    with pytest.raises(ValueError, match="out\\['df'\\]"):
+        ppm.relaxed_scan(grid, good_ff, probe, fire, scan, dfp=dfp,
+                         out={"df": torch.zeros((12, 2, 3))})
