@@ -11,7 +11,9 @@
  * A Decade of Development in Probe-Particle Models" (arXiv 2401.14564).
  *
  *   - per-atom mixing rules ............ Sec. 2.2.1 (Eq. 5), Sec. 2.2.2 (Eq. 6)
- *   - LJ + point-charge energy/force ... Eq. 5, Eq. 6, with F = -grad E (Sec. 2.2)
+ *   - LJ + point-charge energy/force ... Eq. 5, Eq. 6, with F = -grad E (Sec. 2.2);
+ *                                        periodic samples: minimum image and a
+ *                                        shifted-force cutoff (orc_pair_shift)
  *   - quadrupolar probe charge ......... Sec. 2.2.3 (d_z2 charge of the CO tip,
  *                                        moment -0.025 to -0.15 e A^2)
  *   - grid projection of the force field Sec. 5.1.1, step 1
@@ -119,6 +121,51 @@ static void orc_quad(double kQ, const double *d, double rho2, double *E, double 
 }
 
 /*
+ * Shifted-force truncation at the cutoff rc of a periodic sample.  A pair term
+ * of the form Y(direction) g(rho) is replaced by Y(direction) g_sf(rho) with
+ *   g_sf(rho) = g(rho) - g(rc) - (rho - rc) g'(rc)   for rho < rc, 0 beyond,
+ * so that the term and its force both vanish on the cutoff sphere (a plain
+ * truncation leaves a force step there on every charged atom's sphere).  For
+ * the LJ + Coulomb pair (Y = 1) this adds -U(rc) + (rho - rc) f(rc) to the
+ * energy, with f = -dU/drho, and -f(rc) d/rho to the force.  For the d_z2 term
+ * (Y = 3 dz^2/rho^2 - 1, g = rho^-3) it adds Y (3 rho rc^-4 - 4 rc^-3) to
+ * u = (3 dz^2 - rho^2)/rho^5, whose gradient is written out below.
+ */
+static void orc_pair_shift(double e, double Rp, double kq, double rc, double rho,
+                           const double *d, double *E, double *F, double *sE, double *sF)
+{
+    double sc = Rp / rc, sc6 = pow(sc, 6.0), sc12 = sc6 * sc6;
+    double Uc = e * (sc12 - 2.0 * sc6) + kq / rc;
+    double fc = 12.0 * e * (sc12 - sc6) / rc + kq / (rc * rc);
+    *E += -Uc + (rho - rc) * fc;
+    for (int t = 0; t < 3; ++t) F[t] -= fc * d[t] / rho;
+    *sE += fabs(Uc) + fabs(fc) * (rc + rho);
+    *sF += fabs(fc);
+}
+
+static void orc_quad_shift(double kQ, double rc, const double *d, double rho2, double *E,
+                           double *F, double *sE, double *sF)
+{
+    double rho = sqrt(rho2), z = d[2];
+    double Y = 3.0 * z * z / rho2 - 1.0;
+    double irc3 = 1.0 / (rc * rc * rc), irc4 = irc3 / rc;
+    *E += kQ * Y * (3.0 * rho * irc4 - 4.0 * irc3);
+    /* grad of Y (3 rho rc^-4 - 4 rc^-3) = ax d + bx e_z */
+    double ax = -9.0 * irc4 * z * z / (rho2 * rho) + 24.0 * irc3 * z * z / (rho2 * rho2)
+                - 3.0 * irc4 / rho;
+    double bx = 18.0 * irc4 * z / rho - 24.0 * irc3 * z / rho2;
+    F[0] -= kQ * ax * d[0];
+    F[1] -= kQ * ax * d[1];
+    F[2] -= kQ * (ax * d[2] + bx);
+    /* magnitude sums of the separate terms (rounding scale) */
+    *sE += fabs(kQ) * (9.0 * irc4 * z * z / rho + 12.0 * irc3 * z * z / rho2
+                       + 3.0 * irc4 * rho + 4.0 * irc3);
+    *sF += fabs(kQ) * ((9.0 * irc4 * z * z / (rho2 * rho) + 24.0 * irc3 * z * z / (rho2 * rho2)
+                        + 3.0 * irc4 / rho) * rho
+                       + 18.0 * irc4 * fabs(z) / rho + 24.0 * irc3 * fabs(z) / rho2);
+}
+
+/*
  * Energy and force on the probe particle at point r from all atoms
  * (Eq. 5 + Eq. 6, F = -grad E):
  *   E   = sum_i e_iP [ (R_iP/rho)^12 - 2 (R_iP/rho)^6 ] + kq_i / rho
@@ -130,7 +177,8 @@ static void orc_quad(double kQ, const double *d, double rho2, double *E, double 
  * scale[1] = sum_i e_iP ((R/rho)^12 + 2 (R/rho)^6) + |kq_i|/rho,
  * (each plus the quadrupole's magnitude bound), scale[2] = min rho,
  * scale[3] = min |rho^2 - rc^2|.
- * With periodic_xy only pairs with rho^2 < rc^2 contribute.
+ * With periodic_xy only pairs with rho^2 < rc^2 contribute, each shifted so
+ * that it and its force vanish at rc (orc_pair_shift, orc_quad_shift).
  */
 void orc_point(const double *r, int na, const double *pos, const double *RiP,
                const double *eiP, const double *kqi, const double *kQi, const double *g,
@@ -162,9 +210,15 @@ void orc_point(const double *r, int na, const double *pos, const double *RiP,
         Fz += phi * d[2];
         sF += (12.0 * eiP[i] * (s12 + s6) / rho2 + fabs(kqi[i]) / (rho2 * rho)) * rho;
         sE += eiP[i] * (s12 + 2.0 * s6) + fabs(eC);
+        if (periodic) {
+            double Fs[3] = { 0.0, 0.0, 0.0 };
+            orc_pair_shift(eiP[i], RiP[i], kqi[i], g[7], rho, d, &E, Fs, &sE, &sF);
+            Fx += Fs[0]; Fy += Fs[1]; Fz += Fs[2];
+        }
         if (kQi && kQi[i] != 0.0) {
             double Fq[3] = { 0.0, 0.0, 0.0 };
             orc_quad(kQi[i], d, rho2, &E, Fq, &sE, &sF);
+            if (periodic) orc_quad_shift(kQi[i], g[7], d, rho2, &E, Fq, &sE, &sF);
             Fx += Fq[0]; Fy += Fq[1]; Fz += Fq[2];
         }
     }
@@ -616,8 +670,11 @@ static double orc_lambda_min(int mode, const double *ff, const double *g, const 
 /*
  * Relaxed scan (Sec. 2.1 and Sec. 5.1.1): every tip column descends in z
  * independently.  Column c = cols[c] (ix, iy) of the tip lattice, anchor
- * (x0 + ix dx, y0 + iy dy, z_top - k dz) for k = 0 .. nz-1.  At k = 0 the
- * probe starts at anchor + d0; at k > 0 at r*(k-1) + (anchor(k) - anchor(k-1)).
+ * (x0 + ix dx, y0 + iy dy, z_top - k dz) for k = 0 .. nz-1.  With the
+ * displacement u(k) = r*(k) - anchor(k), the probe starts at anchor + d0 at
+ * k = 0, at anchor(1) + u(0) at k = 1 and at anchor(k) + u(k-1) + (u(k-1) -
+ * u(k-2)) from k = 2 on (linear extrapolation), always from rest; the FIRE time
+ * step carries over from the previous height, not below dt0.
  * FIRE relaxes G = F^T + F^S_h to |G| < f_conv; with polish_tol > 0 the result
  * is then Newton-refined to |G| < polish_tol.
  * Readout (text after Eq. 2): Fz_tip = -F^T_z at the relaxed position.
@@ -852,7 +909,10 @@ void orc_df(const double *fz, int nz, int ncol, double dz, double A, double f0,
  *   phi = 12 e (R^12 rho^-14 - R^6 rho^-8) + kq rho^-3  (e = e_iP, R = R_iP),
  * plus, for a quadrupolar probe, f_i = -kQ_i grad u with u = (3 dz^2 - rho^2)/rho^5
  * (orc_quad); grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7, b = 6 dz rho^-5,
- * so d f_i / d a_i = kQ_i hess u and d f_i / d q_i = -k_e q_zz grad u.
+ * so d f_i / d a_i = kQ_i hess u and d f_i / d q_i = -k_e q_zz grad u.  On a
+ * periodic sample both terms carry the shifted-force truncation of orc_point
+ * (phi gains -f(rc)/rho, u gains Y (3 rho rc^-4 - 4 rc^-3)) and pairs beyond rc
+ * are skipped.
  * rstar [ncol][nz][3] in the order of cols; grad_df [nz-2m][ncol].
  */
 void orc_scan_backward(const double *g, const int *n, const double *ff, const double *p,
@@ -932,18 +992,35 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
                                 /* phi'(rho)/rho */
                                 double dphi = 12.0 * e * (-14.0 * s12 + 8.0 * s6) * ir2 * ir2
                                               - 3.0 * kqi[i] * ir3 * ir2;
+                                /* per-rho factors of d phi / d(q_i, R_iP, e_iP) */
+                                double phq = ir3;
+                                double phR = 12.0 * e * (12.0 * s12 - 6.0 * s6) / Rp * ir2;
+                                double phe = 12.0 * (s12 - s6) * ir2;
+                                if (periodic) {
+                                    /* shifted force (orc_pair_shift): phi -= f(rc)/rho with
+                                       f(rc) = 12 e (sc^12 - sc^6)/rc + kq/rc^2 */
+                                    double rc = g[7], sc = Rp / rc;
+                                    double sc6 = pow(sc, 6.0), sc12 = sc6 * sc6;
+                                    double fc = 12.0 * e * (sc12 - sc6) / rc + kqi[i] / (rc * rc);
+                                    phi -= fc / rho;
+                                    dphi += fc * ir3;
+                                    phq -= 1.0 / (rc * rc * rho);
+                                    phR -= 12.0 * e * (12.0 * sc12 - 6.0 * sc6) / (Rp * rc * rho);
+                                    phe -= 12.0 * (sc12 - sc6) / (rc * rho);
+                                }
                                 double md = mw[0] * d[0] + mw[1] * d[1] + mw[2] * d[2];
                                 /* d f / d a_i = -(phi I + (phi'/rho) d d^T) */
                                 for (int t = 0; t < 3; ++t)
                                     lp[6 * i + t] -= phi * mw[t] + dphi * md * d[t];
-                                /* d f / d q_i = k_e q_PP rho^-3 d */
-                                lp[6 * i + 3] += ORC_KE * p[2] * ir3 * md;
-                                /* d f / d R_iP = 12 e (12 s^12 - 6 s^6) / (R rho^2) d */
-                                lp[6 * i + 4] += 12.0 * e * (12.0 * s12 - 6.0 * s6) / Rp * ir2 * md;
-                                /* d f / d e_i = (d e_iP / d e_i) 12 (s^12 - s^6) rho^-2 d,
+                                /* d f / d q_i = k_e q_PP (d phi / d kq_i) d */
+                                lp[6 * i + 3] += ORC_KE * p[2] * phq * md;
+                                /* d f / d R_iP = (d phi / d R_iP) d; without a cutoff
+                                   12 e (12 s^12 - 6 s^6) / (R rho^2) d */
+                                lp[6 * i + 4] += phR * md;
+                                /* d f / d e_i = (d e_iP / d e_i)(d phi / d e_iP) d, with
                                    d e_iP / d e_i = e_PP / (2 e_iP) */
                                 if (e > 0.0)
-                                    lp[6 * i + 5] += (p[1] / (2.0 * e)) * 12.0 * (s12 - s6) * ir2 * md;
+                                    lp[6 * i + 5] += (p[1] / (2.0 * e)) * phe * md;
                                 if (p[9] != 0.0) {
                                     double z = d[2];
                                     double ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
@@ -953,6 +1030,21 @@ void orc_scan_backward(const double *g, const int *n, const double *ff, const do
                                     double ga = (-15.0 * ir7 + 105.0 * z * z * ir9) * md
                                                 - 30.0 * z * ir7 * mw[2];
                                     double gb = 6.0 * ir5 * mw[2] - 30.0 * z * ir7 * md;
+                                    if (periodic) {
+                                        /* shifted d_z2 term (orc_quad_shift): grad u gains
+                                           ax d + bx e_z; add them and their gradients . mw */
+                                        double rc = g[7];
+                                        double irc3 = 1.0 / (rc * rc * rc), irc4 = irc3 / rc;
+                                        double ir1 = 1.0 / rho, ir4 = ir2 * ir2, ir6 = ir4 * ir2;
+                                        ua += -9.0 * irc4 * z * z * ir3 + 24.0 * irc3 * z * z * ir4
+                                              - 3.0 * irc4 * ir1;
+                                        ub += 18.0 * irc4 * z * ir1 - 24.0 * irc3 * z * ir2;
+                                        ga += -9.0 * irc4 * (2.0 * z * ir3 * mw[2] - 3.0 * z * z * ir5 * md)
+                                              + 24.0 * irc3 * (2.0 * z * ir4 * mw[2] - 4.0 * z * z * ir6 * md)
+                                              + 3.0 * irc4 * ir3 * md;
+                                        gb += 18.0 * irc4 * (ir1 * mw[2] - z * ir3 * md)
+                                              - 24.0 * irc3 * (ir2 * mw[2] - 2.0 * z * ir4 * md);
+                                    }
                                     double Hm[3] = { ua * mw[0] + d[0] * ga,
                                                      ua * mw[1] + d[1] * ga,
                                                      ua * mw[2] + d[2] * ga + gb };

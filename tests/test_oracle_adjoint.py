@@ -15,11 +15,18 @@ import oracle as orc
 from paper_2401_14564_amd import workloads as W
 
 
-def _problem():
+def _problem(periodic=False):
     rng = np.random.default_rng(77)
     atoms = W.random_atoms(rng, 4, [0.8, 0.8, -0.2], [2.2, 2.2, 0.2], q_max=0.3)
-    grid = W.Grid((0.0, 0.0, -1.0), (0.1, 0.1, 0.1), (30, 30, 70))
-    scan = W.Scan(1.23, 1.31, 0.17, 0.19, 3, 3, 8.2, 0.1, 14)
+    if periodic:
+        # cell of 9 x 8.4 A with a 4.2 A shifted-force cutoff: the probe heights
+        # put the cutoff sphere of every atom within reach of the tip columns,
+        # and the atoms near x, y = 0 act through their images
+        grid = W.Grid((0.0, 0.0, -1.0), (0.1, 0.1, 0.1), (90, 84, 70), 1, 4.2)
+        scan = W.Scan(8.73, 0.21, 0.37, 0.41, 3, 3, 7.6, 0.1, 14)
+    else:
+        grid = W.Grid((0.0, 0.0, -1.0), (0.1, 0.1, 0.1), (30, 30, 70))
+        scan = W.Scan(1.23, 1.31, 0.17, 0.19, 3, 3, 8.2, 0.1, 14)
     fire = W.parity_fire(W.Fire(), f_conv=1e-9, max_iter=50000)
     dfp = W.DfParams()
     m = orc.df_m(dfp.A, scan.dz)
@@ -39,9 +46,12 @@ def _loss(atoms, grid, scan, fire, dfp, gdf, probe=W.Probe()):
 PROBES = [W.Probe(), W.Probe(q_pp=0.0, q_zz=-0.05)]
 
 
+@pytest.mark.parametrize("periodic", [False, True], ids=["open", "periodic"])
 @pytest.mark.parametrize("probe", PROBES, ids=["monopole", "quadrupole"])
-def test_adjoint_matches_central_differences(probe):
-    atoms, grid, scan, fire, dfp, gdf = _problem()
+def test_adjoint_matches_central_differences(probe, periodic):
+    """Also on a periodic sample, where the shifted-force cutoff enters every
+    pair derivative."""
+    atoms, grid, scan, fire, dfp, gdf = _problem(periodic)
     L0, ff, res = _loss(atoms, grid, scan, fire, dfp, gdf, probe)
     assert np.all(res["gnorm"] < 1e-12)
     g = orc.scan_backward(grid, ff, probe, scan, res["cols"], res["r"], gdf, dfp, atoms)
@@ -55,18 +65,22 @@ def test_adjoint_matches_central_differences(probe):
         return (Lp - Lm) / (2 * h)
 
     scale = max(np.abs(g["pos"]).max(), 1e-12)
+    # smaller steps on the periodic sample: a voxel crossing an atom's cutoff
+    # sphere is a kink of the field in the atom's parameters, and the relaxed
+    # points there sit close to several of them
+    hp = 1e-6 if periodic else 1e-4
     for i in range(atoms.n):
         for k in range(3):
             def mod(a, h, i=i, k=k):
                 a.pos[i, k] += h
-            assert g["pos"][i, k] == pytest.approx(fd(mod, 1e-4), rel=2e-4, abs=2e-5 * scale)
+            assert g["pos"][i, k] == pytest.approx(fd(mod, hp), rel=2e-4, abs=2e-5 * scale)
         def modq(a, h, i=i):
             a.q[i] += h
-        assert g["q"][i] == pytest.approx(fd(modq, 1e-4), rel=2e-4, abs=1e-6)
+        assert g["q"][i] == pytest.approx(fd(modq, hp), rel=2e-4, abs=1e-6)
         def modR(a, h, i=i):
             a.R[i] += h
-        assert g["R"][i] == pytest.approx(fd(modR, 1e-4), rel=2e-4, abs=1e-6)
-        he = 1e-3 * atoms.eps[i]
+        assert g["R"][i] == pytest.approx(fd(modR, hp), rel=2e-4, abs=1e-6)
+        he = (1e-5 if periodic else 1e-3) * atoms.eps[i]
         def mode(a, h, i=i):
             a.eps[i] += h
         assert g["eps"][i] == pytest.approx(fd(mode, he), rel=2e-4, abs=1e-3)

@@ -140,12 +140,62 @@ def test_minimum_image_and_cutoff():
     g = _grid(origin=(0, 0, 0), step=(0.1, 0.1, 0.1), n=(20, 20, 10), periodic=1, cutoff=0.9)
     A = _atoms([[1.95, 0.05, 0.0]], q=[0.3], R=[1.5], eps=[0.002])
     Ashift = _atoms([[1.95 - L, 0.05, 0.0]], q=[0.3], R=[1.5], eps=[0.002])
-    r = np.array([0.2, 0.1, 0.5])
-    out, _ = orc.point_ff([r], A, PROBE, g)
-    ref, _ = orc.point_ff([r], Ashift, PROBE, _grid())
-    np.testing.assert_allclose(out, ref, rtol=1e-13)
+    for probe in (PROBE, W.Probe(q_zz=-0.1)):
+        for r in ([0.2, 0.1, 0.5], [0.25, -0.3, 0.35]):
+            r = np.array(r)
+            out, _ = orc.point_ff([r], A, probe, g)
+            # the same atom's image without periodicity, then the shifted-force
+            # construction along the ray through r (see the next test)
+            d = r - Ashift.pos[0]
+            rho = np.linalg.norm(d)
+            pc = Ashift.pos[0] + 0.9 * d / rho
+            ref, _ = orc.point_ff([r], Ashift, probe, _grid())
+            refc, _ = orc.point_ff([pc], Ashift, probe, _grid())
+            E = ref[0, 3] - refc[0, 3] + (rho - 0.9) * (refc[0, :3] @ d / rho)
+            assert out[0, 3] == pytest.approx(E, rel=1e-12, abs=1e-15)
     far, _ = orc.point_ff([[1.0, 1.0, 0.5]], A, PROBE, g)   # nearest image 1.08 A > r_c
     assert np.all(far == 0.0)
+
+
+@pytest.mark.parametrize("probe", [W.Probe(), W.Probe(q_pp=0.0, q_zz=-0.05),
+                                   W.Probe(q_pp=-0.05, q_zz=-0.1)],
+                         ids=["monopole", "quadrupole", "mixed"])
+def test_shifted_force_cutoff(probe):
+    """The cutoff of a periodic sample is a shifted-force truncation: along every
+    ray from an atom, each pair term Y(direction) g(rho) becomes the remainder of
+    its first-order Taylor expansion about rho = r_c, so the energy and the
+    force both vanish on the cutoff sphere.  Checked against the untruncated sum
+    (open sample, pinned by the LJ and Coulomb closed forms above): for the
+    energy, E_c(r) = E(r) - E(p) + (rho - r_c) F(p).(r - r_i)/rho with p the
+    point of the ray on the sphere; F = -grad E by central differences, also
+    just inside the sphere; and E, F -> 0 as rho -> r_c."""
+    rc = 3.7
+    g = _grid(origin=(0, 0, 0), step=(0.1, 0.1, 0.1), n=(100, 100, 40), periodic=1, cutoff=rc)
+    rng = np.random.default_rng(3)
+    for _ in range(12):
+        a = rng.uniform([2.0, 2.0, -0.5], [8.0, 8.0, 0.5])
+        A = _atoms([a], q=[rng.uniform(-0.3, 0.3)], R=[1.8], eps=[0.003])
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        for rho in (rng.uniform(2.4, rc - 0.05), rc - 1e-7):
+            r = a + rho * u
+            out, _ = orc.point_ff([r], A, probe, g)
+            ref, _ = orc.point_ff([r], A, probe, _grid())
+            refc, _ = orc.point_ff([a + rc * u], A, probe, _grid())
+            E = ref[0, 3] - refc[0, 3] + (rho - rc) * (refc[0, :3] @ u)
+            assert out[0, 3] == pytest.approx(E, rel=1e-11, abs=1e-14)
+            if rho > rc - 1e-6:
+                assert np.all(np.abs(out[0]) < 1e-8)
+                continue
+            h = 1e-5
+            fd = np.zeros(3)
+            for k in range(3):
+                e = np.zeros(3)
+                e[k] = h
+                Ep = orc.point_ff([r + e], A, probe, g)[0][0, 3]
+                Em = orc.point_ff([r - e], A, probe, g)[0][0, 3]
+                fd[k] = -(Ep - Em) / (2 * h)
+            assert np.allclose(out[0, :3], fd, rtol=1e-6, atol=1e-9), (rho, out[0, :3], fd)
 
 
 # ---------------------------------------------------------------- interpolation
@@ -516,3 +566,118 @@ def test_lateral_stiffness_affine_field_matches_eigvalsh():
     ref = np.linalg.eigvalsh(0.5 * (K + K.T))[:2]
     got = orc.lateral_stiffness(g, ff, PROBE, [anchor], [r])[0]
     np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-14)
+
+
+# ------------------------------------------------- grading eigenvalue, FIRE path
+def test_sym3_min_eig_matches_eigvalsh():
+    """The stability measure that decides which relaxed points are graded is the
+    smallest eigenvalue of a symmetric 3x3 matrix.  Against numpy's symmetric
+    eigensolver and against the eigenvalue each matrix was built with, on random
+    spectra and on the hard cases of an iterative solver: two or three equal
+    eigenvalues, clusters 1e-10 apart, diagonal and zero matrices, and spreads of
+    12 orders of magnitude."""
+    rng = np.random.default_rng(2401)
+    cases = []
+    for i in range(1200):
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        kind = i % 6
+        lam = rng.normal(size=3) * 10.0 ** rng.uniform(-3, 2)
+        if kind == 1:
+            lam[1] = lam[0]                                  # double eigenvalue
+        elif kind == 2:
+            lam[:] = lam[0]                                  # multiple of the identity
+        elif kind == 3:
+            lam[1] = lam[0] * (1 + 1e-10)                    # near-degenerate cluster
+            lam[2] = lam[0] * (1 - 1e-10)
+        elif kind == 4:
+            lam = np.array([1e-6, 1.0, 1e6]) * rng.choice([-1, 1], 3)
+        elif kind == 5:
+            Q = np.eye(3)[rng.permutation(3)]                # already diagonal
+        S = (Q * lam) @ Q.T
+        S = 0.5 * (S + S.T)
+        cases.append((S, lam.min()))
+    cases.append((np.zeros((3, 3)), 0.0))
+    for S, lmin in cases:
+        got = orc.sym3_min_eig(S)
+        scale = np.abs(S).max() + 1e-300
+        ref = np.linalg.eigvalsh(S)[0]
+        assert abs(got - ref) <= 1e-12 * scale, (S, got, ref)
+        assert abs(got - lmin) <= 1e-12 * scale, (S, got, lmin)
+
+
+def _fire_1d(G, fire, z0, dt0):
+    """FIRE on a one-dimensional force G(z), written for this test from Bitzek et
+    al. 2006: in one dimension a velocity that is parallel to the force stays
+    parallel under the mixing step, so the mixing is the identity and the path is
+    semi-implicit Euler under FIRE's time-step/alpha schedule alone.  Returns
+    (steps, z, dt, resets, increases) with the stopping rule of Sec. 5.1.1's
+    relaxation (|G| below the threshold or max_iter steps)."""
+    z, v, dt, alpha, npos, it = z0, 0.0, dt0, fire.alpha0, 0, 0
+    resets = increases = 0
+    g = G(z)
+    while not abs(g) < fire.f_conv and it < fire.max_iter:
+        if it > 0:
+            if g * v > 0.0:
+                npos += 1
+                if npos > fire.n_min:
+                    dt = min(dt * fire.f_inc, fire.dt_max)
+                    alpha *= fire.f_alpha
+                    increases += 1
+            else:
+                v, dt, alpha, npos = 0.0, dt * fire.f_dec, fire.alpha0, 0
+                resets += 1
+        v += g * dt / fire.mass
+        z += v * dt
+        g = G(z)
+        it += 1
+    return it, z, dt, resets, increases
+
+
+def test_fire_trajectory_on_a_one_dimensional_well():
+    """Pins FIRE's step counts, not only its fixed points.  On the tip axis of a
+    sample force that depends on z alone the probe feels the radial spring of
+    Eq. 2 (k_R along z) and the trilinear interpolant of the sample force, which
+    there is the piecewise-linear interpolant of the nodal Fz (numpy's interp), so
+    the relaxation is one-dimensional.  Every height's step count must equal that
+    of an independent one-dimensional FIRE, including the warm start between
+    heights (linear extrapolation of the displacement, time step carried over
+    and not below dt0), and the positions must agree to rounding."""
+    n, step, origin = (12, 12, 140), (0.1, 0.1, 0.1), (0.0, 0.0, 0.0)
+    g = _grid(origin=origin, step=step, n=n)
+    zs = origin[2] + step[2] * np.arange(n[2])
+    node_fz = 0.6 * np.exp(-(zs - 4.0) / 0.35) - 0.12 * np.exp(-(zs - 4.0) / 0.9)   # eV/A
+    ff = np.zeros((n[2], n[1], n[0], 4))
+    ff[..., 2] = node_fz[:, None, None]
+    x, y, z_top, dz, nz = 0.55, 0.45, 11.3, 0.1, 30
+    R0 = -PROBE.d0[2]
+    for f_conv, max_iter in ((1e-4, 1000), (1e-9, 5000), (1e-4, 7)):
+        fire = W.Fire(f_conv=f_conv, max_iter=max_iter)
+        res = orc.relaxed_scan(g, ff, PROBE, fire, _scan1(x, y, z_top, nz, dz))
+        u1 = u2 = 0.0
+        dt = fire.dt0
+        resets = increases = 0
+        for k in range(nz):
+            az = z_top - k * dz
+            if k == 0:
+                z0 = az - R0
+            elif k == 1:
+                z0 = az + u1
+            else:
+                z0 = az + u1 + (u1 - u2)
+
+            def G(z, az=az):
+                return float(np.interp(z, zs, node_fz)) + PROBE.k_rad * ((az - z) - R0)
+            it, z, dt, nr, ni = _fire_1d(G, fire, z0, max(dt, fire.dt0))
+            resets += nr
+            increases += ni
+            conv = abs(G(z)) < fire.f_conv
+            assert res["iters"][0, k] == (it if conv else -it), (f_conv, k, res["iters"][0, k], it)
+            assert res["r"][0, k, 2] == pytest.approx(z, abs=1e-11)
+            np.testing.assert_array_equal(res["r"][0, k, :2], [x, y])
+            u2, u1 = u1, z - az
+        # the path exercises both branches of the power test
+        assert resets > 0 and increases > 0
+        if max_iter == 7:
+            assert np.any(res["iters"][0] < 0)
+        else:
+            assert np.all(res["iters"][0] >= 0) and np.abs(res["iters"][0]).sum() > 150
