@@ -70,7 +70,12 @@ typedef int32_t ppm_status;
 /* Uniform grid.  Voxel (ix, iy, iz) sits at origin + (ix*step[0], iy*step[1],
  * iz*step[2]); n = (nx, ny, nz).  With periodic_xy = 1 the sample is periodic in
  * x and y with periods n[0]*step[0] and n[1]*step[1]: each pair uses the
- * minimum image and is included iff rho^2 < cutoff^2.  With periodic_xy = 0 the
+ * minimum image, is included iff rho^2 < cutoff^2, and is truncated with a
+ * shifted force: along every ray from the atom each pair term Y(direction)
+ * g(rho) (Y = 1 for LJ + Coulomb, 3 dz^2/rho^2 - 1 with g = rho^-3 for the d_z2
+ * term) becomes g - g(cutoff) - (rho - cutoff) g'(cutoff), so its energy and
+ * force vanish on the cutoff sphere (the paper names no cutoff scheme; a plain
+ * truncation leaves a force step on every charged atom's sphere).  With periodic_xy = 0 the
  * sum runs over all atoms (open boundary) and cutoff is ignored.  For
  * interpolation a periodic grid wraps in x and y; an open grid is clamped to
  * its first/last cell in x and y (the field is continued constantly beyond
@@ -337,7 +342,10 @@ ppm_status ppm_hartree_ff(const ppm_grid *grid, const float *V, const float *rho
                           size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
- * Batched pipeline: many molecules of different sizes, each scanned with one
+ * Batched pipeline (Sec. 4.4: large batches of simulated image stacks over
+ * many molecules and tip parameters for machine-learning data; Sec. 5.3: the
+ * per-run overheads that dominate small systems are paid once per batch):
+ * many molecules of different sizes, each scanned with one
  * or more probes, in one launch per stage.  Host tables describe the work; the
  * same tables copied to device memory are read by the kernels.  Force fields,
  * tip forces and frequency shifts live in arenas (one device buffer each) at
@@ -375,8 +383,10 @@ typedef struct {
  *   totals[0] force-field voxels (the FF arena holds 4 floats per voxel)
  *   totals[1] force-field work items, totals[2] fz values, totals[3] df values
  *   (0 if dfp is NULL), totals[4] scan work items.
- * All jobs must share scan.dz when dfp is given.  Errors: PPM_EINVAL for bad
- * tables (as the single-molecule calls would report), PPM_EUNSUPPORTED for a
+ * All jobs must share scan.dz when dfp is given, and R_pp, eps_pp, q_pp and
+ * q_zz (the force fields are built once, with one probe).  Errors: PPM_EINVAL
+ * for bad tables (as the single-molecule calls would report) or jobs whose
+ * probe LJ parameters or charges differ from job 0's, PPM_EUNSUPPORTED for a
  * stencil wider than 32 or jobs with different dz.
  */
 ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
@@ -400,7 +410,8 @@ ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
  * frequency-shift settings shared) in one launch, with the frequency shift
  * fused.  fz_arena (totals[2] floats) may be NULL when dfp is given; df_arena
  * (totals[3] floats) is required with dfp.  With more than 256 heights in any
- * job and a frequency shift, fz_arena is required.
+ * job and a frequency shift, fz_arena is required.  PPM_EINVAL also when the
+ * jobs' probe LJ parameters or charges differ from job 0's.
  */
 ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
                                   const ppm_batch_mol *mols_dev, int32_t n_jobs,

@@ -347,6 +347,11 @@ class BatchPipeline:
             eps.append(torch.as_tensor(atoms.eps, dtype=torch.float64))
         self.jobs = (_lib.BatchScan * self.n_jobs)()
         for j, (mi, pr, sc) in enumerate(jobs):
+            mine = (pr.R_pp, pr.eps_pp, pr.q_pp, float(getattr(pr, "q_zz", 0.0)))
+            built = (probe.R_pp, probe.eps_pp, probe.q_pp, float(getattr(probe, "q_zz", 0.0)))
+            if mine != built:
+                raise ValueError(f"job {j}: probe LJ parameters and charges {mine} differ from "
+                                 f"those the force fields are built with {built}")
             self.jobs[j].probe = _lib.probe_struct(pr)
             self.jobs[j].scan = _lib.scan_struct(sc)
             self.jobs[j].mol = int(mi)

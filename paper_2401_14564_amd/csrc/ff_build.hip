@@ -24,7 +24,16 @@
 //    brick centre (exact minimum image for every voxel of the brick as long as
 //    cutoff + brick half-diagonal < L/2, which the host checks), atoms beyond
 //    cutoff + half-diagonal of the centre are dropped with a deterministic
-//    ballot compaction, and each pair is masked by rho^2 < cutoff^2.
+//    ballot compaction, and each pair is masked by rho^2 < cutoff^2.  The
+//    cutoff is a shifted-force truncation: along every ray from an atom each
+//    pair term Y(direction) g(rho) becomes g - g(rc) - (rho - rc) g'(rc), so
+//    energy and force vanish on the cutoff sphere (a plain truncation leaves a
+//    force step k_e q_i q_PP / rc^2 on every charged atom's sphere, which makes
+//    the grid rough at the voxel scale and stalls the relaxation).  For the
+//    LJ + Coulomb pair this is E += fc rho - C, F -= fc d / rho with per-atom
+//    constants fc = -dU/drho(rc), C = U(rc) + rc fc; the radial part of the
+//    d_z2 term folds into the same two constants, its angular part adds
+//    kQ dz^2 (9 rho^-1 rc^-4 - 12 rho^-2 rc^-3) to E.
 #include "ppm.h"
 #include "ppm_kernels.h"
 
@@ -44,6 +53,7 @@ template <int NT>
 struct BrickLds {
     float4 geo[NT];   // brick-local (x, y, z) and R_iP^2
     float4 par[NT];   // e_iP, 12 e_iP, kq_i, kQ_i
+    float2 sf[NT];    // shifted-force constants fc, C (periodic only)
     int wcnt[NT / 64];
 };
 
@@ -63,7 +73,17 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     constexpr int NW = NT / 64;
     float4 *s_geo = lds.geo;
     float4 *s_par = lds.par;
+    float2 *s_sf = lds.sf;
     int *s_wcnt = lds.wcnt;
+    // angular part of the shifted d_z2 term: 9 rc^-4, 12 rc^-3, 18 rc^-4, 24 rc^-3
+    float c9 = 0.f, c12 = 0.f, c18 = 0.f, c24 = 0.f;
+    if (PERIODIC && QUAD) {
+        const double irc3 = 1.0 / (a.rc * a.rc * a.rc), irc4 = irc3 / a.rc;
+        c9 = (float)(9.0 * irc4);
+        c12 = (float)(12.0 * irc3);
+        c18 = (float)(18.0 * irc4);
+        c24 = (float)(24.0 * irc3);
+    }
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
@@ -88,6 +108,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         const int i = base + tid;
         bool keep = false;
         float4 geo = make_float4(0.f, 0.f, 0.f, 0.f), par = geo;
+        float2 sfc = make_float2(0.f, 0.f);
         if (i < a.n_atoms) {
             double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
             if (PERIODIC) {
@@ -102,6 +123,21 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             geo = make_float4((float)dx, (float)dy, (float)dz, (float)(RiP * RiP));
             par = make_float4((float)eiP, (float)(12.0 * eiP), (float)(a.kq_pp * q[i]),
                               (float)(a.kQ_pp * q[i]));
+            if (PERIODIC) {
+                // U(rc) and fc = -dU/drho(rc) of the LJ + Coulomb pair, in FP64
+                const double rc = a.rc, irc = 1.0 / rc;
+                const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2;
+                const double sc12 = sc6 * sc6, kq = a.kq_pp * q[i];
+                const double Uc = eiP * (sc12 - 2.0 * sc6) + kq * irc;
+                double fc = 12.0 * eiP * (sc12 - sc6) * irc + kq * irc * irc;
+                double C = Uc + rc * fc;
+                if (QUAD) {    // radial part of the shifted d_z2 term
+                    const double kQ = a.kQ_pp * q[i], irc3 = irc * irc * irc;
+                    fc -= 3.0 * kQ * irc3 * irc;
+                    C -= 4.0 * kQ * irc3;
+                }
+                sfc = make_float2((float)fc, (float)C);
+            }
         }
         int cnt, slot;
         if (PERIODIC) {
@@ -126,12 +162,14 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         if (keep) {
             s_geo[slot] = geo;
             s_par[slot] = par;
+            if (PERIODIC) s_sf[slot] = sfc;
         }
         __syncthreads();
 
         for (int j = 0; j < cnt; ++j) {
             const float4 g = s_geo[j];
             const float4 p = s_par[j];
+            const float2 sf = PERIODIC ? s_sf[j] : make_float2(0.f, 0.f);
             const float dx = vx - g.x, dy = vy - g.y;
             const float dxy2 = fmaf(dx, dx, dy * dy);
 #pragma unroll
@@ -139,15 +177,22 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                 const float dz = vz[k] - g.z;
                 const float r2 = fmaf(dz, dz, dxy2);
                 float ir = __builtin_amdgcn_rsqf(r2);
-                if (PERIODIC) ir = (r2 < a.rc2) ? ir : 0.0f;
+                const bool in = !PERIODIC || r2 < a.rc2;
+                if (PERIODIC) ir = in ? ir : 0.0f;
                 const float ir2 = ir * ir;
                 const float s2 = g.w * ir2;
                 const float s6 = s2 * s2 * s2;
                 const float s12 = s6 * s6;
                 const float ec = p.z * ir;
-                E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + ec;
+                float et = ec;
+                if (PERIODIC) {     // shifted force: + fc rho - C inside the sphere
+                    const float t = fmaf(sf.x, r2 * ir, ec - sf.y);
+                    et = in ? t : 0.0f;
+                }
+                E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + et;
                 float f = 0.0f;
                 if (!EONLY) f = fmaf(p.y, s12 - s6, ec) * ir2;
+                if (PERIODIC && !EONLY) f = fmaf(-sf.x, ir, f);
                 if (QUAD) {
                     // u = (3 dz^2 - rho^2)/rho^5,
                     // -grad u = rho^-5 [(15 dz^2/rho^2 - 3) d - 6 dz e_z]
@@ -157,6 +202,17 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                     if (!EONLY) {
                         f = fmaf(q5, fmaf(15.0f * z2, ir2, -3.0f), f);
                         Fz[k] = fmaf(-6.0f * q5, dz, Fz[k]);
+                    }
+                    if (PERIODIC) {
+                        // angular part of the shift: kQ dz^2 (9 rc^-4/rho - 12 rc^-3/rho^2),
+                        // its -grad: -kQ [dz^2 rho^-3 (24 rc^-3/rho - 9 rc^-4) d
+                        //                 + dz rho^-1 (18 rc^-4 - 24 rc^-3/rho) e_z]
+                        const float qz2 = p.w * z2;
+                        E[k] = fmaf(qz2, fmaf(c9, ir, -c12 * ir2), E[k]);
+                        if (!EONLY) {
+                            f = fmaf(-qz2 * ir2 * ir, fmaf(c24, ir, -c9), f);
+                            Fz[k] = fmaf(-p.w * dz * ir, fmaf(-c24, ir, c18), Fz[k]);
+                        }
                     }
                 }
                 if (!EONLY) {
@@ -240,6 +296,7 @@ __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
         a.Ly = a.ny * a.hy;
         a.rc2 = (float)(M.grid.cutoff * M.grid.cutoff);
         a.cull2 = (M.grid.cutoff + hd) * (M.grid.cutoff + hd);
+        a.rc = M.grid.cutoff;
         ff_brick<BX, BY, NZB, true, false, QUAD>(a, (rest % nbx) * BX, (rest / nbx) * BY,
                                                  bz * NZB, pos + 3 * (size_t)off, q + off,
                                                  R + off, eps + off, ff, lds);

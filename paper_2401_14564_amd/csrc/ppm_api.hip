@@ -211,6 +211,7 @@ static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t
         a->Ly = Ly;
         a->rc2 = (float)(grid->cutoff * grid->cutoff);
         a->cull2 = (grid->cutoff + hd) * (grid->cutoff + hd);
+        a->rc = grid->cutoff;
     }
     return PPM_OK;
 }
@@ -351,6 +352,7 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
     A.Lx = grid->n[0] * grid->step[0];
     A.Ly = grid->n[1] * grid->step[1];
     A.rc2 = (float)(grid->cutoff * grid->cutoff);
+    A.rc = grid->cutoff;
     A.n_atoms = n_atoms;
     A.R_pp = probe->R_pp;
     A.eps_pp = probe->eps_pp;
@@ -407,6 +409,7 @@ ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
         ppm_batch_scan &J = jobs[j];
         if (J.mol < 0 || J.mol >= n_mol) return PPM_EINVAL;
         if ((st = check_probe(&J.probe)) != PPM_OK) return st;
+        if (!same_probe_lj(J.probe, jobs[0].probe)) return PPM_EINVAL;
         if ((st = check_scan(&J.scan)) != PPM_OK) return st;
         if (dfp) {
             if (J.scan.dz != jobs[0].scan.dz) return PPM_EUNSUPPORTED;
@@ -498,6 +501,7 @@ ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
         const ppm_batch_scan &J = jobs_host[j];
         if (J.mol < 0 || J.mol >= n_mol) return PPM_EINVAL;
         if ((st = check_probe(&J.probe)) != PPM_OK) return st;
+        if (!same_probe_lj(J.probe, jobs_host[0].probe)) return PPM_EINVAL;
         if ((st = check_scan(&J.scan)) != PPM_OK) return st;
         if (J.fz_offset != nfz || J.tile_begin != tiles) return PPM_EINVAL;   // not planned
         if (df_arena) {

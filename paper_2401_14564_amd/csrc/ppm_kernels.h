@@ -32,6 +32,7 @@ struct FFArgs {
     double Lx, Ly;            // periods (periodic only)
     float rc2;                // cutoff^2 (periodic only)
     double cull2;             // (cutoff + brick half-diagonal)^2 (periodic only)
+    double rc;                // cutoff (periodic only; shifted-force truncation)
 };
 
 hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *mols_dev,
@@ -182,9 +183,10 @@ hipError_t launch_hartree(const FftPlan plans[3], int nx, int ny, int nz, double
 struct BwdArgs {
     ScanArgs s;               // same grid/probe/scan description as the forward
     double hx, hy, hz;        // grid steps
-    int periodic;             // minimum image in x,y
+    int periodic;             // minimum image in x,y and shifted-force cutoff rc
     double Lx, Ly;
     float rc2;
+    double rc;
     int n_atoms;
     double R_pp, eps_pp, kq_pp, ke_qpp;
     double kQ_pp;             // k_e * q_zz; the scatter adds the quadrupole terms if != 0

@@ -162,8 +162,11 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
 // the d_z2 quadrupole q_zz, whose pair force is f = -kQ grad u with
 // u = (3 dz^2 - rho^2)/rho^5 and grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7,
 // b = 6 dz rho^-5; its derivatives are df/d(atom) = kQ hess u and
-// df/dq = -k_e q_zz grad u.
-template <bool QUAD>
+// df/dq = -k_e q_zz grad u.  PERIODIC: minimum image and the shifted-force
+// cutoff of the force-field build: phi gains -fc/rho (fc = -dU/drho at rc of
+// the LJ + Coulomb pair), u gains Y (3 rho rc^-4 - 4 rc^-3) with
+// Y = 3 dz^2/rho^2 - 1, and pairs beyond rc drop out.
+template <bool QUAD, bool PERIODIC>
 __global__ __launch_bounds__(64) void atom_scatter_kernel(
     const BwdArgs A, const EqRecord *__restrict__ rec, const double *__restrict__ pos,
     const double *__restrict__ q, const double *__restrict__ R, const double *__restrict__ eps,
@@ -180,6 +183,23 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
     const float e12 = (float)(12.0 * eiP);
     const float kq = (float)(A.kq_pp * q[ia]);
     const float kQ = (float)(A.kQ_pp * q[ia]);
+    // shifted-force constants of this atom (periodic): fc, and the rc-terms of
+    // d phi / d(R_iP, e_iP, kq) per 1/rho
+    float fcm = 0.f, irc2 = 0.f, aRc = 0.f, aec = 0.f;
+    float c3 = 0.f, c9 = 0.f, c18 = 0.f, c24 = 0.f;
+    if (PERIODIC) {
+        const double irc = 1.0 / A.rc;
+        const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2, sc12 = sc6 * sc6;
+        fcm = (float)(12.0 * eiP * (sc12 - sc6) * irc + A.kq_pp * q[ia] * irc * irc);
+        irc2 = (float)(irc * irc);
+        aRc = (float)((2.0 * sc12 - sc6) * irc);
+        aec = (float)((sc12 - sc6) * irc);
+        const double irc3 = irc * irc * irc, irc4 = irc3 * irc;
+        c3 = (float)(3.0 * irc4);
+        c9 = (float)(9.0 * irc4);
+        c18 = (float)(18.0 * irc4);
+        c24 = (float)(24.0 * irc3);
+    }
 
     double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0, gqq = 0.0;
     const size_t n_eq = (size_t)a.snx * a.sny * a.snz;
@@ -193,7 +213,7 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
         const int cy1 = (r.idx.y + 1 < a.gny) ? r.idx.y + 1 : 0;
         double ddx0 = a.ox + r.idx.x * A.hx - px, ddx1 = a.ox + cx1 * A.hx - px;
         double ddy0 = a.oy + r.idx.y * A.hy - py, ddy1 = a.oy + cy1 * A.hy - py;
-        if (A.periodic) {
+        if (PERIODIC) {
             ddx0 -= A.Lx * rint(ddx0 / A.Lx);
             ddx1 -= A.Lx * rint(ddx1 / A.Lx);
             ddy0 -= A.Ly * rint(ddy0 / A.Ly);
@@ -214,34 +234,58 @@ __global__ __launch_bounds__(64) void atom_scatter_kernel(
             const float dx = dxs[i], dy = dys[j], dz = dzs[k];
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             float ir = __builtin_amdgcn_rsqf(r2);
-            if (A.periodic) ir = (r2 < A.rc2) ? ir : 0.0f;
+            if (PERIODIC) ir = (r2 < A.rc2) ? ir : 0.0f;
             const float ir2 = ir * ir;
             const float ir3 = ir * ir2;
             const float s2 = R2 * ir2;
             const float s6 = s2 * s2 * s2;
             const float s12 = s6 * s6;
             const float ec = kq * ir;
-            const float phi = fmaf(e12, s12 - s6, ec) * ir2;
+            float phi = fmaf(e12, s12 - s6, ec) * ir2;
             // phi'(rho)/rho = ir2^2 [12 e (-14 s12 + 8 s6) - 3 kq/rho]
-            const float dphi = fmaf(e12, fmaf(-14.0f, s12, 8.0f * s6), -3.0f * ec) * ir2 * ir2;
+            float dphi = fmaf(e12, fmaf(-14.0f, s12, 8.0f * s6), -3.0f * ec) * ir2 * ir2;
+            if (PERIODIC) {
+                phi = fmaf(-fcm, ir, phi);
+                dphi = fmaf(fcm, ir3, dphi);
+            }
             const float md = fmaf(mx, dx, fmaf(my, dy, mz * dz));
             const float tq = dphi * md;
             ax_ -= fmaf(phi, mx, tq * dx);
             ay_ -= fmaf(phi, my, tq * dy);
             az_ -= fmaf(phi, mz, tq * dz);
             const float im = ir2 * md;
-            aq = fmaf(ir3, md, aq);                       // x k_e q_pp
-            aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
-            ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+            if (PERIODIC) {
+                const float jm = ir * md;
+                aq = fmaf(fmaf(-irc2, ir, ir3), md, aq);
+                aR = fmaf(fmaf(2.0f, s12, -s6), im, fmaf(-aRc, jm, aR));
+                ae = fmaf(s12 - s6, im, fmaf(-aec, jm, ae));
+            } else {
+                aq = fmaf(ir3, md, aq);                       // x k_e q_pp
+                aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
+                ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+            }
             if (QUAD) {
                 const float ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
                 const float z2 = dz * dz;
-                const float ua = fmaf(-15.0f * z2, ir7, 3.0f * ir5);
-                const float ub = 6.0f * dz * ir5;
+                float ua = fmaf(-15.0f * z2, ir7, 3.0f * ir5);
+                float ub = 6.0f * dz * ir5;
                 // grad a . m and grad b . m
-                const float ga = fmaf(fmaf(105.0f * z2, ir9, -15.0f * ir7), md,
-                                      -30.0f * dz * ir7 * mz);
-                const float gb = fmaf(6.0f * ir5, mz, -30.0f * dz * ir7 * md);
+                float ga = fmaf(fmaf(105.0f * z2, ir9, -15.0f * ir7), md,
+                                -30.0f * dz * ir7 * mz);
+                float gb = fmaf(6.0f * ir5, mz, -30.0f * dz * ir7 * md);
+                if (PERIODIC) {
+                    // shifted d_z2 term: grad u gains ax d + bx e_z with
+                    // ax = -9 rc^-4 dz^2 rho^-3 + 24 rc^-3 dz^2 rho^-4 - 3 rc^-4 rho^-1,
+                    // bx = 18 rc^-4 dz rho^-1 - 24 rc^-3 dz rho^-2
+                    const float ir4 = ir2 * ir2, ir6 = ir4 * ir2;
+                    ua += fmaf(z2, fmaf(c24, ir4, -c9 * ir3), -c3 * ir);
+                    ub += dz * fmaf(c18, ir, -c24 * ir2);
+                    ga += fmaf(-c9, fmaf(2.0f * dz * ir3, mz, -3.0f * z2 * ir5 * md),
+                               fmaf(c24, fmaf(2.0f * dz * ir4, mz, -4.0f * z2 * ir6 * md),
+                                    c3 * ir3 * md));
+                    gb += fmaf(c18, fmaf(ir, mz, -dz * ir3 * md),
+                               -c24 * fmaf(ir2, mz, -2.0f * dz * ir4 * md));
+                }
                 ax_ = fmaf(kQ, fmaf(ua, mx, dx * ga), ax_);
                 ay_ = fmaf(kQ, fmaf(ua, my, dy * ga), ay_);
                 az_ = fmaf(kQ, fmaf(ua, mz, fmaf(dz, ga, gb)), az_);
@@ -335,12 +379,21 @@ hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *f
     if (A.n_atoms == 0) return hipSuccess;
     const int na_blocks = (A.n_atoms + 63) / 64;
     dim3 g2(A.n_eq_blocks, na_blocks, 1);
-    if (A.kQ_pp != 0.0)
-        hipLaunchKernelGGL(atom_scatter_kernel<true>, g2, dim3(64, 1, 1), 0, stream, A, rec, pos,
-                           q, R, eps, partial_ws);
-    else
-        hipLaunchKernelGGL(atom_scatter_kernel<false>, g2, dim3(64, 1, 1), 0, stream, A, rec, pos,
-                           q, R, eps, partial_ws);
+    if (A.kQ_pp != 0.0) {
+        if (A.periodic)
+            hipLaunchKernelGGL((atom_scatter_kernel<true, true>), g2, dim3(64, 1, 1), 0, stream,
+                               A, rec, pos, q, R, eps, partial_ws);
+        else
+            hipLaunchKernelGGL((atom_scatter_kernel<true, false>), g2, dim3(64, 1, 1), 0, stream,
+                               A, rec, pos, q, R, eps, partial_ws);
+    } else {
+        if (A.periodic)
+            hipLaunchKernelGGL((atom_scatter_kernel<false, true>), g2, dim3(64, 1, 1), 0, stream,
+                               A, rec, pos, q, R, eps, partial_ws);
+        else
+            hipLaunchKernelGGL((atom_scatter_kernel<false, false>), g2, dim3(64, 1, 1), 0, stream,
+                               A, rec, pos, q, R, eps, partial_ws);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_kernel, dim3(A.n_atoms * 6, 1, 1), dim3(256, 1, 1), 0, stream,

@@ -172,6 +172,14 @@ def test_batch_plan_offsets_on_host():
     # a job pointing at a missing molecule is rejected
     jobs[5].mol = 3
     assert L.ppm_batch_plan(3, mols, 6, jobs, None, totals) == _lib.PPM_EINVAL
+    jobs[5].mol = 2
+    # springs may differ per job, the probe's LJ parameters and charges may not
+    import dataclasses
+    jobs[4].probe = _lib.probe_struct(dataclasses.replace(ws[2].probe, k_lat=(0.01, 0.02)))
+    assert L.ppm_batch_plan(3, mols, 6, jobs, None, totals) == _lib.PPM_OK
+    for change in (dict(q_pp=-0.1), dict(q_zz=-0.05), dict(R_pp=1.7), dict(eps_pp=0.01)):
+        jobs[4].probe = _lib.probe_struct(dataclasses.replace(ws[2].probe, **change))
+        assert L.ppm_batch_plan(3, mols, 6, jobs, None, totals) == _lib.PPM_EINVAL, change
 
 
 def test_hartree_sizes_and_bad_arguments():

@@ -42,36 +42,58 @@ def test_batch_equals_single_calls_bitwise():
 
 
 def test_batch_parity_with_oracle_sampled_columns():
-    """Two molecules, two probes each, at the parity convergence threshold; 150
-    seeded columns per job re-run by the oracle."""
+    """Two molecules, two probes each, at the parity convergence threshold.  The
+    batched build is checked against the oracle's grid; then the oracle's grid,
+    rounded to FP32, is copied into the arena so that the batched scan and the
+    oracle relax on the same input, and 150 seeded columns per job are re-run by
+    the oracle.  A column that settles in another equilibrium (a jump in Fz) is
+    certified point by point from the height where it departs, with the probe
+    positions of the single-molecule scan (whose Fz equals the batch's bit for
+    bit)."""
     ws, mols, jobs = _c3_batch([5, 6], k_lats=(0.25, 0.5))
     fire = W.parity_fire(ws[0].fire)
     bp = ppm.BatchPipeline(mols, jobs, ws[0].probe, fire, ws[0].df, keep_fz=True)
-    bp.run()
+    bp.build_ff()
+    torch.cuda.synchronize()
+    refs = []
+    for mi, w in enumerate(ws):
+        ref, sc_ = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
+        ok = sc_[..., 2] >= 0.5
+        ff64 = bp.ff_grid(mi).cpu().numpy().astype(np.float64)
+        err = np.abs(ff64[..., :3] - ref[..., :3])[ok].max(axis=-1) / sc_[..., 0][ok]
+        assert err.max() <= 1e-5
+        refs.append(ref.astype(np.float32))
+        bp.ff_grid(mi).copy_(torch.as_tensor(refs[-1], device="cuda"))
+    bp.scan()
     torch.cuda.synchronize()
     rng = np.random.default_rng(33)
     for j, (mi, pr, sc) in enumerate(jobs):
         w = ws[mi]
-        ff64 = bp.ff_grid(mi).cpu().numpy().astype(np.float64)
-        ref, sc_ = orc.build_ff(w.grid, w.probe, w.atoms, with_scale=True)
-        ok = sc_[..., 2] >= 0.5
-        err = np.abs(ff64[..., :3] - ref[..., :3])[ok].max(axis=-1) / sc_[..., 0][ok]
-        assert err.max() <= 1e-5
         cols = np.stack([rng.integers(0, sc.nx, 150), rng.integers(0, sc.ny, 150)], axis=1)
-        # oracle scans its own FP32-rounded grid; the batch scanned its own build
-        ff32 = ref.astype(np.float32).astype(np.float64)
+        ff32 = refs[mi].astype(np.float64)
         ores = orc.relaxed_scan(w.grid, ff32, pr, fire, sc, cols=cols, polish_tol=1e-12,
                                 with_lambda=True)
         fz = bp.fz_stack(j).cpu().numpy()
-        # the batch keeps no probe state: compare through Fz and df only
+        # the batch keeps no probe state: compare through Fz and df
         info = grade_df_only(w, pr, fire, sc, cols, ores, fz, bp.df_stack(j).cpu().numpy())
-        print("batch job", j, info, flush=True)
+        if info["basin_cols"]:
+            single = ppm.relaxed_scan(w.grid, bp.ff_grid(mi), pr, fire, sc, pp=True)
+            assert torch.equal(single["fz"], bp.fz_stack(j))
+            pp = single["pp"].cpu().numpy()
+            from parity import anchors_for
+            for c, k0 in info["departures"]:
+                A = anchors_for(sc, cols[c:c + 1])[0, k0:]
+                r = A + np.asarray(pr.d0) + pp[k0:, cols[c, 1], cols[c, 0], :3]
+                gn, _ = orc.residual(w.grid, ff32, pr, A, r)
+                assert np.all(gn <= 2 * fire.f_conv + 1e-6), (j, c, k0, gn.max())
+        print("batch job", j, {k: v for k, v in info.items() if k != "departures"}, flush=True)
 
 
 def grade_df_only(w, probe, fire, scan, cols, ores, fz, df):
     """Without probe positions, compare Fz and df at points the oracle grades
     (stability eigenvalue >= 1e-2): |dFz| <= 1e-5 eV/A there and |d df| <= 1e-3 Hz
-    at outputs whose stencil is graded."""
+    at outputs whose stencil is graded.  Columns whose Fz jumps away (another
+    equilibrium) are returned with the height they depart at, for certification."""
     cols = np.asarray(cols)
     gfz = fz[:, cols[:, 1], cols[:, 0]].T
     graded = ores["lam"] >= 1e-2
@@ -81,6 +103,7 @@ def grade_df_only(w, probe, fire, scan, cols, ores, fz, df):
     far = (dfz > 1e-5) & graded
     bad_cols = np.unique(np.nonzero(far)[0])
     assert len(bad_cols) <= 0.02 * len(cols), f"{len(bad_cols)} columns disagree"
+    departures = [(int(c), int(np.nonzero(dfz[c] > 1e-5)[0][0])) for c in bad_cols]
     keep = np.ones(len(cols), bool)
     keep[bad_cols] = False
     m = orc.df_m(1.0, scan.dz)
@@ -92,7 +115,7 @@ def grade_df_only(w, probe, fire, scan, cols, ores, fz, df):
     d = np.abs(gdf - odf)
     assert np.all(d[win] <= 1e-3), f"worst {d[win].max():.3e} Hz"
     return dict(graded_df=int(win.sum()), total_df=int(win.size), worst_ddf=float(d[win].max()),
-                basin_cols=len(bad_cols))
+                basin_cols=len(bad_cols), departures=departures)
 
 
 def test_batch_graph_replays_match_eager():

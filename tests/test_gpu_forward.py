@@ -307,3 +307,184 @@ def test_scan_single_column(nz):
     info = grade_scan(w.grid, E64, w.probe, fire, scan, otr["cols"], otr, gt["pp"], gt["fz"],
                       label=f"one column tricubic nz {nz}", residual=orc.residual_tricubic)
     assert info["graded"] == info["points"], info
+
+
+def _c2_window():
+    """A 100 x 100-column window of the large periodic workload that crosses the
+    cell's x edge (tips at x = 36.0 ... 45.9 A, wrapping at 40 A) and the flake's
+    edge, all 120 heights; the oracle's force field on the voxels its probes can
+    reach (a 2 A lateral margin, z-layers 100 to 239), NaN elsewhere so that any
+    read outside shows."""
+    w = W.config2()
+    scan = W.Scan(36.0, 14.0, 0.1, 0.1, 100, 100, w.scan.z_top, w.scan.dz, w.scan.nz)
+    w = W.Workload("C2 window", w.atoms, w.grid, w.probe, w.fire, scan, w.df)
+    nx, ny, nz = w.grid.n
+    ix = np.arange(340, 481) % nx
+    iy = np.arange(120, 261)
+    iz = np.arange(100, 240)
+    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+    idx = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.int32)
+    vals = orc.ff_voxels(w.grid, w.probe, w.atoms, idx, with_scale=False)
+    ff32 = np.full((nz, ny, nx, 4), np.nan, dtype=np.float32)
+    ff32[idx[:, 2], idx[:, 1], idx[:, 0]] = vals.astype(np.float32)
+    return w, ff32
+
+
+def test_scan_c2_window_parity_and_certificates():
+    """Large periodic sample (shifted-force 12 A cutoff): the GPU scans a
+    100 x 100 x 120 window at the parity threshold, graded against the polished
+    oracle on 300 seeded columns (positions, Fz and the frequency shift), then at
+    the benchmark's threshold (1e-4 eV/A, FP32 interpolation arithmetic), where
+    every point must converge and 4,000 seeded points are certified by the
+    oracle's FP64 force balance."""
+    w, ff32 = _c2_window()
+    ffd = torch.as_tensor(ff32, device="cuda")
+    fire = W.parity_fire(w.fire)
+    res = ppm.relaxed_scan(w.grid, ffd, w.probe, fire, w.scan, dfp=w.df)
+    g = {k: v.cpu().numpy() for k, v in res.items()}
+    assert np.all(np.isfinite(g["pp"])) and np.all(np.isfinite(g["df"]))
+    rng = np.random.default_rng(2202)
+    cols = np.stack([rng.integers(0, w.scan.nx, 300), rng.integers(0, w.scan.ny, 300)], axis=1)
+    ff64 = ff32.astype(np.float64)
+    ores = orc.relaxed_scan(w.grid, ff64, w.probe, fire, w.scan, cols=cols, polish_tol=1e-12,
+                            with_lambda=True)
+    assert np.all(np.isfinite(ores["r"]))
+    info = grade_scan(w.grid, ff64, w.probe, fire, w.scan, cols, ores, g["pp"], g["fz"],
+                      g["df"], w.df, label="C2 window")
+    print("C2 window scan", info, flush=True)
+    assert info["graded"] > 0.9 * info["points"]
+    # the benchmark's threshold
+    thr = ppm.relaxed_scan(w.grid, ffd, w.probe, w.fire, w.scan, dfp=w.df)
+    pp = thr["pp"].cpu().numpy()
+    assert np.all(pp[..., 3] >= 0), f"{int(np.sum(pp[..., 3] < 0))} points not converged"
+    n = 4000
+    ix, iy = rng.integers(0, w.scan.nx, n), rng.integers(0, w.scan.ny, n)
+    k = rng.integers(0, w.scan.nz, n)
+    from parity import anchors_for
+    A = anchors_for(w.scan, np.stack([ix, iy], axis=1))[np.arange(n), k]
+    r = A + np.asarray(w.probe.d0) + pp[k, iy, ix, :3]
+    gn, _ = orc.residual(w.grid, ff64, w.probe, A, r)
+    print("C2 window certificate: max |G| - f_conv", float((gn - w.fire.f_conv).max()),
+          "mean FIRE steps", float(pp[..., 3].mean()), flush=True)
+    assert np.all(gn < w.fire.f_conv + 2e-6)
+
+
+def test_scan_c2_full_lattice_converges():
+    """The whole large periodic scan as the benchmark runs it (GPU force field,
+    400 x 400 tips x 120 heights, 1e-4 eV/A): every point converges."""
+    w = W.config2()
+    ff = _gpu_ff(w)
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, fz=False, pp=True)
+    it = res["pp"][..., 3]
+    bad = int((it < 0).sum().item())
+    print("C2 full lattice: mean FIRE steps", float(it.abs().mean().item()), "max",
+          float(it.abs().max().item()), "not converged", bad, flush=True)
+    assert bad == 0
+
+
+def test_scan_fire_step_counts_match_oracle_c0():
+    """FIRE's path, not only its end point: at the parity threshold (FP64
+    interpolation arithmetic on the GPU) the number of FIRE steps per relaxed
+    point equals the oracle's (no polish, so both warm starts see the same
+    previous equilibria) on at least 99% of the tiny workload's points; where
+    they differ, by few steps."""
+    w = W.config0()
+    fire = W.parity_fire(w.fire)
+    ff32 = orc.build_ff(w.grid, w.probe, w.atoms).astype(np.float32)
+    res = ppm.relaxed_scan(w.grid, torch.as_tensor(ff32, device="cuda"), w.probe, fire, w.scan,
+                           fz=False)
+    steps = res["pp"][..., 3].cpu().numpy()                  # [nz, ny, nx]
+    ores = orc.relaxed_scan(w.grid, ff32.astype(np.float64), w.probe, fire, w.scan)
+    cols = ores["cols"]
+    gsteps = steps[:, cols[:, 1], cols[:, 0]].T              # [col, k]
+    same = gsteps == ores["iters"]
+    diff = np.abs(gsteps - ores["iters"])
+    print(f"C0 FIRE steps: {same.mean() * 100:.3f}% identical, {int((~same).sum())} differ "
+          f"(largest difference {int(diff.max())}), mean {float(np.abs(gsteps).mean()):.2f}",
+          flush=True)
+    assert same.mean() >= 0.99
+    assert np.all(gsteps >= 0) and np.all(ores["iters"] >= 0)
+
+
+def test_scan_forced_nonconvergence_is_not_an_error():
+    """Non-convergence is reported, not raised: with max_iter = 2 the call
+    succeeds, points that need more steps carry -2, the others their step count,
+    and the lateral stiffness is NaN exactly where the relaxation did not
+    converge."""
+    w = W.config0()
+    scan = W.Scan(6.3, 6.9, 0.2, 0.2, 21, 13, 9.5, 0.1, 17)
+    fire = W.Fire(max_iter=2)
+    ff = ppm.build_ff(w.grid, w.probe, w.atoms)
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, fire, scan, dfp=w.df)
+    steps = res["pp"][..., 3].cpu().numpy()
+    assert np.all((steps == -2) | ((steps >= 0) & (steps <= 2)))
+    assert np.sum(steps < 0) > 0.5 * steps.size
+    k = ppm.lateral_stiffness(w.grid, ff, w.probe, scan, res["pp"]).cpu().numpy()
+    assert np.array_equal(np.isnan(k).any(axis=-1), steps < 0)
+    assert np.all(np.isfinite(k[steps >= 0]))
+
+
+def test_scan_mirror_and_translation_invariance():
+    """The scan commutes with the symmetries of the method (the oracle's force
+    field pins the same for the grid): mirroring the force field in x about the
+    grid's centre plane (Fx -> -Fx) and the tip lattice with it mirrors every
+    relaxed displacement (ux -> -ux) and keeps Fz and the frequency shift; moving
+    the grid origin and the tip lattice together by any offset changes nothing.
+    At the parity threshold both hold to 1e-5 A, 1e-5 eV/A and 1e-4 Hz (the
+    interpolation weights round differently)."""
+    w = W.config0()
+    fire = W.parity_fire(w.fire)
+    g = W.Grid((4.0, 4.0, -2.0), (0.1, 0.1, 0.1), (80, 80, 110))
+    scan = W.Scan(6.3, 6.55, 0.13, 0.11, 23, 19, 10.0, 0.1, 24)
+    ff32 = orc.build_ff(g, w.probe, w.atoms).astype(np.float32)
+    base = ppm.relaxed_scan(g, torch.as_tensor(ff32, device="cuda"), w.probe, fire, scan,
+                            dfp=w.df)
+    b = {k: v.cpu().numpy() for k, v in base.items()}
+    # mirror x about the plane through voxel (nx - 1)/2
+    xc = g.origin[0] + 0.5 * (g.n[0] - 1) * g.step[0]
+    mf = ff32[:, :, ::-1, :].copy()
+    mf[..., 0] *= -1.0
+    mscan = W.Scan(2 * xc - (scan.x0 + (scan.nx - 1) * scan.dx), scan.y0, scan.dx, scan.dy,
+                   scan.nx, scan.ny, scan.z_top, scan.dz, scan.nz)
+    mir = {k: v.cpu().numpy() for k, v in ppm.relaxed_scan(
+        g, torch.as_tensor(mf, device="cuda"), w.probe, fire, mscan, dfp=w.df).items()}
+    mp = mir["pp"][:, :, ::-1, :]
+    np.testing.assert_allclose(mp[..., 0], -b["pp"][..., 0], atol=1e-5)
+    np.testing.assert_allclose(mp[..., 1:3], b["pp"][..., 1:3], atol=1e-5)
+    np.testing.assert_allclose(mir["fz"][:, :, ::-1], b["fz"], atol=1e-5)
+    np.testing.assert_allclose(mir["df"][:, :, ::-1], b["df"], atol=1e-4)
+    # translation of grid and tips together
+    d = np.array([0.7371, -1.0523, 0.4189])
+    tg = W.Grid(tuple(np.array(g.origin) + d), g.step, g.n)
+    tscan = W.Scan(scan.x0 + d[0], scan.y0 + d[1], scan.dx, scan.dy, scan.nx, scan.ny,
+                   scan.z_top + d[2], scan.dz, scan.nz)
+    tr = {k: v.cpu().numpy() for k, v in ppm.relaxed_scan(
+        tg, torch.as_tensor(ff32, device="cuda"), w.probe, fire, tscan, dfp=w.df).items()}
+    np.testing.assert_allclose(tr["pp"][..., :3], b["pp"][..., :3], atol=1e-5)
+    np.testing.assert_allclose(tr["fz"], b["fz"], atol=1e-5)
+    np.testing.assert_allclose(tr["df"], b["df"], atol=1e-4)
+
+
+def test_ff_force_is_negative_energy_gradient_on_fine_grid():
+    """F = -grad E on the GPU: 3 x 3 x 3 grids of 1e-3 A spacing at 40 seeded
+    places around the paper-scale molecule; the force at the centre voxel against
+    the central difference of the stored FP32 energy.  The bound is the FP32
+    rounding of E over 2e-3 A (1e-7 of the energy's magnitude sum, divided by
+    the step) plus 1e-3 of |F|."""
+    w = W.config1()
+    rng = np.random.default_rng(404)
+    h = 1e-3
+    worst = 0.0
+    for _ in range(40):
+        c = np.array([rng.uniform(7.0, 17.0), rng.uniform(7.0, 17.0), rng.uniform(2.8, 6.0)])
+        g = W.Grid(tuple(c - h), (h, h, h), (3, 3, 3))
+        f = ppm.build_ff(g, w.probe, w.atoms).cpu().numpy().astype(np.float64)
+        _, sc = orc.ff_voxels(g, w.probe, w.atoms, np.array([[1, 1, 1]], dtype=np.int32))
+        fd = -np.array([(f[1, 1, 2, 3] - f[1, 1, 0, 3]), (f[1, 2, 1, 3] - f[1, 0, 1, 3]),
+                        (f[2, 1, 1, 3] - f[0, 1, 1, 3])]) / (2 * h)
+        F = f[1, 1, 1, :3]
+        tol = 1e-7 * sc[0, 1] / h + 1e-3 * np.linalg.norm(F) + 1e-6
+        err = np.abs(F - fd).max()
+        worst = max(worst, err / tol)
+        assert err <= tol, (c, F, fd, tol)
+    print("F = -grad E: worst error / bound", worst, flush=True)

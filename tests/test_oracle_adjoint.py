@@ -108,3 +108,31 @@ def test_adjoint_translation_identity(probe):
             vals.append(_loss(atoms, g2, s2, fire, dfp, gdf, probe)[0])
         dshift = (vals[0] - vals[1]) / (2 * h)
         assert tot[k] == pytest.approx(-dshift, rel=1e-5, abs=1e-7 * np.abs(g["pos"]).max())
+
+
+@pytest.mark.parametrize("periodic", [False, True], ids=["open", "periodic"])
+def test_adjoint_dot_product(periodic):
+    """<J u, w> = <u, J^T w> for the Jacobian J of the frequency-shift stack with
+    respect to every parameter at once: J u by a central difference along a
+    random direction u of (positions, charges, R_i, e_i), J^T w by the adjoint
+    with the random cotangent w."""
+    atoms, grid, scan, fire, dfp, w = _problem(periodic)
+    probe = W.Probe(q_zz=-0.04)
+    L0, ff, res = _loss(atoms, grid, scan, fire, dfp, w, probe)
+    g = orc.scan_backward(grid, ff, probe, scan, res["cols"], res["r"], w, dfp, atoms)
+    rng = np.random.default_rng(123)
+    u = dict(pos=rng.normal(size=atoms.pos.shape), q=rng.normal(size=atoms.n),
+             R=rng.normal(size=atoms.n), eps=rng.normal(size=atoms.n) * atoms.eps)
+    ut_w = sum(float(np.sum(u[k] * g[k])) for k in u)
+    h = 1e-6 if periodic else 1e-5
+
+    def moved(s):
+        a = atoms.copy()
+        a.pos = a.pos + s * h * u["pos"]
+        a.q = a.q + s * h * u["q"]
+        a.R = a.R + s * h * u["R"]
+        a.eps = a.eps + s * h * u["eps"]
+        return a
+    Ju_w = (_loss(moved(+1), grid, scan, fire, dfp, w, probe)[0] -
+            _loss(moved(-1), grid, scan, fire, dfp, w, probe)[0]) / (2 * h)
+    assert Ju_w == pytest.approx(ut_w, rel=1e-5)

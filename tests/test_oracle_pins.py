@@ -681,3 +681,68 @@ def test_fire_trajectory_on_a_one_dimensional_well():
             assert np.any(res["iters"][0] < 0)
         else:
             assert np.all(res["iters"][0] >= 0) and np.abs(res["iters"][0]).sum() > 150
+
+
+def test_scan_mirror_and_translation_invariance():
+    """The relaxed scan inherits the symmetries of Eq. 1 and Eq. 2 (d0 has no x
+    component): mirroring the sample in x about a grid plane, with the tip
+    lattice mirrored, mirrors every relaxed position and keeps Fz; moving atoms,
+    grid origin and tip lattice together by whole voxels moves every relaxed
+    position by the same vector and keeps Fz."""
+    rng = np.random.default_rng(17)
+    A = W.random_atoms(rng, 6, [1.2, 1.2, -0.3], [3.2, 3.0, 0.3], q_max=0.25)
+    n = (45, 42, 90)
+    g = _grid(origin=(0.0, 0.0, -2.0), n=n)
+    fire = W.parity_fire(W.Fire(), f_conv=1e-10)
+    scan = W.Scan(1.37, 1.21, 0.23, 0.19, 7, 6, 7.4, 0.1, 12)
+    base = orc.relaxed_scan(g, orc.build_ff(g, PROBE, A), PROBE, fire, scan, polish_tol=1e-13)
+    # mirror about the plane through voxel 22 (x = 2.2)
+    xc = 2.2
+    B = A.copy()
+    B.pos[:, 0] = 2 * xc - A.pos[:, 0]
+    mscan = W.Scan(2 * xc - (scan.x0 + 6 * scan.dx), scan.y0, scan.dx, scan.dy, 7, 6,
+                   scan.z_top, scan.dz, scan.nz)
+    mir = orc.relaxed_scan(g, orc.build_ff(g, PROBE, B), PROBE, fire, mscan, polish_tol=1e-13)
+    # column (ix, iy) of the base is column (6 - ix, iy) of the mirror
+    for c, (ix, iy) in enumerate(base["cols"]):
+        cm = np.nonzero((mir["cols"][:, 0] == 6 - ix) & (mir["cols"][:, 1] == iy))[0][0]
+        np.testing.assert_allclose(mir["r"][cm, :, 0], 2 * xc - base["r"][c, :, 0], atol=1e-9)
+        np.testing.assert_allclose(mir["r"][cm, :, 1:], base["r"][c, :, 1:], atol=1e-9)
+        np.testing.assert_allclose(mir["fz"][cm], base["fz"][c], atol=1e-9)
+    # translation by whole voxels
+    d = np.array([0.4, -0.7, 0.3])
+    T = A.copy()
+    T.pos = A.pos + d
+    tg = _grid(origin=tuple(np.array(g.origin) + d), n=n)
+    tscan = W.Scan(scan.x0 + d[0], scan.y0 + d[1], scan.dx, scan.dy, 7, 6, scan.z_top + d[2],
+                   scan.dz, scan.nz)
+    tr = orc.relaxed_scan(tg, orc.build_ff(tg, PROBE, T), PROBE, fire, tscan, polish_tol=1e-13)
+    np.testing.assert_allclose(tr["r"], base["r"] + d, atol=1e-9)
+    np.testing.assert_allclose(tr["fz"], base["fz"], atol=1e-9)
+
+
+@pytest.mark.parametrize("periodic", [0, 1], ids=["open", "periodic"])
+def test_pair_newton_third_law(periodic):
+    """Each pair acts on the atom with the opposite of its force on the probe:
+    for every atom alone, minus the derivative of the probe's energy with respect
+    to the atom's position (central differences) equals minus the force on the
+    probe, for the LJ + Coulomb pair and the d_z2 term, with and without the
+    periodic minimum image and shifted-force cutoff."""
+    rng = np.random.default_rng(23)
+    A = W.random_atoms(rng, 5, [0.5, 0.5, -0.3], [5.5, 5.0, 0.3], q_max=0.3)
+    g = _grid(origin=(0, 0, 0), n=(60, 56, 40), periodic=periodic, cutoff=2.6 if periodic else 0.0)
+    probe = W.Probe(q_zz=-0.07)
+    h = 1e-5
+    for i in range(A.n):
+        one = A.subset([i])
+        for r in rng.uniform([0.0, 0.0, 2.2], [6.0, 5.6, 3.5], size=(4, 3)):
+            F = orc.point_ff([r], one, probe, g)[0][0, :3]
+            dEda = np.zeros(3)
+            for k in range(3):
+                ap, am = one.copy(), one.copy()
+                ap.pos[0, k] += h
+                am.pos[0, k] -= h
+                dEda[k] = (orc.point_ff([r], ap, probe, g)[0][0, 3] -
+                           orc.point_ff([r], am, probe, g)[0][0, 3]) / (2 * h)
+            # force on the atom = -dE/da; it must be -F
+            np.testing.assert_allclose(-dEda, -F, rtol=1e-6, atol=1e-10)
