@@ -66,6 +66,7 @@ def lib():
             L.orc_scan_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, vp, vp, vp, d, d, d,
                                             i, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_num_threads.restype = i
+            L.orc_set_num_threads.argtypes = [i]
             L.orc_tip_density.argtypes = [vp, vp, d, d, d, vp]
             L.orc_correlate.argtypes = [vp, vp, vp, vp, i, vp, vp]
             _lib = L
@@ -108,6 +109,10 @@ def _atoms(atoms):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------- force field --

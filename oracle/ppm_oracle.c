@@ -1154,3 +1154,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following parallel regions (the CPU baseline's one-thread run). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
