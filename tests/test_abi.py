@@ -242,3 +242,23 @@ def test_python_wrappers_reject_bad_buffers_before_launch():
     with pytest.raises(ValueError, match="out\\['df'\\]"):
         ppm.relaxed_scan(grid, good_ff, probe, fire, scan, dfp=dfp,
                          out={"df": torch.zeros((12, 2, 3))})
+
+
+def test_microbench_library_exports_its_header():
+    """The benchmark's measurement kernels (libppm_microbench.so) export what
+    include/ppm_microbench.h declares and reject bad arguments on the host."""
+    src = open(os.path.join(ROOT, "include", "ppm_microbench.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(ppm_mb_[a-z_0-9]+)\s*\(", src)))
+    assert names == ["ppm_mb_gather", "ppm_mb_gather_band_bytes", "ppm_mb_pair"]
+    L = ct.CDLL(os.path.join(ROOT, "paper_2401_14564_amd", "libppm_microbench.so"))
+    for n in names:
+        assert hasattr(L, n), n
+    L.ppm_mb_gather_band_bytes.restype = ct.c_size_t
+    assert L.ppm_mb_gather_band_bytes() == 64 * 64 * 32 * 16
+    L.ppm_mb_gather.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_uint32,
+                                ct.c_void_p, ct.c_void_p]
+    L.ppm_mb_pair.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]
+    assert L.ppm_mb_gather(None, 1, 1, 1, 0, FAKE, None) == -1
+    assert L.ppm_mb_gather(FAKE, 1, 0, 1, 0, FAKE, None) == -1
+    assert L.ppm_mb_pair(0, 1, 1, None, None) == -1
