@@ -55,7 +55,78 @@ struct BrickLds {
     float4 par[NT];   // e_iP, 12 e_iP, kq_i, kQ_i
     float2 sf[NT];    // shifted-force constants fc, C (periodic only)
     int wcnt[NT / 64];
+    // periodic: per wave, the staged atoms whose cutoff sphere holds the whole
+    // wave box (interior) and those it only cuts (shell), in staging order
+    uint8_t list[NT / 64][2][NT];
 };
+
+// One atom's terms at the NZB voxels of a thread's z-column.  MASKED: the pair
+// enters only inside the cutoff sphere (rho^2 < rc^2 in FP32), and the
+// shifted-force constant -C with it; unmasked periodic pairs (every voxel of
+// the wave inside the sphere) leave -C to the caller, which adds it once per
+// atom for the whole wave.
+template <int NZB, bool PERIODIC, bool MASKED, bool EONLY, bool QUAD>
+__device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const float2 sf, float vx,
+                                        float vy, const float (&vz)[NZB], float rc2, float c9,
+                                        float c12, float c18, float c24, float (&Fx)[NZB],
+                                        float (&Fy)[NZB], float (&Fz)[NZB], float (&E)[NZB])
+{
+    const float dx = vx - g.x, dy = vy - g.y;
+    const float dxy2 = fmaf(dx, dx, dy * dy);
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        const float dz = vz[k] - g.z;
+        const float r2 = fmaf(dz, dz, dxy2);
+        float ir = __builtin_amdgcn_rsqf(r2);
+        const bool in = !MASKED || r2 < rc2;
+        if (MASKED) ir = in ? ir : 0.0f;
+        const float ir2 = ir * ir;
+        const float s2 = g.w * ir2;
+        const float s6 = s2 * s2 * s2;
+        const float s12 = s6 * s6;
+        const float ec = p.z * ir;
+        float et = ec;
+        if (PERIODIC) {     // shifted force: + fc rho (- C) inside the sphere
+            if (MASKED) {
+                const float t = fmaf(sf.x, r2 * ir, ec - sf.y);
+                et = in ? t : 0.0f;
+            } else {
+                et = fmaf(sf.x, r2 * ir, ec);
+            }
+        }
+        E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + et;
+        float f = 0.0f;
+        if (!EONLY) f = fmaf(p.y, s12 - s6, ec) * ir2;
+        if (PERIODIC && !EONLY) f = fmaf(-sf.x, ir, f);
+        if (QUAD) {
+            // u = (3 dz^2 - rho^2)/rho^5,
+            // -grad u = rho^-5 [(15 dz^2/rho^2 - 3) d - 6 dz e_z]
+            const float z2 = dz * dz;
+            const float q5 = p.w * (ir2 * ir2 * ir);          // kQ_i / rho^5
+            E[k] = fmaf(q5, fmaf(3.0f, z2, -r2), E[k]);
+            if (!EONLY) {
+                f = fmaf(q5, fmaf(15.0f * z2, ir2, -3.0f), f);
+                Fz[k] = fmaf(-6.0f * q5, dz, Fz[k]);
+            }
+            if (PERIODIC) {
+                // angular part of the shift: kQ dz^2 (9 rc^-4/rho - 12 rc^-3/rho^2),
+                // its -grad: -kQ [dz^2 rho^-3 (24 rc^-3/rho - 9 rc^-4) d
+                //                 + dz rho^-1 (18 rc^-4 - 24 rc^-3/rho) e_z]
+                const float qz2 = p.w * z2;
+                E[k] = fmaf(qz2, fmaf(c9, ir, -c12 * ir2), E[k]);
+                if (!EONLY) {
+                    f = fmaf(-qz2 * ir2 * ir, fmaf(c24, ir, -c9), f);
+                    Fz[k] = fmaf(-p.w * dz * ir, fmaf(-c24, ir, c18), Fz[k]);
+                }
+            }
+        }
+        if (!EONLY) {
+            Fx[k] = fmaf(f, dx, Fx[k]);
+            Fy[k] = fmaf(f, dy, Fy[k]);
+            Fz[k] = fmaf(f, dz, Fz[k]);
+        }
+    }
+}
 
 // One brick of BX x BY x NZB voxels with corner voxel (ix0, iy0, iz0).
 // EONLY: only the energy is accumulated and stored (one float per voxel, the
@@ -75,6 +146,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     float4 *s_par = lds.par;
     float2 *s_sf = lds.sf;
     int *s_wcnt = lds.wcnt;
+    static_assert(NT <= 256 && (64 % BX) == 0, "uint8 lists and whole rows per wave");
     // angular part of the shifted d_z2 term: 9 rc^-4, 12 rc^-3, 18 rc^-4, 24 rc^-3
     float c9 = 0.f, c12 = 0.f, c18 = 0.f, c24 = 0.f;
     if (PERIODIC && QUAD) {
@@ -103,6 +175,16 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     float Fx[NZB], Fy[NZB], Fz[NZB], E[NZB];
 #pragma unroll
     for (int k = 0; k < NZB; ++k) Fx[k] = Fy[k] = Fz[k] = E[k] = 0.0f;
+    // this wave's box (periodic culling): rows ty in [RW wv, RW wv + RW - 1]
+    constexpr int RW = 64 / BX;
+    const float wex = (float)(hcx * a.hx), wez = (float)(hcz * a.hz);
+    const float wey = (float)(0.5 * (RW - 1) * a.hy);
+    const float wcy = (float)((RW * (tid >> 6) + 0.5 * (RW - 1) - hcy) * a.hy);
+    float rc2_in = 0.f, rc2_out = 0.f;
+    if (PERIODIC) {
+        rc2_in = (float)((a.rc - 1e-3) * (a.rc - 1e-3));
+        rc2_out = (float)((a.rc + 1e-3) * (a.rc + 1e-3));
+    }
 
     for (int base = 0; base < a.n_atoms; base += NT) {
         const int i = base + tid;
@@ -166,61 +248,79 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         }
         __syncthreads();
 
-        for (int j = 0; j < cnt; ++j) {
-            const float4 g = s_geo[j];
-            const float4 p = s_par[j];
-            const float2 sf = PERIODIC ? s_sf[j] : make_float2(0.f, 0.f);
-            const float dx = vx - g.x, dy = vy - g.y;
-            const float dxy2 = fmaf(dx, dx, dy * dy);
+        if (PERIODIC) {
+            // Per-wave lists: the wave's 16 x 4 x NZB voxels span a box (brick-
+            // local, FP32) of centre (0, wcy, 0) and half extents (wex, wey, wez).
+            // An atom enters the shell list if the box comes within rc (+1e-3 A,
+            // so that no pair the FP32 mask would admit is dropped) and the
+            // interior list if the whole box is within rc - 1e-3 A (every pair
+            // inside the sphere, so no mask is needed).
+            const int lane = tid & 63, wv = tid >> 6;
+            int n_in = 0, n_sh = 0;
 #pragma unroll
-            for (int k = 0; k < NZB; ++k) {
-                const float dz = vz[k] - g.z;
-                const float r2 = fmaf(dz, dz, dxy2);
-                float ir = __builtin_amdgcn_rsqf(r2);
-                const bool in = !PERIODIC || r2 < a.rc2;
-                if (PERIODIC) ir = in ? ir : 0.0f;
-                const float ir2 = ir * ir;
-                const float s2 = g.w * ir2;
-                const float s6 = s2 * s2 * s2;
-                const float s12 = s6 * s6;
-                const float ec = p.z * ir;
-                float et = ec;
-                if (PERIODIC) {     // shifted force: + fc rho - C inside the sphere
-                    const float t = fmaf(sf.x, r2 * ir, ec - sf.y);
-                    et = in ? t : 0.0f;
+            for (int r = 0; r < NT / 64; ++r) {
+                const int j = r * 64 + lane;
+                bool is_in = false, is_sh = false;
+                if (j < cnt) {
+                    const float4 g = s_geo[j];
+                    const float ax = fabsf(g.x), ay = fabsf(g.y - wcy), az = fabsf(g.z);
+                    const float nx_ = fmaxf(ax - wex, 0.f), ny_ = fmaxf(ay - wey, 0.f),
+                                nz_ = fmaxf(az - wez, 0.f);
+                    const float near2 = fmaf(nx_, nx_, fmaf(ny_, ny_, nz_ * nz_));
+                    const float fx_ = ax + wex, fy_ = ay + wey, fz_ = az + wez;
+                    const float far2 = fmaf(fx_, fx_, fmaf(fy_, fy_, fz_ * fz_));
+                    is_in = far2 < rc2_in;
+                    is_sh = !is_in && near2 < rc2_out;
                 }
-                E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + et;
-                float f = 0.0f;
-                if (!EONLY) f = fmaf(p.y, s12 - s6, ec) * ir2;
-                if (PERIODIC && !EONLY) f = fmaf(-sf.x, ir, f);
-                if (QUAD) {
-                    // u = (3 dz^2 - rho^2)/rho^5,
-                    // -grad u = rho^-5 [(15 dz^2/rho^2 - 3) d - 6 dz e_z]
-                    const float z2 = dz * dz;
-                    const float q5 = p.w * (ir2 * ir2 * ir);          // kQ_i / rho^5
-                    E[k] = fmaf(q5, fmaf(3.0f, z2, -r2), E[k]);
-                    if (!EONLY) {
-                        f = fmaf(q5, fmaf(15.0f * z2, ir2, -3.0f), f);
-                        Fz[k] = fmaf(-6.0f * q5, dz, Fz[k]);
-                    }
-                    if (PERIODIC) {
-                        // angular part of the shift: kQ dz^2 (9 rc^-4/rho - 12 rc^-3/rho^2),
-                        // its -grad: -kQ [dz^2 rho^-3 (24 rc^-3/rho - 9 rc^-4) d
-                        //                 + dz rho^-1 (18 rc^-4 - 24 rc^-3/rho) e_z]
-                        const float qz2 = p.w * z2;
-                        E[k] = fmaf(qz2, fmaf(c9, ir, -c12 * ir2), E[k]);
-                        if (!EONLY) {
-                            f = fmaf(-qz2 * ir2 * ir, fmaf(c24, ir, -c9), f);
-                            Fz[k] = fmaf(-p.w * dz * ir, fmaf(-c24, ir, c18), Fz[k]);
-                        }
-                    }
-                }
-                if (!EONLY) {
-                    Fx[k] = fmaf(f, dx, Fx[k]);
-                    Fy[k] = fmaf(f, dy, Fy[k]);
-                    Fz[k] = fmaf(f, dz, Fz[k]);
+                const unsigned long long mi = __ballot(is_in), ms = __ballot(is_sh);
+                const unsigned long long below = (1ull << lane) - 1ull;
+                if (is_in) lds.list[wv][0][n_in + __popcll(mi & below)] = (uint8_t)j;
+                if (is_sh) lds.list[wv][1][n_sh + __popcll(ms & below)] = (uint8_t)j;
+                n_in += __popcll(mi);
+                n_sh += __popcll(ms);
+            }
+            __syncthreads();
+            // the next atom's list entry and data are read before the current
+            // atom's pairs, so the LDS latency overlaps them
+            float sumC = 0.0f;
+            if (n_in > 0) {
+                int t = lds.list[wv][0][0];
+                float4 g = s_geo[t], pa = s_par[t];
+                float2 sf = s_sf[t];
+                for (int j = 0; j < n_in; ++j) {
+                    const int tn = lds.list[wv][0][min(j + 1, n_in - 1)];
+                    const float4 gn = s_geo[tn], pn = s_par[tn];
+                    const float2 sfn = s_sf[tn];
+                    ff_pair<NZB, true, false, EONLY, QUAD>(g, pa, sf, vx, vy, vz, a.rc2, c9, c12,
+                                                           c18, c24, Fx, Fy, Fz, E);
+                    sumC += sf.y;
+                    g = gn;
+                    pa = pn;
+                    sf = sfn;
                 }
             }
+#pragma unroll
+            for (int k = 0; k < NZB; ++k) E[k] -= sumC;
+            if (n_sh > 0) {
+                int t = lds.list[wv][1][0];
+                float4 g = s_geo[t], pa = s_par[t];
+                float2 sf = s_sf[t];
+                for (int j = 0; j < n_sh; ++j) {
+                    const int tn = lds.list[wv][1][min(j + 1, n_sh - 1)];
+                    const float4 gn = s_geo[tn], pn = s_par[tn];
+                    const float2 sfn = s_sf[tn];
+                    ff_pair<NZB, true, true, EONLY, QUAD>(g, pa, sf, vx, vy, vz, a.rc2, c9, c12,
+                                                          c18, c24, Fx, Fy, Fz, E);
+                    g = gn;
+                    pa = pn;
+                    sf = sfn;
+                }
+            }
+        } else {
+            for (int j = 0; j < cnt; ++j)
+                ff_pair<NZB, false, false, EONLY, QUAD>(s_geo[j], s_par[j], make_float2(0.f, 0.f),
+                                                        vx, vy, vz, a.rc2, c9, c12, c18, c24, Fx,
+                                                        Fy, Fz, E);
         }
         __syncthreads();
     }
