@@ -178,7 +178,7 @@ def _traffic(kernel_key, src, launches_bytes_key):
     return e.get(launches_bytes_key)
 
 
-def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup):
+def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup, tuning=None):
     """Time `steps` forward steps (force-field build -> relaxed scan with fused
     frequency shift) after `warmup` untimed ones.  Returns (ms per step, mean
     build ms, mean scan ms), the kernel times from HIP events on the streams
@@ -199,7 +199,7 @@ def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup):
             s_ff.wait_event(scan_done[b])          # buffer b is free again
             if ev is not None:
                 ev[0].record(s_ff)
-            ppm.build_ff(w.grid, w.probe, atoms, out=ffs[b])
+            ppm.build_ff(w.grid, w.probe, atoms, out=ffs[b], tuning=tuning)
             if ev is not None:
                 ev[1].record(s_ff)
             ff_done[b].record(s_ff)
@@ -208,7 +208,7 @@ def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup):
             if ev is not None:
                 ev[2].record(s_scan)
             ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=False,
-                             pp=False, out=outs[b])
+                             pp=False, out=outs[b], tuning=tuning)
             if ev is not None:
                 ev[3].record(s_scan)
             scan_done[b].record(s_scan)
@@ -282,8 +282,13 @@ def main():
     w = W.config2()
     atoms = ppm.atoms_to_device(w.atoms)
     ffs, outs, m = _buffers(ppm, torch, w, 2 if a.pipeline else 1)
+    # launch shapes from the autotuner, on these inputs, before the timed steps
+    tuning, ff_tune_ms = ppm.tune_build_ff(w.grid, w.probe, atoms, out=ffs[0])
+    tuning, scan_tune_ms, _ = ppm.tune_relaxed_scan(w.grid, ffs[0], w.probe, w.fire, w.scan,
+                                                    dfp=w.df, fz=False, pp=False, out=outs[0],
+                                                    tuning=tuning)
     ms_per_step, ff_ms, scan_ms = _run_steps(ppm, torch, w, atoms, ffs, outs, a.pipeline,
-                                             a.steps, a.warmup)
+                                             a.steps, a.warmup, tuning)
     n_eq = w.scan.n_eq
     st = _scan_stats(ppm, torch, w, ffs[0])
     pairs = _pairs_within_cutoff(w)
@@ -326,7 +331,11 @@ def main():
                    "pipelining": ("step i+1's force-field build overlaps step i's scan on a "
                                   "second stream (double-buffered grid)") if a.pipeline else
                                  "none: build then scan, in order, on one stream",
-                   "relaxations_per_step": n_eq, "voxels": w.grid.nvox, "atoms": w.atoms.n},
+                   "relaxations_per_step": n_eq, "voxels": w.grid.nvox, "atoms": w.atoms.n,
+                   "launch_shapes": {"ff_voxels_per_thread": tuning.ff_nzb,
+                                     "scan_tile": f"{tuning.scan_tile}x{tuning.scan_tile}",
+                                     "autotuner_ms": {"ff_build": ff_tune_ms,
+                                                      "relaxed_scan": scan_tune_ms}}},
         "roofline": roof,
         "kernels": {
             "ff_build": {"ms": round(ff_ms, 4), "pairs_within_cutoff": pairs,
@@ -361,7 +370,8 @@ def main():
     if not a.no_extra:
         other = not a.pipeline
         ffs, outs, _ = _buffers(ppm, torch, w, 2 if other else 1)
-        o_ms, o_ff, o_scan = _run_steps(ppm, torch, w, atoms, ffs, outs, other, a.steps, a.warmup)
+        o_ms, o_ff, o_scan = _run_steps(ppm, torch, w, atoms, ffs, outs, other, a.steps, a.warmup,
+                                        tuning)
         result["pipelined" if other else "sequential"] = {
             "pipelining": ("step i+1's force-field build overlaps step i's scan on a second "
                            "stream (double-buffered grid)") if other else
@@ -521,7 +531,7 @@ def _bench_batch(ppm, W, torch, n_mol=256):
         for k in W.C3_K_LAT_N_PER_M:
             jobs.append((i, dataclasses.replace(w.probe, k_lat=(k * W.N_PER_M, k * W.N_PER_M)),
                          w.scan))
-    bp = ppm.BatchPipeline(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df)
+    bp = ppm.BatchPipeline.tuned(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df)
     # eager stage times
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     bp.run()
@@ -551,16 +561,26 @@ def _bench_batch(ppm, W, torch, n_mol=256):
     outs = [torch.empty((sc.nz - 2 * m, sc.ny, sc.nx), dtype=torch.float32, device=dev)
             for (_, _, sc) in jobs]
 
+    # the per-molecule loop builds with the batch's tuned depth (same bits) and
+    # scans 128 x 128 lattices with the shape the autotuner picks for them
+    tune = ppm.Tuning(ff_nzb=bp.ff_nzb)
+    ff0 = ffbuf[:ws[0].grid.nvox * 4].view(ws[0].grid.n[2], ws[0].grid.n[1], ws[0].grid.n[0], 4)
+    ppm.build_ff(ws[0].grid, ws[0].probe, atoms_dev[0], out=ff0, tuning=tune)
+    tune, plain_scan_tune_ms, _ = ppm.tune_relaxed_scan(ws[0].grid, ff0, jobs[0][1], ws[0].fire,
+                                                        jobs[0][2], dfp=ws[0].df, fz=False,
+                                                        pp=False, out={"df": outs[0]},
+                                                        tuning=tune)
+
     def plain():
         j = 0
         for i, w in enumerate(ws):
             nx, ny, nz = w.grid.n
             ff = ffbuf[:w.grid.nvox * 4].view(nz, ny, nx, 4)
-            ppm.build_ff(w.grid, w.probe, atoms_dev[i], out=ff)
+            ppm.build_ff(w.grid, w.probe, atoms_dev[i], out=ff, tuning=tune)
             for _ in W.C3_K_LAT_N_PER_M:
                 _, pr, sc = jobs[j]
                 ppm.relaxed_scan(w.grid, ff, pr, w.fire, sc, dfp=w.df, fz=False, pp=False,
-                                 out={"df": outs[j]})
+                                 out={"df": outs[j]}, tuning=tune)
                 j += 1
 
     plain()
@@ -609,6 +629,11 @@ def _bench_batch(ppm, W, torch, n_mol=256):
                                 "speedup_vs_plain_graph: the same loop replayed as one graph",
             "batched_stage_ms": {"ff_build": round(ff_ms, 3), "scan": round(scan_ms, 3)},
             "batched_ff_tflops": round(pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12, 2),
+            "launch_shapes": {"ff_voxels_per_thread": bp.ff_nzb,
+                              "ff_autotuner_ms": bp.tuning_ms,
+                              "batched_scan_tile": "8x8",
+                              "plain_scan_tile": f"{tune.scan_tile}x{tune.scan_tile}",
+                              "plain_scan_autotuner_ms": plain_scan_tune_ms},
             "outputs_identical": bool(same and same_graph)}
 
 

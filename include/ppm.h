@@ -206,6 +206,71 @@ ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_pro
                             const ppm_fire *fire, const ppm_scan *scan, float *fz,
                             float *pp, const ppm_df_params *dfp, float *df, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Launch shapes and their autotuner.  The force field is the step that
+ * limits the two-step method (Sec. 5.1.1 step 1, Sec. 5.3), and the best
+ * shapes depend on the probe (the d_z2 term adds ~11 instructions per pair,
+ * which changes the register budget) and on the tip lattice (how many
+ * columns fill the GPU, how many heights fit on chip).  The tuner times the
+ * candidate shapes on the caller's own inputs and returns the fastest; the
+ * calls below take the result.
+ *   ff_nzb    voxels per thread along z in the force-field build (the brick
+ *             is 16 x 16 x ff_nzb voxels): 0 (= 8), 6 or 8.  Brick-local
+ *             coordinates depend on the brick, so builds with different depths
+ *             differ in FP32 rounding (each within the parity bound); builds
+ *             with the same depth, single or batched, are bit-identical.
+ *   scan_tile relaxed-scan work-group: 0 (automatic: 16 x 16-column blocks of
+ *             four waves where the heights fit the LDS staging, else 8 x 8),
+ *             16 (16 x 16 where the requested outputs allow it) or 8 (8 x 8
+ *             one-wave blocks).  Every scan shape gives the same bits.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t ff_nzb;
+    int32_t scan_tile;
+} ppm_tuning;
+
+/* ppm_build_ff with the brick depth of `tuning` (NULL = defaults).  Errors as
+ * ppm_build_ff, and PPM_EINVAL for a depth other than 0, 6, 8. */
+ppm_status ppm_build_ff_tuned(const ppm_grid *grid, const ppm_probe *probe,
+                              const ppm_tuning *tuning, int32_t n_atoms, const double *pos,
+                              const double *q, const double *R, const double *eps, float *ff,
+                              void *stream);
+
+/* ppm_relaxed_scan with the work-group shape of `tuning` (NULL = automatic).
+ * Errors as ppm_relaxed_scan, and PPM_EINVAL for a tile other than 0, 8, 16. */
+ppm_status ppm_relaxed_scan_tuned(const ppm_grid *grid, const float *ff,
+                                  const ppm_probe *probe, const ppm_fire *fire,
+                                  const ppm_scan *scan, const ppm_tuning *tuning, float *fz,
+                                  float *pp, const ppm_df_params *dfp, float *df,
+                                  void *stream);
+
+/*
+ * ppm_tune_build_ff -- autotuner of the force-field brick depth: builds the
+ * grid (arguments as ppm_build_ff; ff is overwritten) with each candidate
+ * depth (8, then 6), once untimed and three times timed with HIP events on
+ * `stream`, and sets tuning->ff_nzb to the fastest (median); the other field
+ * is left as it was.  ms (may be NULL) receives the two medians in that
+ * order.  Blocks until the stream is idle; creates and destroys two events,
+ * allocates no memory.  Errors as ppm_build_ff, PPM_EINVAL if tuning is NULL,
+ * PPM_EHIP if an event call fails.
+ */
+ppm_status ppm_tune_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                             const double *pos, const double *q, const double *R,
+                             const double *eps, float *ff, void *stream, ppm_tuning *tuning,
+                             float *ms);
+
+/*
+ * ppm_tune_relaxed_scan -- autotuner of the scan's work-group shape: runs the
+ * scan (arguments as ppm_relaxed_scan; the outputs are overwritten, with the
+ * same bits whatever the shape) with scan_tile 16 and 8, once untimed and
+ * three times timed, and sets tuning->scan_tile to the faster (median); ms
+ * (may be NULL) receives the two medians.  Blocking, as ppm_tune_build_ff.
+ */
+ppm_status ppm_tune_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                                 const ppm_fire *fire, const ppm_scan *scan, float *fz,
+                                 float *pp, const ppm_df_params *dfp, float *df, void *stream,
+                                 ppm_tuning *tuning, float *ms);
+
 /*
  * ppm_build_energy -- energy-only grid for the tricubic scan (Sec. 5.1.1 step 2:
  * interpolating the potential tricubically avoids storing the forces).  Same
@@ -354,11 +419,15 @@ ppm_status ppm_hartree_ff(const ppm_grid *grid, const float *V, const float *rho
  * ------------------------------------------------------------------------ */
 
 /* One molecule.  atom_begin/n_atoms index the concatenated atom arrays
- * (positions [.][3], q, R, eps) shared by the whole batch. */
+ * (positions [.][3], q, R, eps) shared by the whole batch; ff_nzb is the
+ * force-field brick depth (0, 6 or 8, as ppm_tuning.ff_nzb): a molecule built
+ * with the depth a single ppm_build_ff_tuned call uses gets the same bits. */
 typedef struct {
     ppm_grid grid;
     int32_t atom_begin;
     int32_t n_atoms;
+    int32_t ff_nzb;
+    int32_t reserved;
     int64_t ff_offset;     /* set by ppm_batch_plan: first voxel in the FF arena */
     int64_t brick_begin;   /* set by ppm_batch_plan: first FF work item */
 } ppm_batch_mol;

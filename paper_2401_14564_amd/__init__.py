@@ -21,13 +21,26 @@ Atoms may be given as a workloads.Atoms or as a tuple of device tensors
 """
 from __future__ import annotations
 
+import dataclasses
+
+import numpy as np
 import torch
 
 from . import _lib
 
 __all__ = ["build_ff", "relaxed_scan", "df", "df_half_width", "relaxed_scan_backward",
            "AFMStack", "atoms_to_device", "BatchPipeline", "lateral_stiffness",
-           "build_energy", "relaxed_scan_tricubic"]
+           "build_energy", "relaxed_scan_tricubic", "Tuning", "tune_build_ff",
+           "tune_relaxed_scan"]
+
+
+@dataclasses.dataclass
+class Tuning:
+    """Launch shapes (include/ppm.h, ppm_tuning): ff_nzb = force-field voxels per
+    thread along z (0 = 8, or 6), scan_tile = relaxed-scan work-group (0 =
+    automatic, 16 or 8).  Chosen by tune_build_ff / tune_relaxed_scan."""
+    ff_nzb: int = 0
+    scan_tile: int = 0
 
 
 def _stream():
@@ -103,27 +116,46 @@ def df_half_width(A: float, dz: float) -> int:
     return int(_lib.lib().ppm_df_half_width(float(A), float(dz)))
 
 
-def build_ff(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Force-field grid (Fx, Fy, Fz, E) [nz, ny, nx, 4], float32, on the device."""
+def build_ff(grid, probe, atoms, out: torch.Tensor | None = None,
+             tuning: Tuning | None = None) -> torch.Tensor:
+    """Force-field grid (Fx, Fy, Fz, E) [nz, ny, nx, 4], float32, on the device;
+    with the brick depth of `tuning` if given."""
     L = _lib.lib()
     pos, q, R, eps = atoms_to_device(atoms)
     nx, ny, nz = (int(v) for v in grid.n)
     if out is None:
         out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=pos.device)
     _need(out, (nz, ny, nx, 4), "out")
-    st = L.ppm_build_ff(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
-                        _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps), _lib.ptr(out),
-                        _stream())
-    _lib.check(st, "ppm_build_ff")
+    t = _lib.tuning_struct(tuning)
+    st = L.ppm_build_ff_tuned(_lib.grid_struct(grid), _lib.probe_struct(probe), t,
+                              int(q.numel()), _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R),
+                              _lib.ptr(eps), _lib.ptr(out), _stream())
+    _lib.check(st, "ppm_build_ff_tuned")
     return out
 
 
-def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
-                 out: dict | None = None) -> dict:
-    """Relaxed scan.  Returns dict with 'fz' [nz,ny,nx] (tip force, eV/A), 'pp'
-    [nz,ny,nx,4] (probe displacement from rest and FIRE steps, negative if not
-    converged) and 'df' [nz-2m,ny,nx] (Hz, when dfp is given)."""
+def tune_build_ff(grid, probe, atoms, out: torch.Tensor | None = None,
+                  tuning: Tuning | None = None):
+    """Autotune the force-field brick depth on these inputs (ppm_tune_build_ff:
+    each candidate timed on the stream; blocks).  Returns (Tuning, {depth: ms});
+    `out` (or a scratch grid) holds a built force field afterwards."""
     L = _lib.lib()
+    pos, q, R, eps = atoms_to_device(atoms)
+    nx, ny, nz = (int(v) for v in grid.n)
+    if out is None:
+        out = torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=pos.device)
+    _need(out, (nz, ny, nx, 4), "out")
+    import ctypes as ct
+    t = _lib.tuning_struct(tuning or Tuning())
+    ms = (ct.c_float * 2)()
+    st = L.ppm_tune_build_ff(_lib.grid_struct(grid), _lib.probe_struct(probe), int(q.numel()),
+                             _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps),
+                             _lib.ptr(out), _stream(), t, ms)
+    _lib.check(st, "ppm_tune_build_ff")
+    return Tuning(t.ff_nzb, t.scan_tile), {8: float(ms[0]), 6: float(ms[1])}
+
+
+def _scan_outputs(grid, ff, scan, dfp, fz, pp, out):
     _need(ff, _grid_shape(grid, 4), "ff")
     dev = ff.device
     nz, ny, nx = int(scan.nz), int(scan.ny), int(scan.nx)
@@ -136,13 +168,43 @@ def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: boo
     if dfp is not None and "df" not in out:
         m = df_half_width(dfp.A, scan.dz)
         out["df"] = torch.empty((max(nz - 2 * m, 0), ny, nx), dtype=torch.float32, device=dev)
-    st = L.ppm_relaxed_scan(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
-                            _lib.fire_struct(fire), _lib.scan_struct(scan),
-                            _lib.ptr(out.get("fz")), _lib.ptr(out.get("pp")),
-                            None if dfp is None else _lib.df_struct(dfp),
-                            _lib.ptr(out.get("df")), _stream())
-    _lib.check(st, "ppm_relaxed_scan")
     return out
+
+
+def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
+                 out: dict | None = None, tuning: Tuning | None = None) -> dict:
+    """Relaxed scan.  Returns dict with 'fz' [nz,ny,nx] (tip force, eV/A), 'pp'
+    [nz,ny,nx,4] (probe displacement from rest and FIRE steps, negative if not
+    converged) and 'df' [nz-2m,ny,nx] (Hz, when dfp is given).  `tuning` picks
+    the work-group shape (the outputs are the same bits for every shape)."""
+    L = _lib.lib()
+    out = _scan_outputs(grid, ff, scan, dfp, fz, pp, out)
+    st = L.ppm_relaxed_scan_tuned(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
+                                  _lib.fire_struct(fire), _lib.scan_struct(scan),
+                                  _lib.tuning_struct(tuning), _lib.ptr(out.get("fz")),
+                                  _lib.ptr(out.get("pp")),
+                                  None if dfp is None else _lib.df_struct(dfp),
+                                  _lib.ptr(out.get("df")), _stream())
+    _lib.check(st, "ppm_relaxed_scan_tuned")
+    return out
+
+
+def tune_relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
+                      out: dict | None = None, tuning: Tuning | None = None):
+    """Autotune the scan's work-group shape for these outputs (ppm_tune_relaxed_scan;
+    blocks).  Returns (Tuning, {tile: ms}, outputs)."""
+    import ctypes as ct
+    L = _lib.lib()
+    out = _scan_outputs(grid, ff, scan, dfp, fz, pp, out)
+    t = _lib.tuning_struct(tuning or Tuning())
+    ms = (ct.c_float * 2)()
+    st = L.ppm_tune_relaxed_scan(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
+                                 _lib.fire_struct(fire), _lib.scan_struct(scan),
+                                 _lib.ptr(out.get("fz")), _lib.ptr(out.get("pp")),
+                                 None if dfp is None else _lib.df_struct(dfp),
+                                 _lib.ptr(out.get("df")), _stream(), t, ms)
+    _lib.check(st, "ppm_tune_relaxed_scan")
+    return Tuning(t.ff_nzb, t.scan_tile), {16: float(ms[0]), 8: float(ms[1])}, out
 
 
 def build_energy(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -324,15 +386,34 @@ class BatchPipeline:
 
     molecules: list of (atoms, grid); jobs: list of (molecule index, probe, scan).
     The force fields are built with `probe`'s LJ parameters and charge; every
-    job's probe must share them (its springs may differ).  Tables, atoms and
-    arenas are allocated once here; run() only launches, so it can be captured
-    with capture() and replayed with replay()."""
+    job's probe must share them (its springs may differ).  ff_nzb: the brick
+    depth of every molecule's build (0 = 8, or 6; BatchPipeline.tuned picks it
+    with the autotuner); a molecule's grid equals the single build_ff with the
+    same depth bit for bit.  Tables, atoms and arenas are allocated once here;
+    run() only launches, so it can be captured with capture() and replayed
+    with replay()."""
 
-    def __init__(self, molecules, jobs, probe, fire, dfp, keep_fz: bool = False, device=None):
+    @classmethod
+    def tuned(cls, molecules, jobs, probe, fire, dfp, keep_fz: bool = False, device=None):
+        """A pipeline whose force-field brick depth is chosen by the autotuner
+        (ppm_tune_build_ff) on the batch's largest molecule with this probe;
+        the timings are kept in .tuning_ms."""
+        big = max(range(len(molecules)), key=lambda i: int(np.prod(molecules[i][1].n)) *
+                  max(int(molecules[i][0].n), 1))
+        atoms, grid = molecules[big]
+        t, ms = tune_build_ff(grid, probe, atoms)
+        bp = cls(molecules, jobs, probe, fire, dfp, keep_fz=keep_fz, device=device,
+                 ff_nzb=t.ff_nzb)
+        bp.tuning_ms = ms
+        return bp
+
+    def __init__(self, molecules, jobs, probe, fire, dfp, keep_fz: bool = False, device=None,
+                 ff_nzb: int = 0):
         import ctypes as ct
         L = _lib.lib()
         dev = device or _device()
         self.n_mol, self.n_jobs = len(molecules), len(jobs)
+        self.ff_nzb = int(ff_nzb)
         self.mols = (_lib.BatchMol * self.n_mol)()
         begin = 0
         pos, q, R, eps = [], [], [], []
@@ -340,6 +421,7 @@ class BatchPipeline:
             self.mols[i].grid = _lib.grid_struct(grid)
             self.mols[i].atom_begin = begin
             self.mols[i].n_atoms = int(atoms.n)
+            self.mols[i].ff_nzb = self.ff_nzb
             begin += int(atoms.n)
             pos.append(torch.as_tensor(atoms.pos, dtype=torch.float64).reshape(-1, 3))
             q.append(torch.as_tensor(atoms.q, dtype=torch.float64))

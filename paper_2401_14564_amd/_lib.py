@@ -25,7 +25,8 @@ EXPORTED = (
     "ppm_relaxed_scan_backward", "ppm_batch_plan", "ppm_batch_build_ff",
     "ppm_batch_relaxed_scan", "ppm_lateral_stiffness", "ppm_build_energy",
     "ppm_relaxed_scan_tricubic", "ppm_tip_density", "ppm_hartree_workspace_bytes",
-    "ppm_hartree_ff",
+    "ppm_hartree_ff", "ppm_build_ff_tuned", "ppm_relaxed_scan_tuned", "ppm_tune_build_ff",
+    "ppm_tune_relaxed_scan",
 )
 
 
@@ -67,8 +68,13 @@ class DfParams(ct.Structure):
     _fields_ = [("A", ct.c_double), ("f0", ct.c_double), ("k_cant", ct.c_double)]
 
 
+class Tuning(ct.Structure):
+    _fields_ = [("ff_nzb", ct.c_int32), ("scan_tile", ct.c_int32)]
+
+
 class BatchMol(ct.Structure):
     _fields_ = [("grid", Grid), ("atom_begin", ct.c_int32), ("n_atoms", ct.c_int32),
+                ("ff_nzb", ct.c_int32), ("reserved", ct.c_int32),
                 ("ff_offset", ct.c_int64), ("brick_begin", ct.c_int64)]
 
 
@@ -133,6 +139,18 @@ def lib():
             L.ppm_hartree_workspace_bytes.restype = ct.c_size_t
             L.ppm_hartree_ff.argtypes = [P(Grid), vp, vp, i32, vp, vp, ct.c_size_t, vp]
             L.ppm_hartree_ff.restype = st
+            L.ppm_build_ff_tuned.argtypes = [P(Grid), P(Probe), P(Tuning), i32, vp, vp, vp, vp,
+                                             vp, vp]
+            L.ppm_build_ff_tuned.restype = st
+            L.ppm_relaxed_scan_tuned.argtypes = [P(Grid), vp, P(Probe), P(Fire), P(Scan),
+                                                 P(Tuning), vp, vp, P(DfParams), vp, vp]
+            L.ppm_relaxed_scan_tuned.restype = st
+            L.ppm_tune_build_ff.argtypes = [P(Grid), P(Probe), i32, vp, vp, vp, vp, vp, vp,
+                                            P(Tuning), vp]
+            L.ppm_tune_build_ff.restype = st
+            L.ppm_tune_relaxed_scan.argtypes = [P(Grid), vp, P(Probe), P(Fire), P(Scan), vp, vp,
+                                                P(DfParams), vp, vp, P(Tuning), vp]
+            L.ppm_tune_relaxed_scan.restype = st
             _LIB = L
     return _LIB
 
@@ -168,6 +186,13 @@ def scan_struct(s) -> Scan:
 
 def df_struct(d) -> DfParams:
     return DfParams(d.A, d.f0, d.k_cant)
+
+
+def tuning_struct(t) -> Tuning | None:
+    """ctypes Tuning from anything with ff_nzb / scan_tile attributes (None -> NULL)."""
+    if t is None:
+        return None
+    return Tuning(int(getattr(t, "ff_nzb", 0)), int(getattr(t, "scan_tile", 0)))
 
 
 def ptr(t):

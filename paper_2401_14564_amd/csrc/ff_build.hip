@@ -355,39 +355,21 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(1, 4)))
 
 // Batched build: one block per brick of any molecule of the batch.  The
 // molecule of a brick is found by a binary search over the table's
-// brick_begin (wave-uniform, scalar loads); its grid, atom range and arena
-// offset come from the table.  The probe (mixing parameters) is shared.
+// brick_begin (wave-uniform, scalar loads); its grid, atom range, arena
+// offset and brick depth (ff_nzb, 6 or 8 voxels per thread) come from the
+// table.  The probe (mixing parameters) is shared.
 template <int BX, int BY, int NZB, bool QUAD>
-__global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
-    const FFArgs probe_args, const ppm_batch_mol *__restrict__ mols, int n_mol,
-    const double *__restrict__ pos, const double *__restrict__ q, const double *__restrict__ R,
-    const double *__restrict__ eps, float4 *__restrict__ arena)
+__device__ __forceinline__ void ff_batch_brick(FFArgs a, const ppm_batch_mol &M, long long local,
+                                               const double *__restrict__ pos,
+                                               const double *__restrict__ q,
+                                               const double *__restrict__ R,
+                                               const double *__restrict__ eps,
+                                               float4 *__restrict__ arena, BrickLds<BX * BY> &lds)
 {
-    __shared__ BrickLds<BX * BY> lds;
-    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-    int lo = 0, hi = n_mol - 1;               // last molecule with brick_begin <= b
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (mols[mid].brick_begin <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const ppm_batch_mol &M = mols[lo];
     const int nbx = (M.grid.n[0] + BX - 1) / BX, nby = (M.grid.n[1] + BY - 1) / BY;
-    const long long local = b - M.brick_begin;
     const int bz = (int)(local / ((long long)nbx * nby));
     if (bz * NZB >= M.grid.n[2]) return;      // past the last brick of the batch
     const int rest = (int)(local - (long long)bz * nbx * nby);
-    FFArgs a = probe_args;
-    a.ox = M.grid.origin[0];
-    a.oy = M.grid.origin[1];
-    a.oz = M.grid.origin[2];
-    a.hx = M.grid.step[0];
-    a.hy = M.grid.step[1];
-    a.hz = M.grid.step[2];
-    a.nx = M.grid.n[0];
-    a.ny = M.grid.n[1];
-    a.nz = M.grid.n[2];
-    a.n_atoms = M.n_atoms;
     const int off = M.atom_begin;
     float4 *ff = arena + M.ff_offset;
     if (M.grid.periodic_xy) {
@@ -407,56 +389,91 @@ __global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
     }
 }
 
-// 16 x 16 x 8 bricks for every sample.  Grid extents are usually multiples of
-// 16 voxels (240 at the paper's scale) or close to one, so few threads of the
-// last brick of a row idle (64-wide bricks left a quarter of them idle on a
-// 240-voxel row: 0.38 against 0.35 ms); the small half-diagonal keeps a
-// periodic brick's cull sphere (cutoff + half-diagonal) close to the cutoff
-// sphere and the brick-local coordinates small.
+template <int BX, int BY, bool QUAD>
+__global__ __launch_bounds__(BX * BY) void ff_build_batch_kernel(
+    const FFArgs probe_args, const ppm_batch_mol *__restrict__ mols, int n_mol,
+    const double *__restrict__ pos, const double *__restrict__ q, const double *__restrict__ R,
+    const double *__restrict__ eps, float4 *__restrict__ arena)
+{
+    __shared__ BrickLds<BX * BY> lds;
+    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    int lo = 0, hi = n_mol - 1;               // last molecule with brick_begin <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mols[mid].brick_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ppm_batch_mol &M = mols[lo];
+    FFArgs a = probe_args;
+    a.ox = M.grid.origin[0];
+    a.oy = M.grid.origin[1];
+    a.oz = M.grid.origin[2];
+    a.hx = M.grid.step[0];
+    a.hy = M.grid.step[1];
+    a.hz = M.grid.step[2];
+    a.nx = M.grid.n[0];
+    a.ny = M.grid.n[1];
+    a.nz = M.grid.n[2];
+    a.n_atoms = M.n_atoms;
+    const long long local = b - M.brick_begin;
+    if (M.ff_nzb == 6)
+        ff_batch_brick<BX, BY, 6, QUAD>(a, M, local, pos, q, R, eps, arena, lds);
+    else
+        ff_batch_brick<BX, BY, 8, QUAD>(a, M, local, pos, q, R, eps, arena, lds);
+}
+
+// 16 x 16-column bricks, 8 voxels per thread along z unless the autotuner
+// chose 6.  Grid extents are usually multiples of 16 voxels (240 at the
+// paper's scale) or close to one, so few threads of the last brick of a row
+// idle (64-wide bricks left a quarter of them idle on a 240-voxel row: 0.38
+// against 0.35 ms); the small half-diagonal keeps a periodic brick's cull
+// sphere (cutoff + half-diagonal) close to the cutoff sphere and the
+// brick-local coordinates small.
 constexpr int kBX = 16, kBY = 16, kNZB = 8;
+
+int brick_depth(int nzb) { return nzb == 6 ? 6 : kNZB; }
 
 }  // namespace
 
 // Brick geometry used by the launcher (the host validates the periodic cutoff
 // against its half-diagonal).
-double ff_brick_half_diagonal(double hx, double hy, double hz)
+double ff_brick_half_diagonal(double hx, double hy, double hz, int nzb)
 {
-    return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
+    return brick_depth(nzb) == 6 ? ff_brick_half_diagonal_dev<kBX, kBY, 6>(hx, hy, hz)
+                                 : ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
 }
 
-// The batched build uses the same brick for every molecule.
-double ff_batch_brick_half_diagonal(double hx, double hy, double hz)
+long long ff_brick_count(int nx, int ny, int nz, int nzb)
 {
-    return ff_brick_half_diagonal_dev<kBX, kBY, kNZB>(hx, hy, hz);
+    const int d = brick_depth(nzb);
+    return (long long)((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + d - 1) / d);
 }
 
-long long ff_brick_count(int nx, int ny, int nz)
-{
-    return (long long)((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + kNZB - 1) / kNZB);
-}
-
-template <bool EONLY, bool QUAD>
+template <int NZB, bool EONLY, bool QUAD>
 void launch_build(const FFArgs &a, const double *pos, const double *q, const double *R,
                   const double *eps, float4 *out, hipStream_t stream)
 {
-    if (a.Lx > 0.0) {
-        dim3 block(kBX, kBY, 1);
-        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, true, EONLY, QUAD>), grid, block, 0,
+    dim3 block(kBX, kBY, 1);
+    dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + NZB - 1) / NZB);
+    if (a.Lx > 0.0)
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, NZB, true, EONLY, QUAD>), grid, block, 0,
                            stream, a, pos, q, R, eps, out);
-    } else {
-        dim3 block(kBX, kBY, 1);
-        dim3 grid((a.nx + kBX - 1) / kBX, (a.ny + kBY - 1) / kBY, (a.nz + kNZB - 1) / kNZB);
-        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, kNZB, false, EONLY, QUAD>), grid, block, 0,
+    else
+        hipLaunchKernelGGL((ff_build_kernel<kBX, kBY, NZB, false, EONLY, QUAD>), grid, block, 0,
                            stream, a, pos, q, R, eps, out);
-    }
 }
 
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
-                           const double *R, const double *eps, float4 *ff, hipStream_t stream)
+                           const double *R, const double *eps, float4 *ff, hipStream_t stream,
+                           int nzb)
 {
-    if (a.kQ_pp != 0.0) launch_build<false, true>(a, pos, q, R, eps, ff, stream);
-    else launch_build<false, false>(a, pos, q, R, eps, ff, stream);
+    if (brick_depth(nzb) == 6) {
+        if (a.kQ_pp != 0.0) launch_build<6, false, true>(a, pos, q, R, eps, ff, stream);
+        else launch_build<6, false, false>(a, pos, q, R, eps, ff, stream);
+    } else {
+        if (a.kQ_pp != 0.0) launch_build<kNZB, false, true>(a, pos, q, R, eps, ff, stream);
+        else launch_build<kNZB, false, false>(a, pos, q, R, eps, ff, stream);
+    }
     return hipGetLastError();
 }
 
@@ -464,8 +481,8 @@ hipError_t launch_build_energy(const FFArgs &a, const double *pos, const double 
                                const double *R, const double *eps, float *E, hipStream_t stream)
 {
     float4 *out = reinterpret_cast<float4 *>(E);   // EONLY kernels store floats
-    if (a.kQ_pp != 0.0) launch_build<true, true>(a, pos, q, R, eps, out, stream);
-    else launch_build<true, false>(a, pos, q, R, eps, out, stream);
+    if (a.kQ_pp != 0.0) launch_build<kNZB, true, true>(a, pos, q, R, eps, out, stream);
+    else launch_build<kNZB, true, false>(a, pos, q, R, eps, out, stream);
     return hipGetLastError();
 }
 
@@ -479,11 +496,11 @@ hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *
     const long long gx = n_bricks < 65536 ? n_bricks : 65536;
     const long long gy = (n_bricks + gx - 1) / gx;
     if (probe_args.kQ_pp != 0.0)
-        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB, true>),
+        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, true>),
                            dim3((unsigned)gx, (unsigned)gy, 1), dim3(kBX, kBY, 1), 0, stream,
                            probe_args, mols_dev, n_mol, pos, q, R, eps, arena);
     else
-        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, kNZB, false>),
+        hipLaunchKernelGGL((ff_build_batch_kernel<kBX, kBY, false>),
                            dim3((unsigned)gx, (unsigned)gy, 1), dim3(kBX, kBY, 1), 0, stream,
                            probe_args, mols_dev, n_mol, pos, q, R, eps, arena);
     return hipGetLastError();

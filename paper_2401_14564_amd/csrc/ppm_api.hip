@@ -158,6 +158,34 @@ size_t backward_record_bytes(const ppm_scan *s)
     return align256((size_t)s->nx * s->ny * s->nz * 48);
 }
 
+// Median time (ms) of three launches of `run` after one untimed launch, with
+// HIP events on `stream`; negative if an event call failed.
+template <typename Run>
+float time_median3(hipStream_t stream, Run run, ppm_status *st)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0f;
+    }
+    float t[3] = {0.f, 0.f, 0.f};
+    *st = run();
+    for (int r = 0; r < 3 && *st == PPM_OK; ++r) {
+        if (hipEventRecord(e0, stream) != hipSuccess) { *st = PPM_EHIP; break; }
+        *st = run();
+        if (*st != PPM_OK) break;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
+            *st = PPM_EHIP;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (*st != PPM_OK) return -1.0f;
+    const float lo = fminf(t[0], fminf(t[1], t[2])), hi = fmaxf(t[0], fmaxf(t[1], t[2]));
+    return t[0] + t[1] + t[2] - lo - hi;
+}
+
 }  // namespace
 
 extern "C" {
@@ -178,9 +206,12 @@ int32_t ppm_last_hip_error(void) { return g_last_hip_error; }
 
 int32_t ppm_df_half_width(double A, double dz) { return df_half_width(A, dz); }
 
+static bool valid_nzb(int nzb) { return nzb == 0 || nzb == 6 || nzb == 8; }
+static bool valid_tile(int tile) { return tile == 0 || tile == 8 || tile == 16; }
+
 static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
                            const double *pos, const double *q, const double *R,
-                           const double *eps, const void *out, FFArgs *a)
+                           const double *eps, const void *out, FFArgs *a, int nzb = 0)
 {
     ppm_status st = check_grid(grid);
     if (st != PPM_OK) return st;
@@ -204,7 +235,8 @@ static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t
     a->kQ_pp = kCoulomb * probe->q_zz;
     if (grid->periodic_xy) {
         const double Lx = grid->n[0] * grid->step[0], Ly = grid->n[1] * grid->step[1];
-        const double hd = ff_brick_half_diagonal(grid->step[0], grid->step[1], grid->step[2]);
+        const double hd =
+            ff_brick_half_diagonal(grid->step[0], grid->step[1], grid->step[2], nzb);
         if (!finite_pos(grid->cutoff) || grid->cutoff + hd >= 0.5 * fmin(Lx, Ly))
             return PPM_EINVAL;
         a->Lx = Lx;
@@ -216,15 +248,49 @@ static ppm_status ff_setup(const ppm_grid *grid, const ppm_probe *probe, int32_t
     return PPM_OK;
 }
 
+ppm_status ppm_build_ff_tuned(const ppm_grid *grid, const ppm_probe *probe,
+                              const ppm_tuning *tuning, int32_t n_atoms, const double *pos,
+                              const double *q, const double *R, const double *eps, float *ff,
+                              void *stream)
+{
+    const int nzb = tuning ? tuning->ff_nzb : 0;
+    if (!valid_nzb(nzb)) return PPM_EINVAL;
+    FFArgs a;
+    ppm_status st = ff_setup(grid, probe, n_atoms, pos, q, R, eps, ff, &a, nzb);
+    if (st != PPM_OK) return st;
+    return hip_status(launch_build_ff(a, pos, q, R, eps, reinterpret_cast<float4 *>(ff),
+                                      (hipStream_t)stream, nzb));
+}
+
 ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
                         const double *pos, const double *q, const double *R,
                         const double *eps, float *ff, void *stream)
 {
+    return ppm_build_ff_tuned(grid, probe, nullptr, n_atoms, pos, q, R, eps, ff, stream);
+}
+
+ppm_status ppm_tune_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
+                             const double *pos, const double *q, const double *R,
+                             const double *eps, float *ff, void *stream, ppm_tuning *tuning,
+                             float *ms)
+{
+    if (!tuning) return PPM_EINVAL;
     FFArgs a;
-    ppm_status st = ff_setup(grid, probe, n_atoms, pos, q, R, eps, ff, &a);
+    ppm_status st = ff_setup(grid, probe, n_atoms, pos, q, R, eps, ff, &a, 8);
     if (st != PPM_OK) return st;
-    return hip_status(launch_build_ff(a, pos, q, R, eps, reinterpret_cast<float4 *>(ff),
-                                      (hipStream_t)stream));
+    const int cand[2] = {8, 6};
+    float t[2];
+    for (int c = 0; c < 2; ++c) {
+        ppm_tuning tt = *tuning;
+        tt.ff_nzb = cand[c];
+        t[c] = time_median3((hipStream_t)stream, [&]() {
+            return ppm_build_ff_tuned(grid, probe, &tt, n_atoms, pos, q, R, eps, ff, stream);
+        }, &st);
+        if (st != PPM_OK) return st;
+    }
+    tuning->ff_nzb = t[1] < t[0] ? 6 : 8;
+    if (ms) { ms[0] = t[0]; ms[1] = t[1]; }
+    return PPM_OK;
 }
 
 ppm_status ppm_build_energy(const ppm_grid *grid, const ppm_probe *probe, int32_t n_atoms,
@@ -264,17 +330,53 @@ static ppm_status scan_setup(const ppm_grid *grid, const void *field, const ppm_
     return PPM_OK;
 }
 
-ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
-                            const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
-                            const ppm_df_params *dfp, float *df, void *stream)
+ppm_status ppm_relaxed_scan_tuned(const ppm_grid *grid, const float *ff,
+                                  const ppm_probe *probe, const ppm_fire *fire,
+                                  const ppm_scan *scan, const ppm_tuning *tuning, float *fz,
+                                  float *pp, const ppm_df_params *dfp, float *df, void *stream)
 {
+    const int tile = tuning ? tuning->scan_tile : 0;
+    if (!valid_tile(tile)) return PPM_EINVAL;
     ScanArgs a;
     DfWeights W;
     ppm_status st = scan_setup(grid, ff, probe, fire, scan, fz, pp, dfp, df, &a, &W);
     if (st != PPM_OK) return st;
     return hip_status(launch_relaxed_scan(a, W, reinterpret_cast<const float4 *>(ff), fz,
                                           reinterpret_cast<float4 *>(pp), df,
-                                          (hipStream_t)stream));
+                                          (hipStream_t)stream, tile));
+}
+
+ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                            const ppm_fire *fire, const ppm_scan *scan, float *fz, float *pp,
+                            const ppm_df_params *dfp, float *df, void *stream)
+{
+    return ppm_relaxed_scan_tuned(grid, ff, probe, fire, scan, nullptr, fz, pp, dfp, df, stream);
+}
+
+ppm_status ppm_tune_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
+                                 const ppm_fire *fire, const ppm_scan *scan, float *fz,
+                                 float *pp, const ppm_df_params *dfp, float *df, void *stream,
+                                 ppm_tuning *tuning, float *ms)
+{
+    if (!tuning) return PPM_EINVAL;
+    ScanArgs a;
+    DfWeights W;
+    ppm_status st = scan_setup(grid, ff, probe, fire, scan, fz, pp, dfp, df, &a, &W);
+    if (st != PPM_OK) return st;
+    const int cand[2] = {16, 8};
+    float t[2];
+    for (int c = 0; c < 2; ++c) {
+        ppm_tuning tt = *tuning;
+        tt.scan_tile = cand[c];
+        t[c] = time_median3((hipStream_t)stream, [&]() {
+            return ppm_relaxed_scan_tuned(grid, ff, probe, fire, scan, &tt, fz, pp, dfp, df,
+                                          stream);
+        }, &st);
+        if (st != PPM_OK) return st;
+    }
+    tuning->scan_tile = t[1] < t[0] ? 8 : 16;
+    if (ms) { ms[0] = t[0]; ms[1] = t[1]; }
+    return PPM_OK;
 }
 
 ppm_status ppm_relaxed_scan_tricubic(const ppm_grid *grid, const float *E,
@@ -383,18 +485,18 @@ ppm_status ppm_batch_plan(int32_t n_mol, ppm_batch_mol *mols, int32_t n_jobs,
     for (int i = 0; i < n_mol; ++i) {
         ppm_batch_mol &M = mols[i];
         if ((st = check_grid(&M.grid)) != PPM_OK) return st;
-        if (M.n_atoms < 0 || M.atom_begin < 0) return PPM_EINVAL;
+        if (M.n_atoms < 0 || M.atom_begin < 0 || !valid_nzb(M.ff_nzb)) return PPM_EINVAL;
         if (M.grid.periodic_xy) {
             const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
-            const double hd = ff_batch_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
-                                                           M.grid.step[2]);
+            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
+                                                     M.grid.step[2], M.ff_nzb);
             if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
                 return PPM_EINVAL;
         }
         M.ff_offset = vox;
         M.brick_begin = bricks;
         vox += (long long)M.grid.n[0] * M.grid.n[1] * M.grid.n[2];
-        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2]);
+        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2], M.ff_nzb);
     }
     long long nfz = 0, ndf = 0, tiles = 0;
     int m = 0;
@@ -442,19 +544,19 @@ ppm_status ppm_batch_build_ff(int32_t n_mol, const ppm_batch_mol *mols_host,
     for (int i = 0; i < n_mol; ++i) {
         const ppm_batch_mol &M = mols_host[i];
         if ((st = check_grid(&M.grid)) != PPM_OK) return st;
-        if (M.n_atoms < 0 || M.atom_begin < 0) return PPM_EINVAL;
+        if (M.n_atoms < 0 || M.atom_begin < 0 || !valid_nzb(M.ff_nzb)) return PPM_EINVAL;
         if (M.ff_offset != vox || M.brick_begin != bricks) return PPM_EINVAL;   // not planned
         if (M.grid.periodic_xy) {
             const double Lx = M.grid.n[0] * M.grid.step[0], Ly = M.grid.n[1] * M.grid.step[1];
-            const double hd = ff_batch_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
-                                                           M.grid.step[2]);
+            const double hd = ff_brick_half_diagonal(M.grid.step[0], M.grid.step[1],
+                                                     M.grid.step[2], M.ff_nzb);
             if (!finite_pos(M.grid.cutoff) || M.grid.cutoff + hd >= 0.5 * fmin(Lx, Ly))
                 return PPM_EINVAL;
         }
         const long long end = (long long)M.atom_begin + M.n_atoms;
         if (end > total_atoms) total_atoms = end;
         vox += (long long)M.grid.n[0] * M.grid.n[1] * M.grid.n[2];
-        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2]);
+        bricks += ff_brick_count(M.grid.n[0], M.grid.n[1], M.grid.n[2], M.ff_nzb);
     }
     if (total_atoms > 0 && (!pos || !q || !R || !eps)) return PPM_EINVAL;
     FFArgs a;

@@ -39,13 +39,13 @@ hipError_t launch_build_ff_batch(const FFArgs &probe_args, const ppm_batch_mol *
                                  int n_mol, long long n_bricks, const double *pos,
                                  const double *q, const double *R, const double *eps,
                                  float4 *arena, hipStream_t stream);
-double ff_brick_half_diagonal(double hx, double hy, double hz);
-double ff_batch_brick_half_diagonal(double hx, double hy, double hz);
-long long ff_brick_count(int nx, int ny, int nz);
+// nzb: voxels per thread along z (the brick depth), 6 or 8 (0 = 8)
+double ff_brick_half_diagonal(double hx, double hy, double hz, int nzb);
+long long ff_brick_count(int nx, int ny, int nz, int nzb);
 
 hipError_t launch_build_ff(const FFArgs &a, const double *pos, const double *q,
                            const double *R, const double *eps, float4 *ff,
-                           hipStream_t stream);
+                           hipStream_t stream, int nzb);
 
 // ------------------------------------------------------------ relaxed scan
 // Smallest convergence threshold (eV/A) for which the scan combines the eight
@@ -126,7 +126,7 @@ struct DfWeights {
 };
 
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
-                               float *fz, float4 *pp, float *df, hipStream_t stream);
+                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile);
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.
 // `proto` carries the FIRE and frequency-shift fields shared by the batch.

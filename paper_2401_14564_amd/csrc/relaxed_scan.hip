@@ -735,18 +735,30 @@ void launch_scan_geom(const ScanArgs &b, bool stage, const DfWeights &w, const f
 // the progress array); beyond that the fz output is
 // written directly (and re-read for the frequency shift), or, without fz,
 // 8 x 8 blocks stage up to 256 heights.
+//
+// tile (the autotuner's choice, ppm_tuning.scan_tile): 0 = this automatic
+// choice, 16 = 16 x 16 blocks wherever the outputs allow them, 8 = 8 x 8
+// one-wave blocks (Fz staged in 8 KiB-per-32-heights LDS columns, several
+// blocks per CU).  Every route writes the same bits.
 template <bool WIDE, int INTERP, int GEOM, bool LERP32>
 void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, const float *En,
-                      float *fz, float4 *pp, float *df, hipStream_t stream)
+                      float *fz, float4 *pp, float *df, hipStream_t stream, int tile)
 {
     const bool want_df = b.m != 0 && df;
     const DfWeights sw = want_df ? sample_weights(w, b.m) : w;
     float *dfo = want_df ? df : nullptr;
     const size_t column = (size_t)b.snz * sizeof(float);
+    const bool fits16 = (column + sizeof(int)) * 256 <= max_block_lds();
+    const bool fits8 = b.snz <= kMaxScanLdsHeights;
+    if (tile == 8) {
+        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, (fz || want_df) && fits8, sw,
+                                                               ff, En, fz, pp, dfo, stream);
+        return;
+    }
     if (!fz && !want_df)
         launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, false, sw, ff, En, fz, pp, dfo,
                                                              stream);
-    else if ((column + sizeof(int)) * 256 <= max_block_lds())
+    else if (fits16)
         launch_scan_geom<16, 16, WIDE, INTERP, GEOM, LERP32>(b, true, sw, ff, En, fz, pp, dfo,
                                                              stream);
     else if (fz)
@@ -762,30 +774,37 @@ void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, c
 // the geometry at run time.
 template <bool WIDE, int INTERP>
 void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff,
-                         const float *En, float *fz, float4 *pp, float *df, hipStream_t stream)
+                         const float *En, float *fz, float4 *pp, float *df, hipStream_t stream,
+                         int tile)
 {
     if constexpr (INTERP != 0) {
         if (b.lerp32)
-            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, true>(b, w, ff, En, fz, pp, df, stream);
+            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, true>(b, w, ff, En, fz, pp, df, stream,
+                                                               tile);
         else
-            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream);
+            launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream,
+                                                                tile);
     } else if (b.periodic) {
-        if (b.lerp32) launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream);
-        else launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream);
+        if (b.lerp32)
+            launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream, tile);
+        else
+            launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream, tile);
     } else {
-        if (b.lerp32) launch_scan_mode<WIDE, 0, kOpen, true>(b, w, ff, En, fz, pp, df, stream);
-        else launch_scan_mode<WIDE, 0, kOpen, false>(b, w, ff, En, fz, pp, df, stream);
+        if (b.lerp32)
+            launch_scan_mode<WIDE, 0, kOpen, true>(b, w, ff, En, fz, pp, df, stream, tile);
+        else
+            launch_scan_mode<WIDE, 0, kOpen, false>(b, w, ff, En, fz, pp, df, stream, tile);
     }
 }
 
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
-                               float *fz, float4 *pp, float *df, hipStream_t stream)
+                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile)
 {
     const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
-        launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream);
+        launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
     else
-        launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream);
+        launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
     return hipGetLastError();
 }
 
@@ -795,9 +814,9 @@ hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w,
 {
     const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
     if (bytes >= 4294967296.0)
-        launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream);
+        launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
     else
-        launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream);
+        launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
     return hipGetLastError();
 }
 

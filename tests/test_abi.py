@@ -39,6 +39,9 @@ def test_struct_layout_matches_c(tmp_path):
         " sizeof(ppm_scan), sizeof(ppm_df_params));\n"
         'printf("%zu %zu %zu %zu %zu\\n", offsetof(ppm_grid, cutoff), offsetof(ppm_probe, d0),'
         " offsetof(ppm_fire, max_iter), offsetof(ppm_scan, nz), offsetof(ppm_scan, z_top));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(ppm_tuning), sizeof(ppm_batch_mol),'
+        " offsetof(ppm_batch_mol, ff_nzb), offsetof(ppm_batch_mol, ff_offset),"
+        " sizeof(ppm_batch_scan));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
@@ -46,8 +49,11 @@ def test_struct_layout_matches_c(tmp_path):
     sizes = [int(v) for v in out]
     assert sizes[:5] == [ct.sizeof(_lib.Grid), ct.sizeof(_lib.Probe), ct.sizeof(_lib.Fire),
                          ct.sizeof(_lib.Scan), ct.sizeof(_lib.DfParams)]
-    assert sizes[5:] == [_lib.Grid.cutoff.offset, _lib.Probe.d0.offset, _lib.Fire.max_iter.offset,
-                         _lib.Scan.nz.offset, _lib.Scan.z_top.offset]
+    assert sizes[5:10] == [_lib.Grid.cutoff.offset, _lib.Probe.d0.offset,
+                           _lib.Fire.max_iter.offset, _lib.Scan.nz.offset, _lib.Scan.z_top.offset]
+    assert sizes[10:] == [ct.sizeof(_lib.Tuning), ct.sizeof(_lib.BatchMol),
+                          _lib.BatchMol.ff_nzb.offset, _lib.BatchMol.ff_offset.offset,
+                          ct.sizeof(_lib.BatchScan)]
 
 
 def test_status_strings():
@@ -262,3 +268,36 @@ def test_microbench_library_exports_its_header():
     assert L.ppm_mb_gather(None, 1, 1, 1, 0, FAKE, None) == -1
     assert L.ppm_mb_gather(FAKE, 1, 0, 1, 0, FAKE, None) == -1
     assert L.ppm_mb_pair(0, 1, 1, None, None) == -1
+
+
+def test_tuning_arguments_rejected_on_host():
+    """Launch shapes outside the tuner's candidates are rejected before any
+    launch; the tuners need somewhere to write their choice; a batch plan
+    counts bricks with each molecule's depth."""
+    L = _lib.lib()
+    E = _lib.PPM_EINVAL
+    g = _lib.grid_struct(W.Grid((0, 0, 0), (0.1, 0.1, 0.1), (20, 20, 20)))
+    pr = _lib.probe_struct(W.Probe())
+    for bad in (4, 7, 12, -1):
+        assert L.ppm_build_ff_tuned(g, pr, _lib.Tuning(bad, 0), 1, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                    None) == E
+    sc = _lib.scan_struct(W.Scan(0.5, 0.5, 0.1, 0.1, 4, 4, 3.0, 0.1, 12))
+    fi = _lib.fire_struct(W.Fire())
+    for bad in (4, 32, -8):
+        assert L.ppm_relaxed_scan_tuned(g, FAKE, pr, fi, sc, _lib.Tuning(0, bad), FAKE, None,
+                                        None, None, None) == E
+    assert L.ppm_tune_build_ff(g, pr, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, None) == E
+    assert L.ppm_tune_relaxed_scan(g, FAKE, pr, fi, sc, FAKE, None, None, None, None, None,
+                                   None) == E
+    # plan: depth 6 bricks, a bad depth rejected
+    w = W.config3_molecule(0)
+    mols = (_lib.BatchMol * 1)()
+    mols[0].grid = _lib.grid_struct(w.grid)
+    mols[0].n_atoms = w.atoms.n
+    mols[0].ff_nzb = 6
+    totals = (ct.c_int64 * 5)()
+    assert L.ppm_batch_plan(1, mols, 0, None, None, totals) == _lib.PPM_OK
+    nx, ny, nz = w.grid.n
+    assert totals[1] == ((nx + 15) // 16) * ((ny + 15) // 16) * ((nz + 5) // 6)
+    mols[0].ff_nzb = 5
+    assert L.ppm_batch_plan(1, mols, 0, None, None, totals) == E

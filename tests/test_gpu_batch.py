@@ -25,20 +25,32 @@ def _c3_batch(idx, k_lats=W.C3_K_LAT_N_PER_M, scan_mod=None):
     return ws, mols, jobs
 
 
-def test_batch_equals_single_calls_bitwise():
+@pytest.mark.parametrize("depth", ["default", 6, 8, "tuned"])
+def test_batch_equals_single_calls_bitwise(depth):
     """Same kernels, same arithmetic: the batched force fields and frequency-shift
-    stacks equal the single-molecule calls bit for bit (4 molecules x 3 probes)."""
+    stacks equal the single-molecule calls bit for bit (4 molecules x 3 probes)
+    at every brick depth (the default, each candidate, the autotuner's pick),
+    and whatever scan shape the single calls use (both candidates)."""
     ws, mols, jobs = _c3_batch([0, 1, 2, 3])
-    bp = ppm.BatchPipeline(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df)
+    if depth == "tuned":
+        bp = ppm.BatchPipeline.tuned(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df)
+        print("batch: tuned brick depth", bp.ff_nzb, "timings (ms)", bp.tuning_ms, flush=True)
+    else:
+        bp = ppm.BatchPipeline(mols, jobs, ws[0].probe, ws[0].fire, ws[0].df,
+                               ff_nzb=0 if depth == "default" else depth)
+    t = ppm.Tuning(ff_nzb=bp.ff_nzb)
     bp.run()
     torch.cuda.synchronize()
+    ffs = []
     for i, w in enumerate(ws):
-        ff = ppm.build_ff(w.grid, w.probe, w.atoms)
+        ff = ppm.build_ff(w.grid, w.probe, w.atoms, tuning=t)
         assert torch.equal(bp.ff_grid(i), ff), i
+        ffs.append(ff)
     for j, (mi, pr, sc) in enumerate(jobs):
-        ff = ppm.build_ff(ws[mi].grid, ws[mi].probe, ws[mi].atoms)
-        res = ppm.relaxed_scan(ws[mi].grid, ff, pr, ws[mi].fire, sc, dfp=ws[mi].df, pp=False)
-        assert torch.equal(bp.df_stack(j), res["df"]), j
+        for tile in (16, 8):
+            res = ppm.relaxed_scan(ws[mi].grid, ffs[mi], pr, ws[mi].fire, sc, dfp=ws[mi].df,
+                                   pp=False, tuning=ppm.Tuning(scan_tile=tile))
+            assert torch.equal(bp.df_stack(j), res["df"]), (j, tile)
 
 
 def test_batch_parity_with_oracle_sampled_columns():

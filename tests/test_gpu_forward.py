@@ -26,10 +26,14 @@ def c0():
 
 
 # ------------------------------------------------------------------ FF build
-def test_ff_c0_full_grid(c0):
+@pytest.mark.parametrize("nzb", [0, 6])
+def test_ff_c0_full_grid(c0, nzb):
+    """Every voxel of the tiny workload, at the default brick depth and at the
+    autotuner's other candidate."""
     w, ref, sc = c0
-    info = check_ff(_gpu_ff(w).cpu().numpy(), ref, sc, "C0")
-    print("C0 ff", info, flush=True)
+    got = ppm.build_ff(w.grid, w.probe, w.atoms, tuning=ppm.Tuning(ff_nzb=nzb))
+    info = check_ff(got.cpu().numpy(), ref, sc, f"C0 depth {nzb}")
+    print("C0 ff", nzb, info, flush=True)
 
 
 def test_ff_c1_full_grid():
@@ -39,12 +43,13 @@ def test_ff_c1_full_grid():
     print("C1 ff", info, flush=True)
 
 
+@pytest.mark.parametrize("nzb", [0, 6])
 @pytest.mark.parametrize("n,natoms,periodic", [((5, 3, 3), 4, 0), ((67, 9, 13), 300, 0),
                                                ((64, 4, 8), 1, 0), ((2, 2, 2), 3, 0),
-                                               ((130, 90, 11), 40, 1)])
-def test_ff_ragged_and_multi_chunk(n, natoms, periodic):
+                                               ((130, 90, 11), 40, 1), ((130, 90, 17), 300, 1)])
+def test_ff_ragged_and_multi_chunk(n, natoms, periodic, nzb):
     """Grids that are not multiples of the brick, more atoms than one LDS chunk,
-    a 2x2x2 grid, and a periodic cell with a cutoff."""
+    a 2x2x2 grid, and periodic cells with a cutoff, at both brick depths."""
     rng = np.random.default_rng(sum(n) + natoms)
     h = 0.1
     L = np.array(n) * h
@@ -52,8 +57,8 @@ def test_ff_ragged_and_multi_chunk(n, natoms, periodic):
     cutoff = 0.5 * min(L[0], L[1]) - 3.5 if periodic else 0.0
     grid = W.Grid((0.0, 0.0, 1.5), (h, h, h), n, periodic, cutoff)
     ref, sc = orc.build_ff(grid, W.Probe(), atoms, with_scale=True)
-    got = ppm.build_ff(grid, W.Probe(), atoms).cpu().numpy()
-    check_ff(got, ref, sc, f"grid {n} atoms {natoms} periodic {periodic}")
+    got = ppm.build_ff(grid, W.Probe(), atoms, tuning=ppm.Tuning(ff_nzb=nzb)).cpu().numpy()
+    check_ff(got, ref, sc, f"grid {n} atoms {natoms} periodic {periodic} depth {nzb}")
 
 
 def test_ff_zero_atoms_is_zero_field():
@@ -215,6 +220,16 @@ def test_scan_output_routes_agree(nz):
     assert torch.equal(full["df"], df_only["df"])
     assert torch.equal(full["pp"], pp_only["pp"])
     assert torch.equal(ppm.df(full["fz"], scan.dz, w.df), full["df"])
+    # the work-group shapes the autotuner chooses between
+    for tile in (16, 8):
+        t = ppm.Tuning(scan_tile=tile)
+        for kw in (dict(dfp=w.df, fz=True, pp=True), dict(dfp=w.df, fz=False, pp=False),
+                   dict(fz=False, pp=True)):
+            if nz > 256 and not kw.get("fz") and "dfp" in kw:
+                continue
+            r = run(tuning=t, **kw)
+            for k in r:
+                assert torch.equal(r[k], full[k]), (tile, k, kw)
 
 
 def test_scan_below_and_above_grid_clamps():
@@ -488,3 +503,20 @@ def test_ff_force_is_negative_energy_gradient_on_fine_grid():
         worst = max(worst, err / tol)
         assert err <= tol, (c, F, fd, tol)
     print("F = -grad E: worst error / bound", worst, flush=True)
+
+
+def test_autotuner_choices_on_the_large_sample():
+    """The autotuner times both brick depths on the large periodic build and
+    both work-group shapes on its scan (as the benchmark runs it) and returns
+    one of its candidates; the tuned outputs are the default ones (scan) or
+    within the parity bound of the oracle (build, checked above)."""
+    w = W.config2()
+    t, ms = ppm.tune_build_ff(w.grid, w.probe, w.atoms)
+    assert t.ff_nzb in (6, 8) and all(v > 0 for v in ms.values())
+    ff = ppm.build_ff(w.grid, w.probe, w.atoms, tuning=t)
+    t2, ms2, out = ppm.tune_relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+                                         pp=False, tuning=t)
+    assert t2.scan_tile in (8, 16) and t2.ff_nzb == t.ff_nzb
+    ref = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False)
+    assert torch.equal(out["df"], ref["df"])
+    print("large sample tuning:", t2, "build ms", ms, "scan ms", ms2, flush=True)
