@@ -344,6 +344,31 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
                                      size_t workspace_bytes, void *stream);
 
 /*
+ * ppm_relaxed_scan_backward_noalloc -- for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): ppm_relaxed_scan_backward without the workspace argument.
+ * The workspace is a static device array of PPM_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that every GPU the library runs on holds until the process ends; its
+ * address is looked up once per device (hipGetSymbolAddress, with that device
+ * current).  The call allocates nothing and runs the same kernels, so its
+ * gradients equal ppm_relaxed_scan_backward's bit for bit.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.
+ * Errors: as ppm_relaxed_scan_backward; PPM_ERANGE when
+ * ppm_backward_workspace_bytes(scan, n_atoms) exceeds PPM_NOALLOC_SCRATCH_BYTES
+ * (the differentiation workload, 128 x 128 x 30 points and 60 atoms, needs
+ * 34.5 MiB); PPM_EHIP if the array's address cannot be obtained.
+ */
+#define PPM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+ppm_status ppm_relaxed_scan_backward_noalloc(const ppm_grid *grid, const float *ff,
+                                             const ppm_probe *probe, const ppm_scan *scan,
+                                             const ppm_df_params *dfp, int32_t n_atoms,
+                                             const double *pos, const double *q,
+                                             const double *R, const double *eps, const float *pp,
+                                             const float *grad_df, double *g_pos, double *g_q,
+                                             double *g_R, double *g_eps, void *stream);
+
+/*
  * ppm_lateral_stiffness -- stiffness of the probe's lateral vibration modes at
  * every relaxed point of a scan (Sec. 3.3: the curvature of the tip-sample
  * interaction shifts the lateral CO mode, the basis of the IETS contrast).

@@ -26,7 +26,7 @@ EXPORTED = (
     "ppm_batch_relaxed_scan", "ppm_lateral_stiffness", "ppm_build_energy",
     "ppm_relaxed_scan_tricubic", "ppm_tip_density", "ppm_hartree_workspace_bytes",
     "ppm_hartree_ff", "ppm_build_ff_tuned", "ppm_relaxed_scan_tuned", "ppm_tune_build_ff",
-    "ppm_tune_relaxed_scan",
+    "ppm_tune_relaxed_scan", "ppm_relaxed_scan_backward_noalloc",
 )
 
 
@@ -117,6 +117,10 @@ def lib():
                                                     i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                                     vp, ct.c_size_t, vp]
             L.ppm_relaxed_scan_backward.restype = st
+            L.ppm_relaxed_scan_backward_noalloc.argtypes = [P(Grid), vp, P(Probe), P(Scan),
+                                                            P(DfParams), i32, vp, vp, vp, vp,
+                                                            vp, vp, vp, vp, vp, vp, vp]
+            L.ppm_relaxed_scan_backward_noalloc.restype = st
             L.ppm_batch_plan.argtypes = [i32, P(BatchMol), i32, P(BatchScan), P(DfParams),
                                          P(ct.c_int64)]
             L.ppm_batch_plan.restype = st

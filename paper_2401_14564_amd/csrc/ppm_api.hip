@@ -4,20 +4,56 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "ppm.h"
 #include "ppm_kernels.h"
 
 using namespace ppm;
 
+// Workspace of ppm_relaxed_scan_backward_noalloc: one copy in every GPU's
+// memory that the library runs on, held until the process ends.  In host code
+// `scratch` is only a symbol: its device address (different on each GPU) comes
+// from hipGetSymbolAddress, taken once per device in noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[PPM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local int32_t g_last_hip_error = 0;
+
+constexpr int kMaxScratchDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxScratchDevices];
+std::mutex g_scratch_mutex;
 
 ppm_status hip_status(hipError_t e)
 {
     if (e == hipSuccess) return PPM_OK;
     g_last_hip_error = (int32_t)e;
     return PPM_EHIP;
+}
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current, then cached).
+ppm_status noalloc_scratch(void **out)
+{
+    int dev = 0;
+    ppm_status st = hip_status(hipGetDevice(&dev));
+    if (st != PPM_OK) return st;
+    if (dev < 0 || dev >= kMaxScratchDevices) return PPM_EUNSUPPORTED;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+        if (!p) {
+            st = hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (st != PPM_OK) return st;
+            if (!p) return PPM_EHIP;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return PPM_OK;
 }
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
@@ -469,6 +505,26 @@ ppm_status ppm_relaxed_scan_backward(const ppm_grid *grid, const float *ff,
                                       reinterpret_cast<const float4 *>(pp), grad_df, pos, q, R,
                                       eps, rec, partial, g_pos, g_q, g_R, g_eps,
                                       (hipStream_t)stream));
+}
+
+ppm_status ppm_relaxed_scan_backward_noalloc(const ppm_grid *grid, const float *ff,
+                                             const ppm_probe *probe, const ppm_scan *scan,
+                                             const ppm_df_params *dfp, int32_t n_atoms,
+                                             const double *pos, const double *q,
+                                             const double *R, const double *eps, const float *pp,
+                                             const float *grad_df, double *g_pos, double *g_q,
+                                             double *g_R, double *g_eps, void *stream)
+{
+    if (check_scan(scan) != PPM_OK || n_atoms < 0) return PPM_EINVAL;
+    if (ppm_backward_workspace_bytes(scan, n_atoms) > (size_t)PPM_NOALLOC_SCRATCH_BYTES)
+        return PPM_ERANGE;
+    void *ws = nullptr;
+    ppm_status st = noalloc_scratch(&ws);
+    if (st != PPM_OK) return st;
+    // the kernels write every record and partial they read: nothing to clear
+    return ppm_relaxed_scan_backward(grid, ff, probe, scan, dfp, n_atoms, pos, q, R, eps, pp,
+                                     grad_df, g_pos, g_q, g_R, g_eps, ws,
+                                     (size_t)PPM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 static bool same_probe_lj(const ppm_probe &a, const ppm_probe &b)

@@ -301,3 +301,16 @@ def test_tuning_arguments_rejected_on_host():
     assert totals[1] == ((nx + 15) // 16) * ((ny + 15) // 16) * ((nz + 5) // 6)
     mols[0].ff_nzb = 5
     assert L.ppm_batch_plan(1, mols, 0, None, None, totals) == E
+
+
+def test_noalloc_backward_limit_checked_on_host():
+    """The no-alloc backward rejects a workload beyond its static array (and a
+    bad scan) on the host, before it looks up the array or launches anything."""
+    L = _lib.lib()
+    w = W.config1()
+    args = (_lib.grid_struct(w.grid), FAKE, _lib.probe_struct(w.probe), _lib.scan_struct(w.scan),
+            _lib.df_struct(w.df), w.atoms.n) + (FAKE,) * 10 + (None,)
+    assert L.ppm_relaxed_scan_backward_noalloc(*args) == _lib.PPM_ERANGE
+    bad = _lib.scan_struct(W.Scan(0.0, 0.0, 0.1, 0.1, 0, 4, 3.0, 0.1, 12))
+    args = args[:3] + (bad,) + args[4:]
+    assert L.ppm_relaxed_scan_backward_noalloc(*args) == _lib.PPM_EINVAL
