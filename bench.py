@@ -64,30 +64,41 @@ def _args():
                          "stream (double-buffered grid)")
     ap.add_argument("--kernels-once", action="store_true",
                     help="for rocprofv3 --pmc: a 1 GiB copy (counter calibration), then one "
-                         "launch of each hot kernel on the paper-scale workload")
+                         "launch of each hot kernel on the large periodic workload (tuned "
+                         "shapes) and on the paper-scale one")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) "
                          "into profiles/traffic.json")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="print the mean per-dispatch counters of the force-field and scan "
+                         "kernels in rocprofv3 --pmc output folders as a markdown table")
     return ap.parse_args()
 
 
 _FF_SRC = ["paper_2401_14564_amd/csrc/ff_build.hip", "paper_2401_14564_amd/csrc/ppm_kernels.h"]
 _SCAN_SRC = ["paper_2401_14564_amd/csrc/relaxed_scan.hip",
              "paper_2401_14564_amd/csrc/ppm_kernels.h", "paper_2401_14564_amd/csrc/ppm_device.h"]
-TRAFFIC_KERNELS = {
-    # key: (kernel-name fragment, source files whose hash the figures belong to)
-    "ff_build_c2": ("ff_build_kernel<16, 16, 8, true, false, false>", _FF_SRC),
-    "relaxed_scan_c2": ("relaxed_scan_kernel<16, 16, true, false, 0, 1,", _SCAN_SRC),
-    "ff_build_c1": ("ff_build_kernel<16, 16, 8, false, false, false>", _FF_SRC),
-    "relaxed_scan_c1": ("relaxed_scan_kernel<16, 16, true, false, 0, 0,", _SCAN_SRC),
-}
 CALIB_BYTES = 1 << 30
 
 
+def _ff_kernel(tuning, periodic):
+    """rocprofv3 name (template part) of the force-field kernel a build launches."""
+    nzb = getattr(tuning, "ff_nzb", 0) or 8
+    return f"ff_build_kernel<16, 16, {nzb}, {'true' if periodic else 'false'}, false, false>"
+
+
+def _scan_kernel(tuning, periodic):
+    """Name prefix of the scan kernel of a launch with a fused frequency shift
+    (Fz staged in LDS), the work-group shape of `tuning`."""
+    t = getattr(tuning, "scan_tile", 0) or 16
+    return f"relaxed_scan_kernel<{t}, {t}, true, false, 0, {1 if periodic else 0},"
+
+
 def kernels_once():
-    """For rocprofv3 --pmc: a 1 GiB copy (counter calibration), then one launch
-    of the force-field build and of the scan (as the timed steps run them) on
-    the large periodic and on the paper-scale workload."""
+    """For rocprofv3 --pmc: a 1 GiB copy (counter calibration), then the
+    autotuner and one launch of the force-field build and of the scan with its
+    choice (as the timed steps run them) on the large periodic workload, and
+    one of each at the default shapes on the paper-scale workload."""
     import torch
     import paper_2401_14564_amd as ppm
     from paper_2401_14564_amd import workloads as W
@@ -98,11 +109,20 @@ def kernels_once():
     b.copy_(a)                        # reads and writes CALIB_BYTES
     torch.cuda.synchronize()
     del a, b
-    for w in (W.config2(), W.config1()):
+    for w, tune in ((W.config2(), True), (W.config1(), False)):
         ff = ppm.build_ff(w.grid, w.probe, w.atoms)
+        t = None
+        if tune:
+            t, _ = ppm.tune_build_ff(w.grid, w.probe, w.atoms, out=ff)
+            t, _, _ = ppm.tune_relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df,
+                                            fz=False, pp=False, tuning=t)
         torch.cuda.synchronize()
-        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False)
+        ppm.build_ff(w.grid, w.probe, w.atoms, out=ff, tuning=t)
         torch.cuda.synchronize()
+        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False,
+                         tuning=t)
+        torch.cuda.synchronize()
+        print(w.name, "shapes", t, flush=True)
         del ff
     print("kernels-once done", flush=True)
 
@@ -125,8 +145,13 @@ def _read_pmc(folder, counter):
 
 
 def summarize_pmc(fetch_dir, write_dir):
+    """profiles/traffic.json: HBM bytes per launch of every force-field and scan
+    kernel in the two counter runs, scaled by what the counters read for the
+    known copy, with the hashes of the sources they were taken on."""
+    import re
     out = {"calibration": f"torch copy of {CALIB_BYTES} bytes (reads and writes that many)",
-           "units": "bytes per launch, counter KiB x 1024 x (known copy bytes / copy reading)"}
+           "units": "bytes per launch, counter KiB x 1024 x (known copy bytes / copy reading)",
+           "ff_source_sha": _sha(_FF_SRC), "scan_source_sha": _sha(_SCAN_SRC), "kernels": {}}
     for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _read_pmc(folder, counter)
         copy = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k.lower()]
@@ -134,26 +159,51 @@ def summarize_pmc(fetch_dir, write_dir):
         factor = (CALIB_BYTES / 1024.0) / calib_kib if calib_kib else 1.0
         out[f"{counter}_copy_reading_kib"] = calib_kib
         out[f"{counter}_scale"] = factor
-        for key, (frag, src) in TRAFFIC_KERNELS.items():
-            vals = [v for k, vs in rows.items() if frag in k for v in vs]
-            if not vals:
+        for k, vs in rows.items():
+            m = re.search(r"((ff_build_kernel|relaxed_scan_kernel)<[^>]*>)", k)
+            if not m:
                 continue
-            e = out.setdefault(key, {"source_sha": _sha(src)})
-            e[counter.lower() + "_bytes"] = float(np.mean(vals)) * 1024.0 * factor
-    for key in TRAFFIC_KERNELS:
-        e = out.get(key)
-        if e and "fetch_size_bytes" in e and "write_size_bytes" in e:
+            e = out["kernels"].setdefault(m.group(1), {"dispatches": len(vs)})
+            e[counter.lower() + "_bytes"] = float(np.mean(vs)) * 1024.0 * factor
+    for e in out["kernels"].values():
+        if "fetch_size_bytes" in e and "write_size_bytes" in e:
             e["hbm_bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
     out["commands"] = [
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/" + fetch_dir.rstrip("/").split(
-            "/")[-1] + " -o pmc -- python3 $REPO/bench.py --kernels-once",
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/" + write_dir.rstrip("/").split(
-            "/")[-1] + " -o pmc -- python3 $REPO/bench.py --kernels-once",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/{fetch_dir.rstrip('/')} -o pmc "
+        "-- python3 $REPO/bench.py --kernels-once",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/{write_dir.rstrip('/')} -o pmc "
+        "-- python3 $REPO/bench.py --kernels-once",
         f"python3 bench.py --summarize-pmc {fetch_dir} {write_dir}"]
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def summarize_counters(folders):
+    """Markdown table of the mean per-dispatch value of every counter in the
+    given rocprofv3 --pmc output folders, for the force-field and scan kernels."""
+    import csv
+    import glob
+    import re
+    table = {}
+    for folder in folders:
+        for fn in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    m = re.search(r"((ff_build_kernel|relaxed_scan_kernel)<[^>]*>)",
+                                  r["Kernel_Name"])
+                    if not m:
+                        continue
+                    table.setdefault(m.group(1), {}).setdefault(r["Counter_Name"], []).append(
+                        float(r["Counter_Value"]))
+    counters = sorted({c for v in table.values() for c in v})
+    lines = ["| kernel | " + " | ".join(counters) + " |",
+             "|---|" + "---|" * len(counters)]
+    for k, v in table.items():
+        lines.append(f"| `{k}` | " + " | ".join(
+            f"{np.mean(v[c]):.4g}" if c in v else "" for c in counters) + " |")
+    print("\n".join(lines))
 
 
 def _sha(paths):
@@ -164,18 +214,21 @@ def _sha(paths):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key, src, launches_bytes_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def _traffic(name_prefix, src_key, src):
+    """HBM bytes per launch of the kernel whose name starts with name_prefix,
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    e = t.get(kernel_key)
-    if not e or e.get("source_sha") != _sha(src):
+    if t.get(src_key) != _sha(src):
         return None
-    return e.get(launches_bytes_key)
+    for name, e in t.get("kernels", {}).items():
+        if name.startswith(name_prefix):
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup, tuning=None):
@@ -264,6 +317,9 @@ def main():
     if a.summarize_pmc:
         summarize_pmc(*a.summarize_pmc)
         return
+    if a.summarize_counters:
+        summarize_counters(a.summarize_counters)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -299,16 +355,15 @@ def main():
     scan_bytes = st["evals"] * BYTES_PER_EVAL + n_df * 4
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
     mb = _microbench(torch)
-    ff_src = TRAFFIC_KERNELS["ff_build_c2"][1]
-    scan_src = TRAFFIC_KERNELS["relaxed_scan_c2"][1]
-    ff_roof = {"kernel": "ff_build_kernel (periodic, shifted force)", "bound": "alu",
+    ff_name, scan_name = _ff_kernel(tuning, True), _scan_kernel(tuning, True)
+    ff_roof = {"kernel": ff_name, "bound": "alu",
                "achieved": round(ff_tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                "frac": round(ff_tflops / FP32_PEAK_TFLOPS, 4),
-               "traffic": _traffic("ff_build_c2", ff_src, "hbm_bytes_per_launch")}
+               "traffic": _traffic(ff_name, "ff_source_sha", _FF_SRC)}
     scan_l2 = mb["gather_coherent_gbs"] * BYTES_PER_EVAL / MB_BYTES_PER_GATHER
-    scan_roof = {"kernel": "relaxed_scan_kernel", "bound": "hbm", "achieved": round(scan_gbs, 1),
+    scan_roof = {"kernel": scan_name + "...>", "bound": "hbm", "achieved": round(scan_gbs, 1),
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(scan_gbs / HBM_PEAK_GBS, 4),
-                 "traffic": _traffic("relaxed_scan_c2", scan_src, "hbm_bytes_per_launch")}
+                 "traffic": _traffic(scan_name, "scan_source_sha", _SCAN_SRC)}
     roof = ff_roof if ff_ms >= scan_ms else scan_roof
 
     result = {
