@@ -176,17 +176,13 @@ ScanArgs make_scan_args(const ppm_grid *g, const ppm_probe *p, const ppm_fire *f
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Chunking of the relaxed points for the atom scatter of the backward pass.
+// Chunks of relaxed points for the atom scatter of the backward pass: tiles of
+// 8 x 8 tip columns x 2 heights (the scatter kernel's layout).
 void backward_chunks(const ppm_scan *s, int *n_blocks, int *per_block)
 {
-    const size_t n_eq = (size_t)s->nx * s->ny * s->nz;
-    size_t nb = (n_eq + 31) / 32;
-    if (nb > 4096) nb = 4096;
-    if (nb < 1) nb = 1;
-    const size_t per = (n_eq + nb - 1) / nb;
-    *per_block = (int)(per < 1 ? 1 : per);
-    *n_blocks = (int)((n_eq + *per_block - 1) / *per_block);
-    if (*n_blocks < 1) *n_blocks = 1;
+    const long long nb = (long long)((s->nx + 7) / 8) * ((s->ny + 7) / 8) * ((s->nz + 1) / 2);
+    *n_blocks = (int)(nb < 1 ? 1 : nb);
+    *per_block = 128;
 }
 
 size_t backward_record_bytes(const ppm_scan *s)

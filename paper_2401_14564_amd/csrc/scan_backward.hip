@@ -16,11 +16,12 @@
 //     ring of grad_df, gathers the eight corners of the relaxed point's cell,
 //     builds J (trilinear cell Jacobian + spring Jacobian, FP64), solves the
 //     3x3 transposed system and writes mu, the cell and its fractions.
-//  2. atom_scatter: one lane per atom, one wave per chunk of relaxed points.  The
-//     point data are wave-uniform (scalar loads); every lane evaluates its own
-//     atom's pair-force derivatives at the eight corners and accumulates in FP64
-//     registers, so no cross-lane reduction is needed.  Each block writes its
-//     per-atom partial sums.
+//  2. atom_scatter: one lane per atom, one wave per chunk of relaxed points (a
+//     tile of 8 x 8 columns x 2 heights).  The chunk's corner weights mu w_c are
+//     merged per distinct voxel in LDS (neighbouring points share corners), then
+//     every lane evaluates its own atom's pair-force derivatives once per voxel
+//     and accumulates in FP64 registers, so no cross-lane reduction is needed.
+//     Each block writes its per-atom partial sums.
 //  3. reduce: sums the partials of every (atom, component) in a fixed order and
 //     applies the per-atom constant factors -> deterministic result.
 #include "ppm_device.h"
@@ -158,157 +159,350 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
     }
 }
 
-// One wave per chunk of relaxed points; lane = atom.  QUAD: the probe carries
-// the d_z2 quadrupole q_zz, whose pair force is f = -kQ grad u with
-// u = (3 dz^2 - rho^2)/rho^5 and grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7,
-// b = 6 dz rho^-5; its derivatives are df/d(atom) = kQ hess u and
-// df/dq = -k_e q_zz grad u.  PERIODIC: minimum image and the shifted-force
-// cutoff of the force-field build: phi gains -fc/rho (fc = -dU/drho at rc of
-// the LJ + Coulomb pair), u gains Y (3 rho rc^-4 - 4 rc^-3) with
-// Y = 3 dz^2/rho^2 - 1, and pairs beyond rc drop out.
+// Points of one scatter chunk: a tile of 8 x 8 tip columns x 2 heights.
+// Neighbouring relaxed points share cell corners (adjacent columns an x or y
+// face, adjacent heights a z face), so the chunk's corner weights are first
+// merged per distinct voxel.
+constexpr int kChX = 8, kChY = 8, kChZ = 2, kChPts = kChX * kChY * kChZ;
+// Largest local box (voxels) the merge accumulates in LDS; larger chunks (a
+// probe that moved far from its neighbours, a chunk across a periodic seam)
+// take the per-point path.
+constexpr int kCellCap = 1024;
+
+// d(force of this lane's atom at v)/d(atom parameters), contracted with m:
+// d = v - r_atom (FP32), m = sum of trilinear weight x mu over the relaxed
+// points that have v as a cell corner.  Accumulates -(phi I + phi'/rho d d^T) m
+// into (ax, ay, az) and the parameter factors into aq, aR, ae, aqq (scaled
+// per atom at the end).  QUAD: the probe carries the d_z2 quadrupole q_zz,
+// whose pair force is f = -kQ grad u with u = (3 dz^2 - rho^2)/rho^5 and
+// grad u = a d + b e_z, a = 3 rho^-5 - 15 dz^2 rho^-7, b = 6 dz rho^-5; its
+// derivatives are df/d(atom) = kQ hess u and df/dq = -k_e q_zz grad u.
+// PERIODIC: minimum image and the shifted-force cutoff of the force-field
+// build: phi gains -fc/rho (fc = -dU/drho at rc of the LJ + Coulomb pair), u
+// gains Y (3 rho rc^-4 - 4 rc^-3) with Y = 3 dz^2/rho^2 - 1, and pairs beyond
+// rc drop out.
+struct AtomConsts {
+    float R2, e12, kq, kQ, rc2;
+    float fcm, irc2, aRc, aec;      // shifted-force terms (periodic)
+    float c3, c9, c18, c24;         // shifted d_z2 terms (periodic)
+};
+
 template <bool QUAD, bool PERIODIC>
-__global__ __launch_bounds__(64) void atom_scatter_kernel(
+__device__ __forceinline__ void pair_jvp(const AtomConsts &k, float dx, float dy, float dz,
+                                         float mx, float my, float mz, float &ax_, float &ay_,
+                                         float &az_, float &aq, float &aR, float &ae, float &aqq)
+{
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float ir = __builtin_amdgcn_rsqf(r2);
+    if (PERIODIC) ir = (r2 < k.rc2) ? ir : 0.0f;
+    const float ir2 = ir * ir;
+    const float ir3 = ir * ir2;
+    const float s2 = k.R2 * ir2;
+    const float s6 = s2 * s2 * s2;
+    const float s12 = s6 * s6;
+    const float ec = k.kq * ir;
+    float phi = fmaf(k.e12, s12 - s6, ec) * ir2;
+    // phi'(rho)/rho = ir2^2 [12 e (-14 s12 + 8 s6) - 3 kq/rho]
+    float dphi = fmaf(k.e12, fmaf(-14.0f, s12, 8.0f * s6), -3.0f * ec) * ir2 * ir2;
+    if (PERIODIC) {
+        phi = fmaf(-k.fcm, ir, phi);
+        dphi = fmaf(k.fcm, ir3, dphi);
+    }
+    const float md = fmaf(mx, dx, fmaf(my, dy, mz * dz));
+    const float tq = dphi * md;
+    ax_ -= fmaf(phi, mx, tq * dx);
+    ay_ -= fmaf(phi, my, tq * dy);
+    az_ -= fmaf(phi, mz, tq * dz);
+    const float im = ir2 * md;
+    if (PERIODIC) {
+        const float jm = ir * md;
+        aq = fmaf(fmaf(-k.irc2, ir, ir3), md, aq);
+        aR = fmaf(fmaf(2.0f, s12, -s6), im, fmaf(-k.aRc, jm, aR));
+        ae = fmaf(s12 - s6, im, fmaf(-k.aec, jm, ae));
+    } else {
+        aq = fmaf(ir3, md, aq);                       // x k_e q_pp
+        aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
+        ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+    }
+    if (QUAD) {
+        const float ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
+        const float z2 = dz * dz;
+        float ua = fmaf(-15.0f * z2, ir7, 3.0f * ir5);
+        float ub = 6.0f * dz * ir5;
+        // grad a . m and grad b . m
+        float ga = fmaf(fmaf(105.0f * z2, ir9, -15.0f * ir7), md, -30.0f * dz * ir7 * mz);
+        float gb = fmaf(6.0f * ir5, mz, -30.0f * dz * ir7 * md);
+        if (PERIODIC) {
+            // shifted d_z2 term: grad u gains ax d + bx e_z with
+            // ax = -9 rc^-4 dz^2 rho^-3 + 24 rc^-3 dz^2 rho^-4 - 3 rc^-4 rho^-1,
+            // bx = 18 rc^-4 dz rho^-1 - 24 rc^-3 dz rho^-2
+            const float ir4 = ir2 * ir2, ir6 = ir4 * ir2;
+            ua += fmaf(z2, fmaf(k.c24, ir4, -k.c9 * ir3), -k.c3 * ir);
+            ub += dz * fmaf(k.c18, ir, -k.c24 * ir2);
+            ga += fmaf(-k.c9, fmaf(2.0f * dz * ir3, mz, -3.0f * z2 * ir5 * md),
+                       fmaf(k.c24, fmaf(2.0f * dz * ir4, mz, -4.0f * z2 * ir6 * md),
+                            k.c3 * ir3 * md));
+            gb += fmaf(k.c18, fmaf(ir, mz, -dz * ir3 * md),
+                       -k.c24 * fmaf(ir2, mz, -2.0f * dz * ir4 * md));
+        }
+        ax_ = fmaf(k.kQ, fmaf(ua, mx, dx * ga), ax_);
+        ay_ = fmaf(k.kQ, fmaf(ua, my, dy * ga), ay_);
+        az_ = fmaf(k.kQ, fmaf(ua, mz, fmaf(dz, ga, gb)), az_);
+        aqq = fmaf(ua, md, fmaf(ub, mz, aqq));    // x -k_e q_zz
+    }
+}
+
+// Displacement component v - r_atom along a periodic or open axis, FP64, then FP32.
+template <bool PERIODIC>
+__device__ __forceinline__ float axis_disp(double v, double p, double L)
+{
+    double d = v - p;
+    if (PERIODIC) d -= L * rint(d / L);
+    return (float)d;
+}
+
+// One block of four waves per (chunk, block of 64 atoms); lane = atom, the
+// same 64 atoms in every wave.  Wave 0 stages the chunk's records and merges
+// their corner weights per voxel in LDS (in a fixed order, so the result is
+// deterministic); the four waves then split the distinct voxels, every lane
+// evaluating its atom's pair-force derivatives once per voxel (FP32 per batch of
+// eight voxels, then FP64), and wave 0 adds the four waves' sums in order.
+constexpr int kScatterWaves = 4;
+
+template <bool QUAD, bool PERIODIC>
+__global__ __launch_bounds__(64 * kScatterWaves) void atom_scatter_kernel(
     const BwdArgs A, const EqRecord *__restrict__ rec, const double *__restrict__ pos,
     const double *__restrict__ q, const double *__restrict__ R, const double *__restrict__ eps,
     double *__restrict__ partial)
 {
+    __shared__ float s_m[3][kCellCap];
+    __shared__ float4 s_u[kCellCap];          // merged voxels: (m, packed local x, y, z)
+    __shared__ EqRecord s_rec[kChPts];
+    __shared__ int s_box[8];                  // lo[3], bx, by, bz, n, flags
     const ScanArgs &a = A.s;
-    const int atom = blockIdx.y * 64 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int atom = blockIdx.y * 64 + lane;
     const bool live = atom < A.n_atoms;
     const int ia = live ? atom : 0;
     const double px = pos[3 * ia], py = pos[3 * ia + 1], pz = pos[3 * ia + 2];
     const double RiP = R[ia] + A.R_pp;
-    const float R2 = (float)(RiP * RiP);
     const double eiP = sqrt(eps[ia] * A.eps_pp);
-    const float e12 = (float)(12.0 * eiP);
-    const float kq = (float)(A.kq_pp * q[ia]);
-    const float kQ = (float)(A.kQ_pp * q[ia]);
-    // shifted-force constants of this atom (periodic): fc, and the rc-terms of
-    // d phi / d(R_iP, e_iP, kq) per 1/rho
-    float fcm = 0.f, irc2 = 0.f, aRc = 0.f, aec = 0.f;
-    float c3 = 0.f, c9 = 0.f, c18 = 0.f, c24 = 0.f;
+    AtomConsts k;
+    k.R2 = (float)(RiP * RiP);
+    k.e12 = (float)(12.0 * eiP);
+    k.kq = (float)(A.kq_pp * q[ia]);
+    k.kQ = (float)(A.kQ_pp * q[ia]);
+    k.rc2 = A.rc2;
+    k.fcm = k.irc2 = k.aRc = k.aec = k.c3 = k.c9 = k.c18 = k.c24 = 0.f;
     if (PERIODIC) {
         const double irc = 1.0 / A.rc;
         const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2, sc12 = sc6 * sc6;
-        fcm = (float)(12.0 * eiP * (sc12 - sc6) * irc + A.kq_pp * q[ia] * irc * irc);
-        irc2 = (float)(irc * irc);
-        aRc = (float)((2.0 * sc12 - sc6) * irc);
-        aec = (float)((sc12 - sc6) * irc);
+        k.fcm = (float)(12.0 * eiP * (sc12 - sc6) * irc + A.kq_pp * q[ia] * irc * irc);
+        k.irc2 = (float)(irc * irc);
+        k.aRc = (float)((2.0 * sc12 - sc6) * irc);
+        k.aec = (float)((sc12 - sc6) * irc);
         const double irc3 = irc * irc * irc, irc4 = irc3 * irc;
-        c3 = (float)(3.0 * irc4);
-        c9 = (float)(9.0 * irc4);
-        c18 = (float)(18.0 * irc4);
-        c24 = (float)(24.0 * irc3);
+        k.c3 = (float)(3.0 * irc4);
+        k.c9 = (float)(9.0 * irc4);
+        k.c18 = (float)(18.0 * irc4);
+        k.c24 = (float)(24.0 * irc3);
     }
 
-    double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0, gqq = 0.0;
-    const size_t n_eq = (size_t)a.snx * a.sny * a.snz;
-    const size_t e0 = (size_t)blockIdx.x * A.eq_per_block;
-    const size_t e1 = min(n_eq, e0 + (size_t)A.eq_per_block);
-    for (size_t e = e0; e < e1; ++e) {
-        const EqRecord r = rec[e];
-        if (r.mu_v.w == 0.0f) continue;
-        // corner coordinates relative to the atom (FP64 difference, then FP32)
-        const int cx1 = (r.idx.x + 1 < a.gnx) ? r.idx.x + 1 : 0;
-        const int cy1 = (r.idx.y + 1 < a.gny) ? r.idx.y + 1 : 0;
-        double ddx0 = a.ox + r.idx.x * A.hx - px, ddx1 = a.ox + cx1 * A.hx - px;
-        double ddy0 = a.oy + r.idx.y * A.hy - py, ddy1 = a.oy + cy1 * A.hy - py;
-        if (PERIODIC) {
-            ddx0 -= A.Lx * rint(ddx0 / A.Lx);
-            ddx1 -= A.Lx * rint(ddx1 / A.Lx);
-            ddy0 -= A.Ly * rint(ddy0 / A.Ly);
-            ddy1 -= A.Ly * rint(ddy1 / A.Ly);
-        }
-        const float dxs[2] = {(float)ddx0, (float)ddx1};
-        const float dys[2] = {(float)ddy0, (float)ddy1};
-        const float dzs[2] = {(float)(a.oz + r.idx.z * A.hz - pz),
-                              (float)(a.oz + (r.idx.z + 1) * A.hz - pz)};
-        const float tx = r.t.x, ty = r.t.y, tz = r.t.z;
-        const float wx[2] = {1.0f - tx, tx}, wy[2] = {1.0f - ty, ty}, wz[2] = {1.0f - tz, tz};
-        float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f, aqq = 0.f;
+    // the chunk: tip columns (cx0 .. cx0+7, cy0 .. cy0+7), heights s0, s0+1
+    const int ntx = (a.snx + kChX - 1) / kChX, nty = (a.sny + kChY - 1) / kChY;
+    const int chunk = blockIdx.x;
+    const int tzi = chunk / (ntx * nty), rest = chunk - tzi * ntx * nty;
+    const int cx0 = (rest % ntx) * kChX, cy0 = (rest / ntx) * kChY, s0 = tzi * kChZ;
+    const size_t plane = (size_t)a.snx * a.sny;
+
+    if (wv == 0) {
+        // stage the chunk's records (invalid or outside the lattice: mu_v.w = 0)
+        // and reduce the local box of its valid cells (base corners)
+        int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+        int hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            const int i = cc & 1, j = (cc >> 1) & 1, k = cc >> 2;
-            const float w = wx[i] * wy[j] * wz[k];
-            const float mx = w * r.mu_v.x, my = w * r.mu_v.y, mz = w * r.mu_v.z;
-            const float dx = dxs[i], dy = dys[j], dz = dzs[k];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            float ir = __builtin_amdgcn_rsqf(r2);
-            if (PERIODIC) ir = (r2 < A.rc2) ? ir : 0.0f;
-            const float ir2 = ir * ir;
-            const float ir3 = ir * ir2;
-            const float s2 = R2 * ir2;
-            const float s6 = s2 * s2 * s2;
-            const float s12 = s6 * s6;
-            const float ec = kq * ir;
-            float phi = fmaf(e12, s12 - s6, ec) * ir2;
-            // phi'(rho)/rho = ir2^2 [12 e (-14 s12 + 8 s6) - 3 kq/rho]
-            float dphi = fmaf(e12, fmaf(-14.0f, s12, 8.0f * s6), -3.0f * ec) * ir2 * ir2;
-            if (PERIODIC) {
-                phi = fmaf(-fcm, ir, phi);
-                dphi = fmaf(fcm, ir3, dphi);
-            }
-            const float md = fmaf(mx, dx, fmaf(my, dy, mz * dz));
-            const float tq = dphi * md;
-            ax_ -= fmaf(phi, mx, tq * dx);
-            ay_ -= fmaf(phi, my, tq * dy);
-            az_ -= fmaf(phi, mz, tq * dz);
-            const float im = ir2 * md;
-            if (PERIODIC) {
-                const float jm = ir * md;
-                aq = fmaf(fmaf(-irc2, ir, ir3), md, aq);
-                aR = fmaf(fmaf(2.0f, s12, -s6), im, fmaf(-aRc, jm, aR));
-                ae = fmaf(s12 - s6, im, fmaf(-aec, jm, ae));
+        for (int r = 0; r < kChPts / 64; ++r) {
+            const int pnt = r * 64 + lane;
+            const int ix = cx0 + (pnt % kChX), iy = cy0 + ((pnt / kChX) % kChY);
+            const int sh = s0 + pnt / (kChX * kChY);
+            EqRecord e;
+            if (ix < a.snx && iy < a.sny && sh < a.snz) {
+                e = rec[(size_t)sh * plane + (size_t)iy * a.snx + ix];
             } else {
-                aq = fmaf(ir3, md, aq);                       // x k_e q_pp
-                aR = fmaf(fmaf(2.0f, s12, -s6), im, aR);      // x 72 e_iP / R_iP
-                ae = fmaf(s12 - s6, im, ae);                  // x 12 de_iP/de_i
+                e.mu_v = make_float4(0.f, 0.f, 0.f, 0.f);
+                e.t = e.mu_v;
+                e.idx = make_int4(0, 0, 0, 0);
             }
-            if (QUAD) {
-                const float ir5 = ir3 * ir2, ir7 = ir5 * ir2, ir9 = ir7 * ir2;
-                const float z2 = dz * dz;
-                float ua = fmaf(-15.0f * z2, ir7, 3.0f * ir5);
-                float ub = 6.0f * dz * ir5;
-                // grad a . m and grad b . m
-                float ga = fmaf(fmaf(105.0f * z2, ir9, -15.0f * ir7), md,
-                                -30.0f * dz * ir7 * mz);
-                float gb = fmaf(6.0f * ir5, mz, -30.0f * dz * ir7 * md);
-                if (PERIODIC) {
-                    // shifted d_z2 term: grad u gains ax d + bx e_z with
-                    // ax = -9 rc^-4 dz^2 rho^-3 + 24 rc^-3 dz^2 rho^-4 - 3 rc^-4 rho^-1,
-                    // bx = 18 rc^-4 dz rho^-1 - 24 rc^-3 dz rho^-2
-                    const float ir4 = ir2 * ir2, ir6 = ir4 * ir2;
-                    ua += fmaf(z2, fmaf(c24, ir4, -c9 * ir3), -c3 * ir);
-                    ub += dz * fmaf(c18, ir, -c24 * ir2);
-                    ga += fmaf(-c9, fmaf(2.0f * dz * ir3, mz, -3.0f * z2 * ir5 * md),
-                               fmaf(c24, fmaf(2.0f * dz * ir4, mz, -4.0f * z2 * ir6 * md),
-                                    c3 * ir3 * md));
-                    gb += fmaf(c18, fmaf(ir, mz, -dz * ir3 * md),
-                               -c24 * fmaf(ir2, mz, -2.0f * dz * ir4 * md));
-                }
-                ax_ = fmaf(kQ, fmaf(ua, mx, dx * ga), ax_);
-                ay_ = fmaf(kQ, fmaf(ua, my, dy * ga), ay_);
-                az_ = fmaf(kQ, fmaf(ua, mz, fmaf(dz, ga, gb)), az_);
-                aqq = fmaf(ua, md, fmaf(ub, mz, aqq));    // x -k_e q_zz
+            s_rec[pnt] = e;
+            if (e.mu_v.w != 0.0f) {
+                lo[0] = min(lo[0], e.idx.x); lo[1] = min(lo[1], e.idx.y);
+                lo[2] = min(lo[2], e.idx.z);
+                hi[0] = max(hi[0], e.idx.x); hi[1] = max(hi[1], e.idx.y);
+                hi[2] = max(hi[2], e.idx.z);
             }
         }
-        gx += ax_;
-        gy += ay_;
-        gz += az_;
-        gq += aq;
-        gR += aR;
-        ge += ae;
-        gqq += aqq;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = min(lo[d], __shfl_xor(lo[d], off));
+                hi[d] = max(hi[d], __shfl_xor(hi[d], off));
+            }
+        const bool any = lo[0] <= hi[0];
+        const int bx = hi[0] - lo[0] + 2, by = hi[1] - lo[1] + 2, bz = hi[2] - lo[2] + 2;
+        const bool merge = any && (long long)bx * by * bz <= kCellCap;
+        int n = 0;
+        if (merge) {
+            const int nc = bx * by * bz;
+            for (int c = lane; c < nc; c += 64) s_m[0][c] = s_m[1][c] = s_m[2][c] = 0.0f;
+            // merge: points in a fixed order, the eight corners of a point on lanes
+            // 0-7 (distinct voxels, so no two lanes of one step touch the same cell;
+            // a wave's LDS operations complete in order, so a step sees the sums of
+            // the steps before it)
+            const int ci = lane & 1, cj = (lane >> 1) & 1, ck = (lane >> 2) & 1;
+            for (int pnt = 0; pnt < kChPts; ++pnt) {
+                const EqRecord r = s_rec[pnt];
+                if (r.mu_v.w == 0.0f) continue;
+                if (lane < 8) {
+                    const float w = (ci ? r.t.x : 1.0f - r.t.x) * (cj ? r.t.y : 1.0f - r.t.y) *
+                                    (ck ? r.t.z : 1.0f - r.t.z);
+                    const int c = ((r.idx.z + ck - lo[2]) * by + (r.idx.y + cj - lo[1])) * bx +
+                                  (r.idx.x + ci - lo[0]);
+                    s_m[0][c] += w * r.mu_v.x;
+                    s_m[1][c] += w * r.mu_v.y;
+                    s_m[2][c] += w * r.mu_v.z;
+                }
+            }
+            // the voxels that received weight, in cell order: (m, packed local x, y, z)
+            int lx = lane % bx, ly = (lane / bx) % by, lz = lane / (bx * by);
+            const int sx = 64 % bx, sy = (64 / bx) % by, sz = 64 / (bx * by);
+            for (int c0 = 0; c0 < nc; c0 += 64) {
+                const int c = c0 + lane;
+                float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (c < nc) m = make_float4(s_m[0][c], s_m[1][c], s_m[2][c], 0.f);
+                const bool hit = m.x != 0.0f || m.y != 0.0f || m.z != 0.0f;
+                const unsigned long long bal = __ballot(hit);
+                if (hit) {
+                    m.w = __uint_as_float((uint32_t)lx | ((uint32_t)ly << 10) |
+                                          ((uint32_t)lz << 20));
+                    s_u[n + __popcll(bal & ((1ull << lane) - 1ull))] = m;
+                }
+                n += __popcll(bal);
+                lx += sx;
+                const int cxr = lx >= bx;
+                lx -= cxr ? bx : 0;
+                ly += sy + cxr;
+                const int cyr = ly >= by;
+                ly -= cyr ? by : 0;
+                lz += sz + cyr;
+            }
+        }
+        if (lane == 0) {
+            s_box[0] = lo[0]; s_box[1] = lo[1]; s_box[2] = lo[2];
+            s_box[3] = bx; s_box[4] = by; s_box[5] = bz;
+            s_box[6] = n;
+            s_box[7] = (any ? 1 : 0) | (merge ? 2 : 0);
+        }
     }
-    if (live) {
-        const int na_pad = gridDim.y * 64;
-        double *out = partial + ((size_t)blockIdx.x * na_pad + atom) * 6;
-        out[0] = gx;
-        out[1] = gy;
-        out[2] = gz;
-        out[3] = gq * A.ke_qpp - (QUAD ? gqq * A.kQ_pp : 0.0);
-        out[4] = gR * 72.0 * eiP / RiP;
-        out[5] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
+    __syncthreads();
+    const int flags = s_box[7];
+    double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0, gR = 0.0, ge = 0.0, gqq = 0.0;
+    if (flags & 2) {
+        const int n = s_box[6];
+        // the box corner relative to the atom, FP64 then FP32 (minimum image on a
+        // periodic grid); a voxel's offset is then one FP32 multiply-add per axis
+        // (plus the wrap, the box being at most 1023 voxels wide)
+        const float bdx = axis_disp<PERIODIC>(a.ox + s_box[0] * A.hx, px, A.Lx);
+        const float bdy = axis_disp<PERIODIC>(a.oy + s_box[1] * A.hy, py, A.Ly);
+        const float bdz = (float)(a.oz + s_box[2] * A.hz - pz);
+        const float hxf = (float)A.hx, hyf = (float)A.hy, hzf = (float)A.hz;
+        const float Lxf = (float)A.Lx, Lyf = (float)A.Ly;
+        const float iLxf = PERIODIC ? (float)(1.0 / A.Lx) : 0.f;
+        const float iLyf = PERIODIC ? (float)(1.0 / A.Ly) : 0.f;
+        // wave wv takes the voxels [n wv / 4, n (wv+1) / 4)
+        const int ub = (n * wv) / kScatterWaves, ue = (n * (wv + 1)) / kScatterWaves;
+        for (int u0 = ub; u0 < ue; u0 += 8) {
+            float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f, aqq = 0.f;
+            const int u1 = min(ue, u0 + 8);
+            for (int u = u0; u < u1; ++u) {
+                const float4 e = s_u[u];
+                const uint32_t pk = __float_as_uint(e.w);
+                float dx = fmaf((float)(pk & 1023u), hxf, bdx);
+                float dy = fmaf((float)((pk >> 10) & 1023u), hyf, bdy);
+                const float dz = fmaf((float)(pk >> 20), hzf, bdz);
+                if (PERIODIC) {
+                    dx = fmaf(-Lxf, rintf(dx * iLxf), dx);
+                    dy = fmaf(-Lyf, rintf(dy * iLyf), dy);
+                }
+                pair_jvp<QUAD, PERIODIC>(k, dx, dy, dz, e.x, e.y, e.z, ax_, ay_, az_, aq, aR,
+                                         ae, aqq);
+            }
+            gx += ax_;
+            gy += ay_;
+            gz += az_;
+            gq += aq;
+            gR += aR;
+            ge += ae;
+            gqq += aqq;
+        }
+    } else if (flags & 1) {
+        // per point (wave wv: points wv, wv + 4, ...): the eight corners of its cell
+        for (int pnt = wv; pnt < kChPts; pnt += kScatterWaves) {
+            const EqRecord r = s_rec[pnt];
+            if (r.mu_v.w == 0.0f) continue;
+            const int cx1 = (r.idx.x + 1 < a.gnx) ? r.idx.x + 1 : 0;
+            const int cy1 = (r.idx.y + 1 < a.gny) ? r.idx.y + 1 : 0;
+            const float dxs[2] = {axis_disp<PERIODIC>(a.ox + r.idx.x * A.hx, px, A.Lx),
+                                  axis_disp<PERIODIC>(a.ox + cx1 * A.hx, px, A.Lx)};
+            const float dys[2] = {axis_disp<PERIODIC>(a.oy + r.idx.y * A.hy, py, A.Ly),
+                                  axis_disp<PERIODIC>(a.oy + cy1 * A.hy, py, A.Ly)};
+            const float dzs[2] = {(float)(a.oz + r.idx.z * A.hz - pz),
+                                  (float)(a.oz + (r.idx.z + 1) * A.hz - pz)};
+            const float tx = r.t.x, ty = r.t.y, tz = r.t.z;
+            const float wx[2] = {1.0f - tx, tx}, wy[2] = {1.0f - ty, ty}, wz[2] = {1.0f - tz, tz};
+            float ax_ = 0.f, ay_ = 0.f, az_ = 0.f, aq = 0.f, aR = 0.f, ae = 0.f, aqq = 0.f;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const int i = cc & 1, j = (cc >> 1) & 1, kk = cc >> 2;
+                const float w = wx[i] * wy[j] * wz[kk];
+                pair_jvp<QUAD, PERIODIC>(k, dxs[i], dys[j], dzs[kk], w * r.mu_v.x,
+                                         w * r.mu_v.y, w * r.mu_v.z, ax_, ay_, az_, aq, aR, ae,
+                                         aqq);
+            }
+            gx += ax_;
+            gy += ay_;
+            gz += az_;
+            gq += aq;
+            gR += aR;
+            ge += ae;
+            gqq += aqq;
+        }
+    }
+    // the four waves' sums, added by wave 0 in wave order (s_u is free again)
+    __syncthreads();
+    double *s_red = reinterpret_cast<double *>(s_u);          // [wave][7][64]
+    if (wv > 0) {
+        double *o = s_red + (size_t)(wv - 1) * 7 * 64 + lane;
+        o[0] = gx; o[64] = gy; o[128] = gz; o[192] = gq; o[256] = gR; o[320] = ge;
+        o[384] = gqq;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        for (int w = 0; w < kScatterWaves - 1; ++w) {
+            const double *o = s_red + (size_t)w * 7 * 64 + lane;
+            gx += o[0]; gy += o[64]; gz += o[128]; gq += o[192]; gR += o[256]; ge += o[320];
+            gqq += o[384];
+        }
+        if (live) {
+            const int na_pad = gridDim.y * 64;
+            double *out = partial + ((size_t)blockIdx.x * na_pad + atom) * 6;
+            out[0] = gx;
+            out[1] = gy;
+            out[2] = gz;
+            out[3] = gq * A.ke_qpp - (QUAD ? gqq * A.kQ_pp : 0.0);
+            out[4] = gR * 72.0 * eiP / RiP;
+            out[5] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
+        }
     }
 }
 
@@ -379,20 +573,21 @@ hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *f
     if (A.n_atoms == 0) return hipSuccess;
     const int na_blocks = (A.n_atoms + 63) / 64;
     dim3 g2(A.n_eq_blocks, na_blocks, 1);
+    const dim3 sblk(64 * kScatterWaves, 1, 1);
     if (A.kQ_pp != 0.0) {
         if (A.periodic)
-            hipLaunchKernelGGL((atom_scatter_kernel<true, true>), g2, dim3(64, 1, 1), 0, stream,
-                               A, rec, pos, q, R, eps, partial_ws);
+            hipLaunchKernelGGL((atom_scatter_kernel<true, true>), g2, sblk, 0, stream, A, rec, pos,
+                               q, R, eps, partial_ws);
         else
-            hipLaunchKernelGGL((atom_scatter_kernel<true, false>), g2, dim3(64, 1, 1), 0, stream,
-                               A, rec, pos, q, R, eps, partial_ws);
+            hipLaunchKernelGGL((atom_scatter_kernel<true, false>), g2, sblk, 0, stream, A, rec,
+                               pos, q, R, eps, partial_ws);
     } else {
         if (A.periodic)
-            hipLaunchKernelGGL((atom_scatter_kernel<false, true>), g2, dim3(64, 1, 1), 0, stream,
-                               A, rec, pos, q, R, eps, partial_ws);
+            hipLaunchKernelGGL((atom_scatter_kernel<false, true>), g2, sblk, 0, stream, A, rec,
+                               pos, q, R, eps, partial_ws);
         else
-            hipLaunchKernelGGL((atom_scatter_kernel<false, false>), g2, dim3(64, 1, 1), 0, stream,
-                               A, rec, pos, q, R, eps, partial_ws);
+            hipLaunchKernelGGL((atom_scatter_kernel<false, false>), g2, sblk, 0, stream, A, rec,
+                               pos, q, R, eps, partial_ws);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
