@@ -438,7 +438,7 @@ def main():
         torch.cuda.empty_cache()
         result["paper_scale"] = _bench_paper_scale(ppm, W, torch, a)
         result["backward"] = _bench_backward(ppm, W, torch)
-        result["batched"] = _bench_batch(ppm, W, torch)
+        result["batched"] = _bench_batch(ppm, W, torch, mb=mb)
         result["next_rows"] = _bench_next_rows(ppm, W, torch)
 
     if not a.no_cpu:
@@ -573,7 +573,7 @@ def _bench_backward(ppm, W, torch):
             "bwd_over_fwd": round(bwd_ms / fwd_ms, 4)}
 
 
-def _bench_batch(ppm, W, torch, n_mol=256):
+def _bench_batch(ppm, W, torch, n_mol=256, mb=None):
     """Frequency-shift stacks per second for 256 molecules x 3 lateral
     stiffnesses: one captured HIP graph (batched force-field launch + batched
     scan launch) against a plain per-molecule loop of build_ff + 3 scans on one
@@ -665,6 +665,20 @@ def _bench_batch(ppm, W, torch, n_mol=256):
     plain_graph_ms = float(np.median(tg))
     same_graph = all(torch.equal(bp.df_stack(j), outs[j]) for j in range(len(jobs)))
     del pg
+    # FIRE evaluations of the batched scan, from the single scans (same bits) of
+    # every 16th job with the probe state kept
+    evals = pts = 0.0
+    for j in range(0, len(jobs), 16):
+        mi, pr, sc = jobs[j]
+        r = ppm.relaxed_scan(ws[mi].grid, bp.ff_grid(mi), pr, ws[mi].fire, sc, fz=False, pp=True)
+        it = r["pp"][..., 3]
+        evals += float(it.abs().sum().item()) + sc.n_eq
+        pts += sc.n_eq
+    total_pts = float(sum(sc.n_eq for (_, _, sc) in jobs))
+    scan_bytes = evals / pts * total_pts * BYTES_PER_EVAL
+    scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
+    gather_ceiling = (mb["gather_coherent_gbs"] * BYTES_PER_EVAL / MB_BYTES_PER_GATHER
+                      if mb else None)
     voxels = sum(w.grid.nvox for w in ws)
     pairs = sum(w.grid.nvox * w.atoms.n for w in ws)
     return {"workload": f"{n_mol} seeded molecules, 10-120 atoms, cells with 5 A margins at "
@@ -684,6 +698,12 @@ def _bench_batch(ppm, W, torch, n_mol=256):
                                 "speedup_vs_plain_graph: the same loop replayed as one graph",
             "batched_stage_ms": {"ff_build": round(ff_ms, 3), "scan": round(scan_ms, 3)},
             "batched_ff_tflops": round(pairs * FLOP_PER_PAIR / (ff_ms * 1e-3) / 1e12, 2),
+            "batched_scan": {"fire_evals_per_point": round(evals / pts, 3),
+                             "evals_sample": f"single scans of {len(range(0, len(jobs), 16))} "
+                                             "of the jobs (every 16th)",
+                             "gather_gbs": round(scan_gbs, 1),
+                             "frac_of_measured_gather_ceiling":
+                                 round(scan_gbs / gather_ceiling, 4) if gather_ceiling else None},
             "launch_shapes": {"ff_voxels_per_thread": bp.ff_nzb,
                               "ff_autotuner_ms": bp.tuning_ms,
                               "batched_scan_tile": "8x8",
