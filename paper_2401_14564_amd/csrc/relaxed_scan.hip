@@ -368,19 +368,23 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
             g2 = Gx * Gx + Gy * Gy + Gz * Gz;
             const bool conv = g2 < a.f_conv2;
             done = conv || it >= a.max_iter;
-            if (done) {
-                // record this height (stores only)
+            {
+                // record this height.  The LDS slots of the current height are
+                // written on every iteration (the last write, at convergence,
+                // is the one that stays), so no branch is needed.
                 const float fzv = (float)(-Tz);
                 const size_t o = (size_t)k * plane + col;
                 if (STAGE) s_col[k * NL + lane] = fzv;
-                else if (fz_out) fz_out[o] = fzv;
+                else if (fz_out && done) fz_out[o] = fzv;
                 if (PROG)
-                    __hip_atomic_store(s_prog + lane, k + 1, __ATOMIC_RELAXED,
+                    __hip_atomic_store(s_prog + lane, done ? k + 1 : k, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (pp_out)
-                    pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
-                                            (float)(rz - az - a.d0z),
-                                            conv ? (float)it : -(float)it);
+                if (pp_out) {
+                    if (done)
+                        pp_out[o] = make_float4((float)(rx - ax - a.d0x), (float)(ry - ay - a.d0y),
+                                                (float)(rz - az - a.d0z),
+                                                conv ? (float)it : -(float)it);
+                }
             }
         }
         if (done && k + 1 >= a.snz) break;
@@ -402,8 +406,15 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         double fvz = om * vz + sc * Gz;
         const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
         const bool grow = pos && fnpos > a.n_min;
-        const double fdt = grow ? fmin(dt * a.f_inc, a.dt_max) : (neg ? dt * a.f_dec : dt);
-        const double falpha = grow ? alpha * a.f_alpha : (neg ? a.alpha0 : alpha);
+        // The empty asm statements pin the alternatives of each select into the
+        // straight-line code: left alone, the compiler sinks them into
+        // exec-masked branches, and on a single wave per SIMD the branch and
+        // mask bookkeeping costs more than the selects (measured 2-6% of the
+        // scan).  They change no value.
+        double dtg = fmin(dt * a.f_inc, a.dt_max), dtn = dt * a.f_dec, alg = alpha * a.f_alpha;
+        asm volatile("" : "+v"(dtg), "+v"(dtn), "+v"(alg));
+        const double fdt = grow ? dtg : (neg ? dtn : dt);
+        const double falpha = grow ? alg : (neg ? a.alpha0 : alpha);
         const double h = fdt * a.inv_mass;
         fvx += Gx * h;
         fvy += Gy * h;
@@ -422,13 +433,18 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         const double azn = a.z_top - kn * a.sdz;
 
         // merge
-        rx = done ? ax + (ux + ex) : frx;
-        ry = done ? ay + (uy + ey) : fry;
-        rz = done ? azn + (uz + ez) : frz;
+        double nrx = ax + (ux + ex), nry = ay + (uy + ey), nrz = azn + (uz + ez);
+        double ndt = fmax(dt, a.dt0);
+        double frx_ = frx, fry_ = fry, frz_ = frz;
+        asm volatile("" : "+v"(nrx), "+v"(nry), "+v"(nrz), "+v"(ndt), "+v"(frx_), "+v"(fry_),
+                     "+v"(frz_));
+        rx = done ? nrx : frx_;
+        ry = done ? nry : fry_;
+        rz = done ? nrz : frz_;
         vx = done ? 0.0 : fvx;
         vy = done ? 0.0 : fvy;
         vz = done ? 0.0 : fvz;
-        dt = done ? fmax(dt, a.dt0) : fdt;
+        dt = done ? ndt : fdt;
         alpha = done ? a.alpha0 : falpha;
         npos = done ? 0 : fnpos;
         it = done ? 0 : it + 1;
