@@ -97,8 +97,9 @@ def _scan_kernel(tuning, periodic):
 def kernels_once():
     """For rocprofv3 --pmc: a 1 GiB copy (counter calibration), then the
     autotuner and one launch of the force-field build and of the scan with its
-    choice (as the timed steps run them) on the large periodic workload, and
-    one of each at the default shapes on the paper-scale workload."""
+    choice (as the timed steps run them) on the large periodic workload, one of
+    each at the default shapes on the paper-scale workload, and one forward and
+    backward on the differentiation workload."""
     import torch
     import paper_2401_14564_amd as ppm
     from paper_2401_14564_amd import workloads as W
@@ -124,6 +125,22 @@ def kernels_once():
         torch.cuda.synchronize()
         print(w.name, "shapes", t, flush=True)
         del ff
+    # one backward on the differentiation workload (loss ||df - df_target||^2)
+    w, target = W.config4()
+    atoms = ppm.atoms_to_device(w.atoms)
+    # (its forward at other launch shapes than the paper-scale launches above,
+    # so that every kernel name in the counter tables covers one workload)
+    t4 = ppm.Tuning(6, 8)
+    ff = ppm.build_ff(w.grid, w.probe, target, tuning=t4)
+    df_t = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+                            tuning=t4)["df"].clone()
+    ppm.build_ff(w.grid, w.probe, atoms, out=ff, tuning=t4)
+    res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, tuning=t4)
+    torch.cuda.synchronize()
+    ppm.relaxed_scan_backward(w.grid, ff, w.probe, w.scan, w.df, atoms, res["pp"],
+                              2.0 * (res["df"] - df_t))
+    torch.cuda.synchronize()
+    print(w.name, "backward", flush=True)
     print("kernels-once done", flush=True)
 
 
@@ -144,9 +161,14 @@ def _read_pmc(folder, counter):
     return rows
 
 
+# the library's kernels in rocprofv3 kernel names (template arguments kept)
+KERNEL_NAME_RE = (r"((ff_build_kernel|relaxed_scan_kernel|atom_scatter_kernel|"
+                  r"adjoint_solve_kernel)<[^>]*>|reduce_kernel)")
+
+
 def summarize_pmc(fetch_dir, write_dir):
-    """profiles/traffic.json: HBM bytes per launch of every force-field and scan
-    kernel in the two counter runs, scaled by what the counters read for the
+    """profiles/traffic.json: HBM bytes per launch of every force-field, scan and
+    backward kernel in the two counter runs, scaled by what the counters read for the
     known copy, with the hashes of the sources they were taken on."""
     import re
     out = {"calibration": f"torch copy of {CALIB_BYTES} bytes (reads and writes that many)",
@@ -160,7 +182,7 @@ def summarize_pmc(fetch_dir, write_dir):
         out[f"{counter}_copy_reading_kib"] = calib_kib
         out[f"{counter}_scale"] = factor
         for k, vs in rows.items():
-            m = re.search(r"((ff_build_kernel|relaxed_scan_kernel)<[^>]*>)", k)
+            m = re.search(KERNEL_NAME_RE, k)
             if not m:
                 continue
             e = out["kernels"].setdefault(m.group(1), {"dispatches": len(vs)})
@@ -182,7 +204,8 @@ def summarize_pmc(fetch_dir, write_dir):
 
 def summarize_counters(folders):
     """Markdown table of the mean per-dispatch value of every counter in the
-    given rocprofv3 --pmc output folders, for the force-field and scan kernels."""
+    given rocprofv3 --pmc output folders, for the force-field, scan and
+    backward kernels."""
     import csv
     import glob
     import re
@@ -191,8 +214,7 @@ def summarize_counters(folders):
         for fn in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
             with open(fn) as f:
                 for r in csv.DictReader(f):
-                    m = re.search(r"((ff_build_kernel|relaxed_scan_kernel)<[^>]*>)",
-                                  r["Kernel_Name"])
+                    m = re.search(KERNEL_NAME_RE, r["Kernel_Name"])
                     if not m:
                         continue
                     table.setdefault(m.group(1), {}).setdefault(r["Counter_Name"], []).append(

@@ -278,6 +278,7 @@ __global__ __launch_bounds__(64 * kScatterWaves) void atom_scatter_kernel(
     __shared__ float s_m[3][kCellCap];
     __shared__ float4 s_u[kCellCap];          // merged voxels: (m, packed local x, y, z)
     __shared__ EqRecord s_rec[kChPts];
+    __shared__ int s_tag[kCellCap];           // merge: last lane to hit a voxel
     __shared__ int s_box[8];                  // lo[3], bx, by, bz, n, flags
     const ScanArgs &a = A.s;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -355,22 +356,48 @@ __global__ __launch_bounds__(64 * kScatterWaves) void atom_scatter_kernel(
         if (merge) {
             const int nc = bx * by * bz;
             for (int c = lane; c < nc; c += 64) s_m[0][c] = s_m[1][c] = s_m[2][c] = 0.0f;
-            // merge: points in a fixed order, the eight corners of a point on lanes
-            // 0-7 (distinct voxels, so no two lanes of one step touch the same cell;
-            // a wave's LDS operations complete in order, so a step sees the sums of
-            // the steps before it)
+            // merge, in 16 groups of eight points taken in a fixed order: lane
+            // 8 p + c holds corner c of the group's point p.  A group's points lie
+            // at least two columns apart, so their cells rarely share a voxel; the
+            // lanes tag the voxels they hit (a wave's LDS operations complete in
+            // order) and, when no two lanes of the group hit the same voxel, the
+            // group adds its 64 weights in one step, else point by point.  Each
+            // voxel therefore sums its weights in a fixed order (deterministic).
+            static_assert(kChX == 8 && kChY == 8 && kChZ == 2, "merge groups of an 8x8x2 chunk");
             const int ci = lane & 1, cj = (lane >> 1) & 1, ck = (lane >> 2) & 1;
-            for (int pnt = 0; pnt < kChPts; ++pnt) {
-                const EqRecord r = s_rec[pnt];
-                if (r.mu_v.w == 0.0f) continue;
-                if (lane < 8) {
-                    const float w = (ci ? r.t.x : 1.0f - r.t.x) * (cj ? r.t.y : 1.0f - r.t.y) *
-                                    (ck ? r.t.z : 1.0f - r.t.z);
-                    const int c = ((r.idx.z + ck - lo[2]) * by + (r.idx.y + cj - lo[1])) * bx +
-                                  (r.idx.x + ci - lo[0]);
-                    s_m[0][c] += w * r.mu_v.x;
-                    s_m[1][c] += w * r.mu_v.y;
-                    s_m[2][c] += w * r.mu_v.z;
+            const int gp = lane >> 3;
+            for (int g = 0; g < 16; ++g) {
+                // group g: height g >> 3, columns (xo + 2 i, yo + 4 j) for i < 4,
+                // j < 2, with xo = (g >> 2) & 1 and yo = g & 3
+                const int px = ((g >> 2) & 1) + 2 * (gp & 3);
+                const int py = (g & 3) + 4 * (gp >> 2);
+                const EqRecord r = s_rec[(g >> 3) * (kChX * kChY) + py * kChX + px];
+                const bool valid = r.mu_v.w != 0.0f;
+                const float w = (ci ? r.t.x : 1.0f - r.t.x) * (cj ? r.t.y : 1.0f - r.t.y) *
+                                (ck ? r.t.z : 1.0f - r.t.z);
+                const int c = valid ? ((r.idx.z + ck - lo[2]) * by + (r.idx.y + cj - lo[1])) * bx +
+                                          (r.idx.x + ci - lo[0])
+                                    : 0;
+                if (valid)
+                    __hip_atomic_store(s_tag + c, lane, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                const bool clash =
+                    valid && __hip_atomic_load(s_tag + c, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP) != lane;
+                if (__ballot(clash) == 0ull) {
+                    if (valid) {
+                        s_m[0][c] += w * r.mu_v.x;
+                        s_m[1][c] += w * r.mu_v.y;
+                        s_m[2][c] += w * r.mu_v.z;
+                    }
+                } else {
+                    for (int q = 0; q < 8; ++q) {
+                        if (gp == q && valid) {
+                            s_m[0][c] += w * r.mu_v.x;
+                            s_m[1][c] += w * r.mu_v.y;
+                            s_m[2][c] += w * r.mu_v.z;
+                        }
+                    }
                 }
             }
             // the voxels that received weight, in cell order: (m, packed local x, y, z)
