@@ -163,7 +163,7 @@ def _read_pmc(folder, counter):
 
 # the library's kernels in rocprofv3 kernel names (template arguments kept)
 KERNEL_NAME_RE = (r"((ff_build_kernel|relaxed_scan_kernel|atom_scatter_kernel|"
-                  r"adjoint_solve_kernel)<[^>]*>|reduce_kernel)")
+                  r"adjoint_solve_kernel)<[^>]*>|reduce_kernel\(double)")
 
 
 def summarize_pmc(fetch_dir, write_dir):

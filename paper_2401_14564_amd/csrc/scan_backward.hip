@@ -521,21 +521,23 @@ __global__ __launch_bounds__(64 * kScatterWaves) void atom_scatter_kernel(
             gqq += o[384];
         }
         if (live) {
-            const int na_pad = gridDim.y * 64;
-            double *out = partial + ((size_t)blockIdx.x * na_pad + atom) * 6;
+            // partial[atom][component][chunk]: the sum over chunks reads rows
+            const size_t nb = gridDim.x;
+            double *out = partial + (size_t)atom * 6 * nb + blockIdx.x;
             out[0] = gx;
-            out[1] = gy;
-            out[2] = gz;
-            out[3] = gq * A.ke_qpp - (QUAD ? gqq * A.kQ_pp : 0.0);
-            out[4] = gR * 72.0 * eiP / RiP;
-            out[5] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
+            out[nb] = gy;
+            out[2 * nb] = gz;
+            out[3 * nb] = gq * A.ke_qpp - (QUAD ? gqq * A.kQ_pp : 0.0);
+            out[4 * nb] = gR * 72.0 * eiP / RiP;
+            out[5 * nb] = (eiP > 0.0) ? ge * 12.0 * (A.eps_pp / (2.0 * eiP)) : 0.0;
         }
     }
 }
 
-// One block per (atom, component): fixed-order sum over the chunk partials.
+// One block per (atom, component): fixed-order sum over the chunk partials, a
+// contiguous row partial[atom][component][0 .. n_blocks) read by this block only.
 __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial,
-                                                     int n_blocks, int na_pad, int n_atoms,
+                                                     int n_blocks, int n_atoms,
                                                      double *__restrict__ g_pos,
                                                      double *__restrict__ g_q,
                                                      double *__restrict__ g_R,
@@ -543,9 +545,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
 {
     __shared__ double s[256];
     const int atom = blockIdx.x / 6, comp = blockIdx.x % 6;
+    const double *rowp = partial + (size_t)blockIdx.x * n_blocks;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < n_blocks; b += 256)
-        acc += partial[((size_t)b * na_pad + atom) * 6 + comp];
+    for (int b = threadIdx.x; b < n_blocks; b += 256) acc += rowp[b];
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -619,8 +621,7 @@ hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *f
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_kernel, dim3(A.n_atoms * 6, 1, 1), dim3(256, 1, 1), 0, stream,
-                       partial_ws, A.n_eq_blocks, na_blocks * 64, A.n_atoms, g_pos, g_q, g_R,
-                       g_eps);
+                       partial_ws, A.n_eq_blocks, A.n_atoms, g_pos, g_q, g_R, g_eps);
     return hipGetLastError();
 }
 
