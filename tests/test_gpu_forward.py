@@ -480,6 +480,39 @@ def test_scan_mirror_and_translation_invariance():
     np.testing.assert_allclose(tr["df"], b["df"], atol=1e-4)
 
 
+def test_scan_quarter_turn_invariance():
+    """With equal lateral springs (kx = ky) the scan commutes with a quarter turn
+    about the vertical axis through the centre of a square grid: turning the force
+    field (node (i, j) -> (n-1-j, i), (Fx, Fy) -> (-Fy, Fx)) and the square tip
+    lattice with it turns every relaxed displacement ((ux, uy) -> (-uy, ux)) and
+    keeps Fz and the frequency shift, to the tolerances of the mirror test."""
+    w = W.config0()
+    assert w.probe.k_lat[0] == w.probe.k_lat[1]
+    fire = W.parity_fire(w.fire)
+    g = W.Grid((4.0, 4.0, -2.0), (0.1, 0.1, 0.1), (80, 80, 110))
+    scan = W.Scan(6.3, 6.55, 0.12, 0.12, 21, 17, 10.0, 0.1, 24)
+    ff32 = orc.build_ff(g, w.probe, w.atoms).astype(np.float32)
+    b = {k: v.cpu().numpy() for k, v in ppm.relaxed_scan(
+        g, torch.as_tensor(ff32, device="cuda"), w.probe, fire, scan, dfp=w.df).items()}
+    n = g.n[0]
+    xc = g.origin[0] + 0.5 * (n - 1) * g.step[0]
+    yc = g.origin[1] + 0.5 * (n - 1) * g.step[1]
+    rf = ff32[:, ::-1, :, :].transpose(0, 2, 1, 3).copy()      # rf[z, a, c] = ff[z, n-1-c, a]
+    rf[..., 0], rf[..., 1] = -rf[..., 1].copy(), rf[..., 0].copy()
+    d = scan.dx
+    rscan = W.Scan(xc - (scan.y0 + (scan.ny - 1) * d - yc), yc + (scan.x0 - xc), d, d,
+                   scan.ny, scan.nx, scan.z_top, scan.dz, scan.nz)
+    rot = {k: v.cpu().numpy() for k, v in ppm.relaxed_scan(
+        g, torch.as_tensor(rf, device="cuda"), w.probe, fire, rscan, dfp=w.df).items()}
+    # rotated column (ny-1-iy, ix) holds base column (ix, iy)
+    back = {k: v[:, :, ::-1].swapaxes(1, 2) for k, v in rot.items()}
+    np.testing.assert_allclose(back["pp"][..., 0], -b["pp"][..., 1], atol=1e-5)
+    np.testing.assert_allclose(back["pp"][..., 1], b["pp"][..., 0], atol=1e-5)
+    np.testing.assert_allclose(back["pp"][..., 2], b["pp"][..., 2], atol=1e-5)
+    np.testing.assert_allclose(back["fz"], b["fz"], atol=1e-5)
+    np.testing.assert_allclose(back["df"], b["df"], atol=1e-4)
+
+
 def test_ff_force_is_negative_energy_gradient_on_fine_grid():
     """F = -grad E on the GPU: 3 x 3 x 3 grids of 1e-3 A spacing at 40 seeded
     places around the paper-scale molecule; the force at the centre voxel against

@@ -721,6 +721,36 @@ def test_scan_mirror_and_translation_invariance():
     np.testing.assert_allclose(tr["fz"], base["fz"], atol=1e-9)
 
 
+def test_scan_quarter_turn_invariance():
+    """With equal lateral springs the relaxed scan commutes with a quarter turn
+    about a vertical grid line (Eq. 1 and Eq. 2 are isotropic in x, y then):
+    turning atoms and the square tip lattice about the line through the centre
+    node of a square grid turns every relaxed position and keeps Fz."""
+    rng = np.random.default_rng(29)
+    A = W.random_atoms(rng, 6, [1.2, 1.2, -0.3], [3.2, 3.2, 0.3], q_max=0.25)
+    assert PROBE.k_lat[0] == PROBE.k_lat[1]
+    n = (45, 45, 90)
+    g = _grid(origin=(0.0, 0.0, -2.0), n=n)
+    fire = W.parity_fire(W.Fire(), f_conv=1e-10)
+    d = 0.21
+    scan = W.Scan(1.37, 1.21, d, d, 7, 6, 7.4, 0.1, 12)
+    base = orc.relaxed_scan(g, orc.build_ff(g, PROBE, A), PROBE, fire, scan, polish_tol=1e-13)
+    xc = yc = 2.2                                     # node 22 of 0 .. 44
+    B = A.copy()
+    B.pos[:, 0] = xc - (A.pos[:, 1] - yc)
+    B.pos[:, 1] = yc + (A.pos[:, 0] - xc)
+    rscan = W.Scan(xc - (scan.y0 + 5 * d - yc), yc + (scan.x0 - xc), d, d, 6, 7, scan.z_top,
+                   scan.dz, scan.nz)
+    rot = orc.relaxed_scan(g, orc.build_ff(g, PROBE, B), PROBE, fire, rscan, polish_tol=1e-13)
+    # column (ix, iy) of the base is column (5 - iy, ix) of the turned scan
+    for c, (ix, iy) in enumerate(base["cols"]):
+        cr = np.nonzero((rot["cols"][:, 0] == 5 - iy) & (rot["cols"][:, 1] == ix))[0][0]
+        np.testing.assert_allclose(rot["r"][cr, :, 0], xc - (base["r"][c, :, 1] - yc), atol=1e-9)
+        np.testing.assert_allclose(rot["r"][cr, :, 1], yc + (base["r"][c, :, 0] - xc), atol=1e-9)
+        np.testing.assert_allclose(rot["r"][cr, :, 2], base["r"][c, :, 2], atol=1e-9)
+        np.testing.assert_allclose(rot["fz"][cr], base["fz"][c], atol=1e-9)
+
+
 @pytest.mark.parametrize("periodic", [0, 1], ids=["open", "periodic"])
 def test_pair_newton_third_law(periodic):
     """Each pair acts on the atom with the opposite of its force on the probe:
