@@ -80,6 +80,46 @@ def _args():
             _lib.scan_struct(w.scan), _lib.df_struct(w.df))
 
 
+def test_c_program_links_the_library_and_gets_its_errors(tmp_path):
+    """A C99 program (strict, warnings as errors) includes the public headers,
+    links libppm.so and receives the host-side validation results: a zero-sized
+    grid, a missing output and a workspace query for an invalid scan (no launch
+    is reached, so no GPU is needed)."""
+    prog = tmp_path / "client.c"
+    prog.write_text(r"""
+#include <stdio.h>
+#include <string.h>
+#include "ppm.h"
+int main(void) {
+    ppm_grid g; ppm_probe p; ppm_scan s;
+    memset(&g, 0, sizeof g); memset(&p, 0, sizeof p); memset(&s, 0, sizeof s);
+    double x = 0.0;
+    float out = 0.0f;
+    ppm_status a = ppm_build_ff(&g, &p, 1, &x, &x, &x, &x, &out, NULL);
+    g.n[0] = g.n[1] = g.n[2] = 8;
+    g.step[0] = g.step[1] = g.step[2] = 0.1;
+    p.d0[2] = -4.0; p.k_rad = 1.0; p.R_pp = 1.66; p.eps_pp = 0.0091;
+    ppm_status b = ppm_build_ff(&g, &p, 1, &x, &x, &x, &x, NULL, NULL);
+    size_t ws = ppm_backward_workspace_bytes(&s, 10);
+    printf("%d %d %zu %s\n", (int)a, (int)b, ws, ppm_status_string(a));
+    return 0;
+}
+""")
+    exe = tmp_path / "client"
+    pkg = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                    os.path.dirname(HEADER), str(prog), "-o", str(exe), "-L", pkg, "-lppm",
+                    f"-Wl,-rpath,{pkg}"], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == _lib.PPM_EINVAL and int(out[1]) == _lib.PPM_EINVAL
+    assert int(out[2]) == 0
+    assert " ".join(out[3:]) == _status_string(_lib.PPM_EINVAL)
+
+
+def _status_string(code):
+    return _lib.lib().ppm_status_string(code).decode()
+
+
 def test_build_ff_rejects_bad_arguments():
     L = _lib.lib()
     g, p, f, s, d = _args()
