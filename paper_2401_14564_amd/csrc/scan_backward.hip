@@ -16,14 +16,15 @@
 //     ring of grad_df, gathers the eight corners of the relaxed point's cell,
 //     builds J (trilinear cell Jacobian + spring Jacobian, FP64), solves the
 //     3x3 transposed system and writes mu, the cell and its fractions.
-//  2. atom_scatter: one lane per atom, one wave per chunk of relaxed points (a
-//     tile of 8 x 8 columns x 2 heights).  The chunk's corner weights mu w_c are
-//     merged per distinct voxel in LDS (neighbouring points share corners), then
-//     every lane evaluates its own atom's pair-force derivatives once per voxel
-//     and accumulates in FP64 registers, so no cross-lane reduction is needed.
-//     Each block writes its per-atom partial sums.
-//  3. reduce: sums the partials of every (atom, component) in a fixed order and
-//     applies the per-atom constant factors -> deterministic result.
+//  2. atom_scatter: one lane per atom, one block of four waves per chunk of
+//     relaxed points (a tile of 8 x 8 columns x 2 heights).  The chunk's corner
+//     weights mu w_c are merged per distinct voxel in LDS (neighbouring points
+//     share corners), then the four waves split the voxels, every lane evaluating
+//     its own atom's pair-force derivatives once per voxel and accumulating in
+//     FP64 registers, so no cross-lane reduction is needed.  Each block writes
+//     its per-atom partial sums, scaled by the per-atom constant factors.
+//  3. reduce: sums the partials of every (atom, component) in a fixed order ->
+//     deterministic result.
 #include "ppm_device.h"
 #include "ppm_kernels.h"
 
