@@ -128,8 +128,8 @@ __device__ __forceinline__ float3 corner(const float4 *__restrict__ ff, uint32_t
 // (ix + i, iy + j, iz + k).  XSTEP1: the +x corner is always the next voxel
 // (clamped x), so with 32-bit offsets its 16-byte step folds into the load's
 // immediate offset.
-template <bool WIDE, bool XSTEP1 = false>
-__device__ __forceinline__ void gather8(const float4 *__restrict__ ff, const Cell &c, float3 *v)
+template <bool WIDE, bool XSTEP1 = false, typename CellT = Cell>
+__device__ __forceinline__ void gather8(const float4 *__restrict__ ff, const CellT &c, float3 *v)
 {
     if constexpr (!WIDE && XSTEP1) {
         const char *b = reinterpret_cast<const char *>(ff);

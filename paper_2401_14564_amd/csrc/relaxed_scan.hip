@@ -295,6 +295,32 @@ __device__ __forceinline__ void tricubic_force(const ScanArgs &a, const float *_
     Fz = -(double)gz * a.ihz;
 }
 
+// A finished column's outputs: the staged Fz column written out (STAGE), and
+// Eq. 3 over it: output o uses samples o .. o + 2m, wts.w[j] weighting sample
+// o + j (read back from LDS, or from fz_out when not staged).
+template <bool STAGE, int NL>
+__device__ __forceinline__ void column_outputs(const ScanArgs &a, const DfWeights &wts,
+                                               size_t col, int lane, float *__restrict__ fz_out,
+                                               float *__restrict__ df_out, const float *s_col)
+{
+    const size_t plane = (size_t)a.snx * a.sny;
+    if (STAGE && fz_out) {
+        for (int kk = 0; kk < a.snz; ++kk) fz_out[(size_t)kk * plane + col] = s_col[kk * NL + lane];
+    }
+    if (df_out) {
+        const int m2 = 2 * a.m;
+        for (int o = 0; o + m2 < a.snz; ++o) {
+            float s = 0.0f;
+            for (int j = 0; j <= m2; ++j) {
+                const float f = STAGE ? s_col[(o + j) * NL + lane]
+                                      : fz_out[(size_t)(o + j) * plane + col];
+                s = fmaf(wts.w[j], f, s);
+            }
+            df_out[(size_t)o * plane + col] = s;
+        }
+    }
+}
+
 // One tip column (ix, iy): all heights, then its fz output and (df_out != null)
 // its frequency shift.  NL = lanes per block (the stride of the per-lane Fz
 // columns in LDS).  STAGE: each finished height's Fz goes to the lane's LDS
@@ -455,23 +481,226 @@ __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &
         k = done ? kn : k;
     }
 
-    if (STAGE && fz_out) {
-        for (int kk = 0; kk < a.snz; ++kk) fz_out[(size_t)kk * plane + col] = s_col[kk * NL + lane];
+    column_outputs<STAGE, NL>(a, wts, col, lane, fz_out, df_out, s_col);
+}
+
+// FP32 probe state for the FP32-level instances (LERP32, trilinear): the state is
+// the displacement u = r - anchor (|u| ~ R0, so FP32 resolves it to ~5e-7 A),
+// the cell lookup works on FP32 grid coordinates (the anchor's, rounded once per
+// column, with the height's as top - k dz/h in FP32, plus u / h), and FIRE runs
+// in FP32.  At the FP32-level thresholds this path serves (f_conv >=
+// kLerp32MinFconv) the rounding of the force balance stays well below f_conv:
+// ~1e-6 eV/A from the interpolation and the springs, and (stiffness x ~3e-6 A)
+// from the rounded anchor coordinates (half an FP32 ulp of a grid coordinate
+// below 512, times the step).
+// FP64 and FP32 operations issue at the same rate on gfx950; the FP32 state
+// saves the conversions around the FP32 interpolation, one of the two halves of
+// every select and move, and the anchor arithmetic of the warm start.
+struct CellF {
+    uint32_t i000;
+    int dx1, dy1, dz1;
+    float tx, ty, tz;
+};
+
+// FP32 counterparts of clamp_cell / periodic_cell (same rules).
+__device__ __forceinline__ int clamp_cell_f(float u, int n, float &t)
+{
+    const float top =
+        __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, (float)(n - 1)) - 1u);
+    const float uc = fminf(fmaxf(u, 0.0f), top);
+    t = __builtin_amdgcn_fractf(uc);
+    return (int)uc;
+}
+
+__device__ __forceinline__ int periodic_cell_f(float u, int n, float &t)
+{
+    float f = floorf(u);
+    t = u - f;
+    f = fminf(fmaxf(f, -1.0e9f), 1.0e9f);
+    int i = (int)f;
+    i += (i < 0) ? n : 0;
+    i -= (i >= n) ? n : 0;
+    if ((unsigned)i >= (unsigned)n) {
+        i %= n;
+        i += (i < 0) ? n : 0;
     }
-    if (df_out) {
-        // Eq. 3 over the finished column: output o uses samples o .. o + 2m,
-        // wts.w[j] weighting sample o + j.
-        const int m2 = 2 * a.m;
-        for (int o = 0; o + m2 < a.snz; ++o) {
-            float s = 0.0f;
-            for (int j = 0; j <= m2; ++j) {
-                const float f = STAGE ? s_col[(o + j) * NL + lane]
-                                      : fz_out[(size_t)(o + j) * plane + col];
-                s = fmaf(wts.w[j], f, s);
+    return i;
+}
+
+template <int GEOM>
+__device__ __forceinline__ CellF locate_f(const ScanArgs &a, float gx, float gy, float gz)
+{
+    CellF c;
+    int ix, iy;
+    const bool periodic = GEOM == kRuntimeGeom ? a.periodic != 0 : GEOM == kPeriodic;
+    if (periodic) {
+        ix = periodic_cell_f(gx, a.gnx, c.tx);
+        iy = periodic_cell_f(gy, a.gny, c.ty);
+        c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
+        c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
+    } else {
+        ix = clamp_cell_f(gx, a.gnx, c.tx);
+        iy = clamp_cell_f(gy, a.gny, c.ty);
+        c.dx1 = 1;
+        c.dy1 = a.gnx;
+    }
+    const int iz = clamp_cell_f(gz, a.gnz, c.tz);
+    const int plane = a.gnx * a.gny;
+    c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
+    c.dz1 = plane;
+    return c;
+}
+
+// Trilinear combination in FP32 (the weights and summation order of trilerp).
+__device__ __forceinline__ void trilerp_f(const float3 *v, float tx, float ty, float tz,
+                                          float &Fx, float &Fy, float &Fz)
+{
+    const float3 v000 = v[0], v100 = v[1], v010 = v[2], v110 = v[3];
+    const float3 v001 = v[4], v101 = v[5], v011 = v[6], v111 = v[7];
+    const float sx = 1.0f - tx, sy = 1.0f - ty, sz = 1.0f - tz;
+    const float w00 = sy * sz, w10 = ty * sz, w01 = sy * tz, w11 = ty * tz;
+    const float w000 = sx * w00, w100 = tx * w00, w010 = sx * w10, w110 = tx * w10;
+    const float w001 = sx * w01, w101 = tx * w01, w011 = sx * w11, w111 = tx * w11;
+    Fx = w000 * v000.x + w100 * v100.x + w010 * v010.x + w110 * v110.x + w001 * v001.x +
+         w101 * v101.x + w011 * v011.x + w111 * v111.x;
+    Fy = w000 * v000.y + w100 * v100.y + w010 * v010.y + w110 * v110.y + w001 * v001.y +
+         w101 * v101.y + w011 * v011.y + w111 * v111.y;
+    Fz = w000 * v000.z + w100 * v100.z + w010 * v010.z + w110 * v110.z + w001 * v001.z +
+         w101 * v101.z + w011 * v011.z + w111 * v111.z;
+}
+
+// scan_column for the FP32-level trilinear instances: the same loop (one force
+// evaluation per lane per iteration, per-lane heights, cell cache, staged Fz,
+// straight-line merge) on the FP32 displacement state described above.
+template <bool STAGE, bool WIDE, int NL, int GEOM, bool PROG = false>
+__device__ __forceinline__ void scan_column_f32(const ScanArgs &a, const DfWeights &wts, int ix,
+                                                int iy, int lane, const float4 *__restrict__ ff,
+                                                float *__restrict__ fz_out,
+                                                float4 *__restrict__ pp_out,
+                                                float *__restrict__ df_out, float *s_col,
+                                                int *s_prog = nullptr)
+{
+    const size_t plane = (size_t)a.snx * a.sny;
+    const size_t col = (size_t)iy * a.snx + ix;
+    const double ax = a.x0 + ix * a.sdx, ay = a.y0 + iy * a.sdy;
+    // grid coordinates of the anchor (x, y per column, z per height)
+    const float gx0 = (float)fma(ax, a.ihx, a.oxi), gy0 = (float)fma(ay, a.ihy, a.oyi);
+    const float ihx = (float)a.ihx, ihy = (float)a.ihy, ihz = (float)a.ihz;
+    const float kx = (float)a.kx, ky = (float)a.ky, kR = (float)a.kR, R0 = (float)a.R0;
+    const float d0x = (float)a.d0x, d0y = (float)a.d0y, d0z = (float)a.d0z;
+    const float f_conv2 = (float)a.f_conv2, inv_mass = (float)a.inv_mass;
+    const float dt0 = (float)a.dt0, dt_max = (float)a.dt_max, f_inc = (float)a.f_inc;
+    const float f_dec = (float)a.f_dec, alpha0 = (float)a.alpha0, f_alpha = (float)a.f_alpha;
+
+    int k = 0;
+    // anchor height k at grid coordinate gztop - k dgz
+    const float gztop = (float)fma(a.z_top, a.ihz, a.ozi), dgz = (float)(a.sdz * a.ihz);
+    float gz0 = gztop;
+    float ux = d0x, uy = d0y, uz = d0z;
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    float dt = dt0, alpha = alpha0;
+    float u1x = 0.0f, u1y = 0.0f, u1z = 0.0f;   // relaxed displacement of the previous height
+    int npos = 0, it = 0;
+    float3 cv[8];
+    uint32_t cell = 0xffffffffu;
+    while (true) {
+        float Gx, Gy, Gz, g2, Tz;
+        bool done;
+        {
+            float Sx, Sy, Sz, Tx, Ty;
+            // issue the eight gathers, then the springs (independent of them)
+            // while they are in flight, then interpolate
+            const CellF c = locate_f<GEOM>(a, fmaf(ux, ihx, gx0), fmaf(uy, ihy, gy0),
+                                           fmaf(uz, ihz, gz0));
+            if (c.i000 != cell) {
+                gather8<WIDE, GEOM == kOpen>(ff, c, cv);
+                cell = c.i000;
             }
-            df_out[(size_t)o * plane + col] = s;
+            __builtin_amdgcn_sched_barrier(0);
+            // tip springs, Eq. 2, on d = u: F^T = -k_R (1 - R0/|d|) d - k_xy (.) (d - d0)
+            const float d2 = ux * ux + uy * uy + uz * uz;
+            const float fr = -kR * fmaf(-R0, __builtin_amdgcn_rsqf(d2), 1.0f);
+            Tx = fr * ux - kx * (ux - d0x);
+            Ty = fr * uy - ky * (uy - d0y);
+            Tz = fr * uz;
+            __builtin_amdgcn_sched_barrier(0);
+            trilerp_f(cv, c.tx, c.ty, c.tz, Sx, Sy, Sz);
+            Gx = Tx + Sx;
+            Gy = Ty + Sy;
+            Gz = Tz + Sz;
+            g2 = Gx * Gx + Gy * Gy + Gz * Gz;
+            const bool conv = g2 < f_conv2;
+            done = conv || it >= a.max_iter;
+            // record this height (the LDS slot of the current height is written
+            // on every iteration; the write at convergence is the one that stays)
+            const size_t o = (size_t)k * plane + col;
+            if (STAGE) s_col[k * NL + lane] = -Tz;
+            else if (fz_out && done) fz_out[o] = -Tz;
+            if (PROG)
+                __hip_atomic_store(s_prog + lane, done ? k + 1 : k, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (pp_out) {
+                if (done)
+                    pp_out[o] = make_float4(ux - d0x, uy - d0y, uz - d0z,
+                                            conv ? (float)it : -(float)it);
+            }
         }
+        if (done && k + 1 >= a.snz) break;
+        // (a) FIRE step (the rules of scan_column, in FP32)
+        const float P = Gx * vx + Gy * vy + Gz * vz;
+        const bool pos = (it > 0) && (P > 0.0f);
+        const bool neg = (it > 0) && !(P > 0.0f);
+        const float vn2 = vx * vx + vy * vy + vz * vz;
+        const float mix = alpha * vn2 * __builtin_amdgcn_rsqf(vn2 * g2);
+        const float sc = pos ? mix : 0.0f;
+        const float om = pos ? 1.0f - alpha : (neg ? 0.0f : 1.0f);
+        float fvx = om * vx + sc * Gx;
+        float fvy = om * vy + sc * Gy;
+        float fvz = om * vz + sc * Gz;
+        const int fnpos = pos ? npos + 1 : (neg ? 0 : npos);
+        const bool grow = pos && fnpos > a.n_min;
+        // (empty asm: keep the alternatives in straight-line code, as in scan_column;
+        // min/max as compare-and-select, which needs no canonicalised operands)
+        const float dti = dt * f_inc;
+        float dtg = dti < dt_max ? dti : dt_max, dtn = dt * f_dec, alg = alpha * f_alpha;
+        asm volatile("" : "+v"(dtg), "+v"(dtn), "+v"(alg));
+        const float fdt = grow ? dtg : (neg ? dtn : dt);
+        const float falpha = grow ? alg : (neg ? alpha0 : alpha);
+        const float h = fdt * inv_mass;
+        fvx += Gx * h;
+        fvy += Gy * h;
+        fvz += Gz * h;
+        float fux = ux + fvx * fdt, fuy = uy + fvy * fdt, fuz = uz + fvz * fdt;
+
+        // (b) next height: warm start from the displacement extrapolated
+        // linearly from this height and the previous one; v and alpha restart,
+        // dt carries over (not below dt0)
+        const bool lin = k >= 1;
+        const float ex = lin ? ux - u1x : 0.0f, ey = lin ? uy - u1y : 0.0f,
+                    ez = lin ? uz - u1z : 0.0f;
+        float nux = ux + ex, nuy = uy + ey, nuz = uz + ez;
+        float ndt = dt > dt0 ? dt : dt0;
+        asm volatile("" : "+v"(nux), "+v"(nuy), "+v"(nuz), "+v"(ndt), "+v"(fux), "+v"(fuy),
+                     "+v"(fuz));
+        const int kn = k + 1;
+        const float ngz0 = fmaf(-(float)kn, dgz, gztop);
+        u1x = done ? ux : u1x;
+        u1y = done ? uy : u1y;
+        u1z = done ? uz : u1z;
+        ux = done ? nux : fux;
+        uy = done ? nuy : fuy;
+        uz = done ? nuz : fuz;
+        vx = done ? 0.0f : fvx;
+        vy = done ? 0.0f : fvy;
+        vz = done ? 0.0f : fvz;
+        dt = done ? ndt : fdt;
+        alpha = done ? alpha0 : falpha;
+        npos = done ? 0 : fnpos;
+        it = done ? 0 : it + 1;
+        gz0 = done ? ngz0 : gz0;
+        k = done ? kn : k;
     }
+    column_outputs<STAGE, NL>(a, wts, col, lane, fz_out, df_out, s_col);
 }
 
 // Grid prefetch by one extra wave per block (single scans of open grids): the
@@ -589,8 +818,12 @@ __global__ __launch_bounds__(TX * TY + (PF ? 64 : 0)) void relaxed_scan_kernel(
         }
     }
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32, PF>(
-        a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col, En, s_prog);
+    if constexpr (INTERP == 0 && LERP32)
+        scan_column_f32<STAGE, WIDE, TX * TY, GEOM, PF>(a, wts, ix, iy, lane, ff, fz_out, pp_out,
+                                                       df_out, s_col, s_prog);
+    else
+        scan_column<STAGE, WIDE, TX * TY, INTERP, GEOM, LERP32, PF>(
+            a, wts, ix, iy, lane, ff, fz_out, pp_out, df_out, s_col, En, s_prog);
 }
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.  The
@@ -629,9 +862,15 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
     const int ix = (int)(local % tiles_x) * kTX + (int)threadIdx.x;
     const int iy = (int)(local / tiles_x) * kTY + (int)threadIdx.y;
     if (ix >= a.snx || iy >= a.sny) return;
-    scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32>(
-        a, wts, ix, iy, lane, arena + M.ff_offset, fz_arena ? fz_arena + J.fz_offset : nullptr,
-        nullptr, df_arena ? df_arena + J.df_offset : nullptr, s_col);
+    float *fzo = fz_arena ? fz_arena + J.fz_offset : nullptr;
+    float *dfo = df_arena ? df_arena + J.df_offset : nullptr;
+    if constexpr (LERP32)
+        scan_column_f32<STAGE, WIDE, kTX * kTY, kRuntimeGeom>(a, wts, ix, iy, lane,
+                                                              arena + M.ff_offset, fzo, nullptr,
+                                                              dfo, s_col);
+    else
+        scan_column<STAGE, WIDE, kTX * kTY, 0, kRuntimeGeom, LERP32>(
+            a, wts, ix, iy, lane, arena + M.ff_offset, fzo, nullptr, dfo, s_col);
 }
 
 // Standalone frequency shift: one lane per (x, y) column sliding along z.
