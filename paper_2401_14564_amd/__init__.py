@@ -443,7 +443,8 @@ class BatchPipeline:
                                     totals), "ppm_batch_plan")
         self.totals = [int(v) for v in totals]
         self.mols_dev = torch.frombuffer(bytearray(bytes(self.mols)), dtype=torch.uint8).to(dev)
-        self.jobs_dev = torch.frombuffer(bytearray(bytes(self.jobs)), dtype=torch.uint8).to(dev)
+        self.jobs_dev = (torch.frombuffer(bytearray(bytes(self.jobs)), dtype=torch.uint8).to(dev)
+                         if self.n_jobs else torch.empty(0, dtype=torch.uint8, device=dev))
         self.pos = torch.cat(pos).contiguous().to(dev)
         self.q = torch.cat(q).contiguous().to(dev)
         self.R = torch.cat(R).contiguous().to(dev)
@@ -455,7 +456,7 @@ class BatchPipeline:
                    if dfp is not None else None)
         self.probe = _lib.probe_struct(probe)
         self.fire = _lib.fire_struct(fire)
-        self.m = 0 if dfp is None else df_half_width(dfp.A, jobs[0][2].dz)
+        self.m = 0 if dfp is None or not jobs else df_half_width(dfp.A, jobs[0][2].dz)
         self.graph = None
 
     def build_ff(self):
@@ -466,6 +467,8 @@ class BatchPipeline:
         _lib.check(st, "ppm_batch_build_ff")
 
     def scan(self):
+        if self.n_jobs == 0:             # a batch of force fields only
+            return
         L = _lib.lib()
         st = L.ppm_batch_relaxed_scan(self.n_mol, self.mols, _lib.ptr(self.mols_dev), self.n_jobs,
                                       self.jobs, _lib.ptr(self.jobs_dev), self.fire, self.dfp,

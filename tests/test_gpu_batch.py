@@ -178,3 +178,9 @@ def test_batch_edge_cases():
         res = ppm.relaxed_scan(grids[mi], ff, pr, ws[0].fire, sc, dfp=ws[0].df)
         assert torch.equal(bp.df_stack(j), res["df"]), j
         assert torch.equal(bp.fz_stack(j), res["fz"]), j
+    # a batch of force fields only (no scan jobs)
+    fo = ppm.BatchPipeline(mols, [], ws[0].probe, ws[0].fire, ws[0].df)
+    fo.run()
+    torch.cuda.synchronize()
+    for i in range(len(mols)):
+        assert torch.equal(fo.ff_grid(i), bp.ff_grid(i)), i
