@@ -485,6 +485,7 @@ def _microbench(torch):
     L.ppm_mb_gather.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_uint32,
                                 ct.c_void_p, ct.c_void_p]
     L.ppm_mb_pair.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]
+    L.ppm_mb_issue.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]
     dev = torch.device("cuda:0")
     band = torch.rand(int(L.ppm_mb_gather_band_bytes()) // 4, device=dev)
     gb, gi = 8192, 64
@@ -515,6 +516,19 @@ def _microbench(torch):
         ms = timed(lambda: L.ppm_mb_pair(per, pb, pr, ct.c_void_p(pout.data_ptr()),
                                           ct.c_void_p(stream)))
         out[f"pair_{key}_tflops"] = round(pairs * flop / (ms * 1e-3) / 1e12, 2)
+    # VALU issue rate per instruction kind, in lanes per SIMD and cycle at the
+    # 2.4 GHz the published peaks assume (16 = one wave64 instruction per 4 cycles)
+    ib, ii = 2048, 4096
+    lanes = ib * 256 * ii * 8
+    issue = {}
+    for kind, key in ((0, "fp32_fma_vector_operands"), (1, "fp32_fma_scalar_factor"),
+                      (2, "fp64_fma_vector_operands"), (3, "fp32_rsq")):
+        ms = timed(lambda: L.ppm_mb_issue(kind, ib, ii, ct.c_void_p(pout.data_ptr()),
+                                           ct.c_void_p(stream)))
+        issue[key] = round(lanes / (ms * 1e-3) / (1024 * 2.4e9), 1)
+    out["valu_issue_lanes_per_simd_cycle"] = issue
+    out["fp32_fma_vector_tflops"] = round(issue["fp32_fma_vector_operands"] * 2 * 1024 * 2.4e9
+                                          / 1e12, 1)
     out["note"] = ("gather: 128 B per lane-step (8 float4 corners), 2 MiB band; pair: "
                    f"{FLOP_PER_PAIR} (open) / {FLOP_PER_PAIR_SF} (periodic) algorithmic FLOP per "
                    "pair, 8 voxels per thread, atoms in LDS, no global traffic")

@@ -18,6 +18,12 @@
  *   mask and shifted-force terms) for `reps` x 256 atoms at 8 voxels, with the
  *   atoms in LDS and no global traffic.  out: device, blocks * 256 floats.
  *   Returns as ppm_mb_gather.
+ * ppm_mb_issue: `blocks` blocks of 256 lanes, each lane running `iters` steps
+ *   of eight independent chains of one instruction kind: 0 = FP32 FMA with
+ *   vector-register operands only, 1 = FP32 FMA with one scalar-register
+ *   (wave-uniform) factor, 2 = FP64 FMA with vector-register operands, 3 = FP32
+ *   reciprocal square root (8 x iters instructions per lane).  out: device,
+ *   blocks * 256 floats.  Returns as ppm_mb_gather (-1 also for an unknown kind).
  */
 #ifndef PPM_MICROBENCH_H
 #define PPM_MICROBENCH_H
@@ -33,6 +39,7 @@ size_t ppm_mb_gather_band_bytes(void);
 int ppm_mb_gather(const float *band, int coherent, int blocks, int iters, uint32_t seed,
                   float *out, void *stream);
 int ppm_mb_pair(int periodic, int blocks, int reps, float *out, void *stream);
+int ppm_mb_issue(int kind, int blocks, int iters, float *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,8 +17,14 @@
 //    voxels of a thread's z-column, atoms broadcast from LDS, no global memory
 //    traffic and no culling: the issue ceiling of that instruction mix.  The
 //    periodic variant adds the cutoff mask and the shifted-force terms.
+//  * mb_issue: the VALU issue rate of one instruction kind, eight independent
+//    chains per lane at 32 waves per CU: FP32 FMA with vector operands only,
+//    FP32 FMA with one wave-uniform (scalar-register) factor, FP64 FMA with
+//    vector operands, FP32 reciprocal square root.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "ppm_microbench.h"
 
@@ -144,6 +150,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     out[blockIdx.x * 256 + tid] = acc;
 }
 
+// VALU issue-rate chains.  y: lane-varying factors (vector registers); s: a
+// kernel argument, so the compiler reads it from a scalar register.
+template <int KIND>
+__global__ __launch_bounds__(256) void mb_issue_kernel(int iters, float s, float *__restrict__ out)
+{
+    const int tid = threadIdx.x;
+    using T = typename std::conditional<KIND == 2, double, float>::type;
+    T x[8], y[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        x[c] = (T)(1.0f + 1e-3f * (float)((tid + c) & 7));
+        y[c] = (T)(0.5f + 1e-3f * (float)((tid * 3 + c) & 7));
+    }
+#pragma unroll 4
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if constexpr (KIND == 0 || KIND == 2) x[c] = x[c] * y[c] + y[(c + 1) & 7];
+            if constexpr (KIND == 1) x[c] = fmaf(x[c], s, y[c]);
+            if constexpr (KIND == 3) x[c] = __builtin_amdgcn_rsqf(x[c]);
+        }
+    }
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += x[c];
+    out[blockIdx.x * 256 + tid] = (float)acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +208,19 @@ int ppm_mb_pair(int periodic, int blocks, int reps, float *out, void *stream)
     else
         hipLaunchKernelGGL(mb_pair_kernel<false>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                            reps, out);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ppm_mb_issue(int kind, int blocks, int iters, float *out, void *stream)
+{
+    if (!out || blocks < 1 || iters < 1 || kind < 0 || kind > 3) return -1;
+    const hipStream_t st = (hipStream_t)stream;
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(mb_issue_kernel<0>, dim3(blocks), dim3(256), 0, st, iters, 0.5f, out); break;
+    case 1: hipLaunchKernelGGL(mb_issue_kernel<1>, dim3(blocks), dim3(256), 0, st, iters, 0.5f, out); break;
+    case 2: hipLaunchKernelGGL(mb_issue_kernel<2>, dim3(blocks), dim3(256), 0, st, iters, 0.5f, out); break;
+    default: hipLaunchKernelGGL(mb_issue_kernel<3>, dim3(blocks), dim3(256), 0, st, iters, 0.5f, out); break;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -296,7 +296,7 @@ def test_microbench_library_exports_its_header():
     src = open(os.path.join(ROOT, "include", "ppm_microbench.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = sorted(set(re.findall(r"\b(ppm_mb_[a-z_0-9]+)\s*\(", src)))
-    assert names == ["ppm_mb_gather", "ppm_mb_gather_band_bytes", "ppm_mb_pair"]
+    assert names == ["ppm_mb_gather", "ppm_mb_gather_band_bytes", "ppm_mb_issue", "ppm_mb_pair"]
     L = ct.CDLL(os.path.join(ROOT, "paper_2401_14564_amd", "libppm_microbench.so"))
     for n in names:
         assert hasattr(L, n), n
@@ -308,6 +308,10 @@ def test_microbench_library_exports_its_header():
     assert L.ppm_mb_gather(None, 1, 1, 1, 0, FAKE, None) == -1
     assert L.ppm_mb_gather(FAKE, 1, 0, 1, 0, FAKE, None) == -1
     assert L.ppm_mb_pair(0, 1, 1, None, None) == -1
+    L.ppm_mb_issue.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]
+    assert L.ppm_mb_issue(4, 1, 1, FAKE, None) == -1       # unknown kind
+    assert L.ppm_mb_issue(0, 1, 0, FAKE, None) == -1
+    assert L.ppm_mb_issue(0, 1, 1, None, None) == -1
 
 
 def test_tuning_arguments_rejected_on_host():
