@@ -182,11 +182,12 @@ ppm_status ppm_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32_t n_
  * ppm_relaxed_scan -- relaxed scan with optional fused frequency shift
  * (Sec. 2.1 Eq. 1-3, Sec. 5.1.1 step 2).
  * in:  ff[nz][ny][nx][4] from ppm_build_ff (only Fx, Fy, Fz are read).
- * The probe state and FIRE are FP64.  When fire->f_conv >= 1e-5 eV/A the
- * trilinear combination of the FP32 corner forces is FP32 and the spring's
- * 1/|d| is the hardware estimate (both err at about 1e-7 of the force, far
- * below the threshold); otherwise both are FP64, so tight thresholds resolve
- * the force balance below FP32 rounding.
+ * Precision: when fire->f_conv >= 1e-5 eV/A the probe state (its displacement
+ * from the tip anchor), FIRE, the springs (hardware 1/sqrt estimate) and the
+ * trilinear combination are FP32 -- the force balance then carries about 1e-6
+ * eV/A of rounding, an order below the threshold; otherwise all of them are
+ * FP64 (absolute positions), so tight thresholds resolve the force balance
+ * below FP32 rounding.
  * out (each may be NULL, at least one must be given):
  *   fz[scan.nz][scan.ny][scan.nx]  tip force Fz_tip = -F^T_z at the relaxed
  *                                   probe position (eV/A)
