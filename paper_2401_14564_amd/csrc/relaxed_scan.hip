@@ -26,13 +26,13 @@
 //  * Heights progress per lane: a lane that converges moves to its next height
 //    in the same loop, so a wave runs for the largest per-column total of FIRE
 //    steps rather than the sum of per-height maxima.
-//  * Probe state (position, velocity, FIRE scalars) and the springs are FP64:
-//    on gfx950 FP64 FMA issues at the same rate as unpacked FP32, and the
-//    force balance must be resolved far below the FP32 rounding of absolute
-//    coordinates.  The grid is FP32 (16 B per voxel, one float4 gather per
-//    corner); the interpolation is FP32 and the spring's 1/|d| the hardware
-//    estimate when the convergence threshold is far above their rounding
-//    (kLerp32MinFconv), FP64 otherwise.
+//  * Two precision tiers by the convergence threshold.  Far above FP32 rounding
+//    (f_conv >= kLerp32MinFconv) the probe state is its FP32 displacement from
+//    the tip anchor, and FIRE, the springs (hardware 1/sqrt estimate) and the
+//    interpolation are FP32 (scan_column_f32).  Below it the state is the
+//    absolute FP64 position and everything is FP64 (scan_column), so the force
+//    balance is resolved far below the FP32 rounding of absolute coordinates.
+//    The grid is FP32 in both (16 B per voxel, one float4 gather per corner).
 //  * Multiply-adds are fused only within one expression (contract(on), placed
 //    before the includes so it also covers the device helpers): the kernel
 //    instances (tile shape, geometry, precision, batched or single) differ in
@@ -331,7 +331,9 @@ __device__ __forceinline__ void column_outputs(const ScanArgs &a, const DfWeight
 // INTERP 0: trilinear forces from the float4 grid ff; 1: tricubic potential
 // from the energy grid En.  GEOM: grid geometry of the trilinear lookup
 // (GridGeom).  LERP32: FP32-level arithmetic where the threshold allows it (FP32
-// interpolation, hardware 1/sqrt estimate in the springs).
+// interpolation, hardware 1/sqrt estimate in the springs); the kernels route
+// the FP32-level trilinear instances to scan_column_f32 instead, so here it
+// serves the tricubic scan.
 template <bool STAGE, bool WIDE, int NL, int INTERP, int GEOM, bool LERP32, bool PROG = false>
 __device__ __forceinline__ void scan_column(const ScanArgs &a, const DfWeights &wts, int ix,
                                             int iy, int lane, const float4 *__restrict__ ff,
