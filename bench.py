@@ -229,10 +229,16 @@ def summarize_counters(folders):
 
 
 def _sha(paths):
+    """Hash of the code in the given sources, comments and whitespace removed
+    (a counter summary stays valid across comment-only edits)."""
+    import re
     h = hashlib.sha256()
     for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
