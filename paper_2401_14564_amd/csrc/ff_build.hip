@@ -83,20 +83,22 @@ __device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const fl
         const float ir2 = ir * ir;
         const float s2 = g.w * ir2;
         const float s6 = s2 * s2 * s2;
-        const float s12 = s6 * s6;
+        const float t12 = fmaf(s6, s6, -s6);       // s12 - s6 (s12 itself is not needed)
         const float ec = p.z * ir;
-        float et = ec;
-        if (PERIODIC) {     // shifted force: + fc rho (- C) inside the sphere
-            if (MASKED) {
-                const float t = fmaf(sf.x, r2 * ir, ec - sf.y);
-                et = in ? t : 0.0f;
-            } else {
-                et = fmaf(sf.x, r2 * ir, ec);
-            }
+        // E: e (s12 - 2 s6) + kq/rho; on periodic samples the shifted-force
+        // terms + fc rho (- C inside the sphere), folded as (fc rho^2 + kq)/rho
+        float e = fmaf(p.x, t12 - s6, E[k]);
+        if (PERIODIC) {
+            if (MASKED)     // one rounding for the pair's Coulomb + shift terms
+                e += fmaf(fmaf(sf.x, r2, p.z), ir, in ? -sf.y : 0.0f);   // ir = 0 outside
+            else            // (-C is summed per wave for interior atoms)
+                e = fmaf(fmaf(sf.x, r2, p.z), ir, e);
+        } else {
+            e += ec;
         }
-        E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + et;
+        E[k] = e;
         float f = 0.0f;
-        if (!EONLY) f = fmaf(p.y, s12 - s6, ec) * ir2;
+        if (!EONLY) f = fmaf(p.y, t12, ec) * ir2;
         if (PERIODIC && !EONLY) f = fmaf(-sf.x, ir, f);
         if (QUAD) {
             // u = (3 dz^2 - rho^2)/rho^5,

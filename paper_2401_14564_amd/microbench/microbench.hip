@@ -128,15 +128,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 const float ir2 = ir * ir;
                 const float s2 = g.w * ir2;
                 const float s6 = s2 * s2 * s2;
-                const float s12 = s6 * s6;
+                const float t12 = fmaf(s6, s6, -s6);
                 const float ec = p.z * ir;
-                float et = ec;
+                float e = fmaf(p.x, t12 - s6, E[k]);
                 if (PERIODIC) {
-                    const float t = fmaf(sf.x, r2 * ir, ec - sf.y);
-                    et = in ? t : 0.0f;
+                    e += fmaf(fmaf(sf.x, r2, p.z), ir, in ? -sf.y : 0.0f);
+                } else {
+                    e += ec;
                 }
-                E[k] = fmaf(p.x, fmaf(-2.0f, s6, s12), E[k]) + et;
-                float f = fmaf(p.y, s12 - s6, ec) * ir2;
+                E[k] = e;
+                float f = fmaf(p.y, t12, ec) * ir2;
                 if (PERIODIC) f = fmaf(-sf.x, ir, f);
                 Fx[k] = fmaf(f, dx, Fx[k]);
                 Fy[k] = fmaf(f, dy, Fy[k]);

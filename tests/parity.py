@@ -68,7 +68,10 @@ def check_ff(gpu_ff: np.ndarray, ref: np.ndarray, scale: np.ndarray, label: str 
     assert not bad_r.any(), f"{label}: {bad_r.sum()} relative errors, worst {rel.max():.3e}"
     assert not bad_r2.any(), (f"{label}: {bad_r2.sum()} relative errors where S/10 <= |F| < "
                               f"S/2, worst {rel2.max():.3e}")
+    wc = np.max(dF[ok] / np.maximum(scale[ok][:, :1], 1e-300)) if ok.any() else 0.0
+    we = np.max(dE[ok] / np.maximum(scale[ok][:, 1], 1e-300)) if ok.any() else 0.0
     return dict(n=int(ok.sum()), excluded=int(excl.sum()),
+                worst_component_over_S=float(wc), worst_energy_over_S=float(we),
                 worst_rel=float(rel.max()) if rel.size else 0.0,
                 worst_rel_mid=float(rel2.max()) if rel2.size else 0.0,
                 n_strong=int(strong.sum()), n_mid=int(mid.sum()))
