@@ -15,7 +15,9 @@
 //    so its float4 stores are four contiguous 256-byte runs.
 //  * Atoms are staged through LDS in chunks of BX*BY.  While staging, each atom's
 //    mixing rules are applied once (R_iP = R_i + R_PP, e_iP = sqrt(e_i e_PP),
-//    kq_i = k_e q_i q_PP) and its position is made brick-local in FP64 before
+//    kq_i = k_e q_i q_PP) and folded, in FP64, into A_i = e_iP R_iP^12 and
+//    B_i = 2 e_iP R_iP^6, so that a pair needs rho^-6 alone (its LJ energy is
+//    rho^-6 (A_i rho^-6 - B_i)), and its position is made brick-local in FP64 before
 //    rounding to FP32: FP32 differences of small local coordinates keep the
 //    relative error of rho near 1e-7, which absolute FP32 coordinates (ulp of
 //    24 A = 1.9e-6 A) would not.  The inner loop reads one atom per step with
@@ -51,14 +53,24 @@ __device__ __host__ __forceinline__ double ff_brick_half_diagonal_dev(double hx,
 // LDS of one brick: staged atoms and per-wave counts of the compaction.
 template <int NT>
 struct BrickLds {
-    float4 geo[NT];   // brick-local (x, y, z) and R_iP^2
-    float4 par[NT];   // e_iP, 12 e_iP, kq_i, kQ_i
-    float2 sf[NT];    // shifted-force constants fc, C (periodic only)
+    float4 geo[NT];   // brick-local (x, y, z) and A_i = e_iP R_iP^12
+    float4 par[NT];   // 12 A_i, -6 B_i, kq_i, -B_i  (B_i = 2 e_iP R_iP^6)
+    float4 aux[NT];   // shifted-force constants fc, C (periodic), kQ_i (quadrupole)
     int wcnt[NT / 64];
     // periodic: per wave, the staged atoms whose cutoff sphere holds the whole
     // wave box (interior) and those it only cuts (shell), in staging order
     uint8_t list[NT / 64][2][NT];
 };
+
+// An atom's auxiliary constants: all four with a quadrupolar probe, else
+// only the shifted-force pair (fc, C).
+template <bool QUAD>
+__device__ __forceinline__ float4 lds_aux(const float4 *s_aux, int t)
+{
+    if (QUAD) return s_aux[t];
+    const float2 v = *reinterpret_cast<const float2 *>(&s_aux[t]);
+    return make_float4(v.x, v.y, 0.f, 0.f);
+}
 
 // One atom's terms at the NZB voxels of a thread's z-column.  MASKED: the pair
 // enters only inside the cutoff sphere (rho^2 < rc^2 in FP32), and the
@@ -66,7 +78,7 @@ struct BrickLds {
 // the wave inside the sphere) leave -C to the caller, which adds it once per
 // atom for the whole wave.
 template <int NZB, bool PERIODIC, bool MASKED, bool EONLY, bool QUAD>
-__device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const float2 sf, float vx,
+__device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const float4 aux, float vx,
                                         float vy, const float (&vz)[NZB], float rc2, float c9,
                                         float c12, float c18, float c24, float (&Fx)[NZB],
                                         float (&Fy)[NZB], float (&Fz)[NZB], float (&E)[NZB])
@@ -81,30 +93,31 @@ __device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const fl
         const bool in = !MASKED || r2 < rc2;
         if (MASKED) ir = in ? ir : 0.0f;
         const float ir2 = ir * ir;
-        const float s2 = g.w * ir2;
-        const float s6 = s2 * s2 * s2;
-        const float t12 = fmaf(s6, s6, -s6);       // s12 - s6 (s12 itself is not needed)
+        const float ir4 = ir2 * ir2;
+        const float ir6 = ir4 * ir2;
         const float ec = p.z * ir;
-        // E: e (s12 - 2 s6) + kq/rho; on periodic samples the shifted-force
-        // terms + fc rho (- C inside the sphere), folded as (fc rho^2 + kq)/rho
-        float e = fmaf(p.x, t12 - s6, E[k]);
+        // E: e (s12 - 2 s6) = rho^-6 (A rho^-6 - B), plus kq/rho; on periodic
+        // samples the shifted-force terms + fc rho (- C inside the sphere),
+        // folded as (fc rho^2 + kq)/rho
+        float e = fmaf(fmaf(g.w, ir6, p.w), ir6, E[k]);
         if (PERIODIC) {
             if (MASKED)     // one rounding for the pair's Coulomb + shift terms
-                e += fmaf(fmaf(sf.x, r2, p.z), ir, in ? -sf.y : 0.0f);   // ir = 0 outside
+                e += fmaf(fmaf(aux.x, r2, p.z), ir, in ? -aux.y : 0.0f);   // ir = 0 outside
             else            // (-C is summed per wave for interior atoms)
-                e = fmaf(fmaf(sf.x, r2, p.z), ir, e);
+                e = fmaf(fmaf(aux.x, r2, p.z), ir, e);
         } else {
             e += ec;
         }
         E[k] = e;
         float f = 0.0f;
-        if (!EONLY) f = fmaf(p.y, t12, ec) * ir2;
-        if (PERIODIC && !EONLY) f = fmaf(-sf.x, ir, f);
+        // F/rho: 12 e (s12 - s6)/rho^2 = rho^-8 (12 A rho^-6 - 6 B), plus kq/rho^3
+        if (!EONLY) f = fmaf(fmaf(p.x, ir6, p.y), ir6, ec) * ir2;
+        if (PERIODIC && !EONLY) f = fmaf(-aux.x, ir, f);
         if (QUAD) {
             // u = (3 dz^2 - rho^2)/rho^5,
             // -grad u = rho^-5 [(15 dz^2/rho^2 - 3) d - 6 dz e_z]
             const float z2 = dz * dz;
-            const float q5 = p.w * (ir2 * ir2 * ir);          // kQ_i / rho^5
+            const float q5 = aux.z * (ir4 * ir);               // kQ_i / rho^5
             E[k] = fmaf(q5, fmaf(3.0f, z2, -r2), E[k]);
             if (!EONLY) {
                 f = fmaf(q5, fmaf(15.0f * z2, ir2, -3.0f), f);
@@ -114,11 +127,11 @@ __device__ __forceinline__ void ff_pair(const float4 g, const float4 p, const fl
                 // angular part of the shift: kQ dz^2 (9 rc^-4/rho - 12 rc^-3/rho^2),
                 // its -grad: -kQ [dz^2 rho^-3 (24 rc^-3/rho - 9 rc^-4) d
                 //                 + dz rho^-1 (18 rc^-4 - 24 rc^-3/rho) e_z]
-                const float qz2 = p.w * z2;
+                const float qz2 = aux.z * z2;
                 E[k] = fmaf(qz2, fmaf(c9, ir, -c12 * ir2), E[k]);
                 if (!EONLY) {
                     f = fmaf(-qz2 * ir2 * ir, fmaf(c24, ir, -c9), f);
-                    Fz[k] = fmaf(-p.w * dz * ir, fmaf(-c24, ir, c18), Fz[k]);
+                    Fz[k] = fmaf(-aux.z * dz * ir, fmaf(-c24, ir, c18), Fz[k]);
                 }
             }
         }
@@ -146,7 +159,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     constexpr int NW = NT / 64;
     float4 *s_geo = lds.geo;
     float4 *s_par = lds.par;
-    float2 *s_sf = lds.sf;
+    float4 *s_aux = lds.aux;
     int *s_wcnt = lds.wcnt;
     static_assert(NT <= 256 && (64 % BX) == 0, "uint8 lists and whole rows per wave");
     // angular part of the shifted d_z2 term: 9 rc^-4, 12 rc^-3, 18 rc^-4, 24 rc^-3
@@ -192,7 +205,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         const int i = base + tid;
         bool keep = false;
         float4 geo = make_float4(0.f, 0.f, 0.f, 0.f), par = geo;
-        float2 sfc = make_float2(0.f, 0.f);
+        float4 aux = geo;
         if (i < a.n_atoms) {
             double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
             if (PERIODIC) {
@@ -204,9 +217,12 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             }
             const double RiP = R[i] + a.R_pp;
             const double eiP = sqrt(eps[i] * a.eps_pp);
-            geo = make_float4((float)dx, (float)dy, (float)dz, (float)(RiP * RiP));
-            par = make_float4((float)eiP, (float)(12.0 * eiP), (float)(a.kq_pp * q[i]),
-                              (float)(a.kQ_pp * q[i]));
+            const double R6 = RiP * RiP * RiP * RiP * RiP * RiP;
+            const double A = eiP * R6 * R6, B = 2.0 * eiP * R6;
+            geo = make_float4((float)dx, (float)dy, (float)dz, (float)A);
+            par = make_float4((float)(12.0 * A), (float)(-6.0 * B), (float)(a.kq_pp * q[i]),
+                              (float)(-B));
+            aux.z = (float)(a.kQ_pp * q[i]);
             if (PERIODIC) {
                 // U(rc) and fc = -dU/drho(rc) of the LJ + Coulomb pair, in FP64
                 const double rc = a.rc, irc = 1.0 / rc;
@@ -220,7 +236,8 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                     fc -= 3.0 * kQ * irc3 * irc;
                     C -= 4.0 * kQ * irc3;
                 }
-                sfc = make_float2((float)fc, (float)C);
+                aux.x = (float)fc;
+                aux.y = (float)C;
             }
         }
         int cnt, slot;
@@ -246,7 +263,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         if (keep) {
             s_geo[slot] = geo;
             s_par[slot] = par;
-            if (PERIODIC) s_sf[slot] = sfc;
+            if (PERIODIC || QUAD) s_aux[slot] = aux;
         }
         __syncthreads();
 
@@ -287,42 +304,39 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             float sumC = 0.0f;
             if (n_in > 0) {
                 int t = lds.list[wv][0][0];
-                float4 g = s_geo[t], pa = s_par[t];
-                float2 sf = s_sf[t];
+                float4 g = s_geo[t], pa = s_par[t], ax = lds_aux<QUAD>(s_aux, t);
                 for (int j = 0; j < n_in; ++j) {
                     const int tn = lds.list[wv][0][min(j + 1, n_in - 1)];
-                    const float4 gn = s_geo[tn], pn = s_par[tn];
-                    const float2 sfn = s_sf[tn];
-                    ff_pair<NZB, true, false, EONLY, QUAD>(g, pa, sf, vx, vy, vz, a.rc2, c9, c12,
+                    const float4 gn = s_geo[tn], pn = s_par[tn], xn = lds_aux<QUAD>(s_aux, tn);
+                    ff_pair<NZB, true, false, EONLY, QUAD>(g, pa, ax, vx, vy, vz, a.rc2, c9, c12,
                                                            c18, c24, Fx, Fy, Fz, E);
-                    sumC += sf.y;
+                    sumC += ax.y;
                     g = gn;
                     pa = pn;
-                    sf = sfn;
+                    ax = xn;
                 }
             }
 #pragma unroll
             for (int k = 0; k < NZB; ++k) E[k] -= sumC;
             if (n_sh > 0) {
                 int t = lds.list[wv][1][0];
-                float4 g = s_geo[t], pa = s_par[t];
-                float2 sf = s_sf[t];
+                float4 g = s_geo[t], pa = s_par[t], ax = lds_aux<QUAD>(s_aux, t);
                 for (int j = 0; j < n_sh; ++j) {
                     const int tn = lds.list[wv][1][min(j + 1, n_sh - 1)];
-                    const float4 gn = s_geo[tn], pn = s_par[tn];
-                    const float2 sfn = s_sf[tn];
-                    ff_pair<NZB, true, true, EONLY, QUAD>(g, pa, sf, vx, vy, vz, a.rc2, c9, c12,
+                    const float4 gn = s_geo[tn], pn = s_par[tn], xn = lds_aux<QUAD>(s_aux, tn);
+                    ff_pair<NZB, true, true, EONLY, QUAD>(g, pa, ax, vx, vy, vz, a.rc2, c9, c12,
                                                           c18, c24, Fx, Fy, Fz, E);
                     g = gn;
                     pa = pn;
-                    sf = sfn;
+                    ax = xn;
                 }
             }
         } else {
             for (int j = 0; j < cnt; ++j)
-                ff_pair<NZB, false, false, EONLY, QUAD>(s_geo[j], s_par[j], make_float2(0.f, 0.f),
-                                                        vx, vy, vz, a.rc2, c9, c12, c18, c24, Fx,
-                                                        Fy, Fz, E);
+                ff_pair<NZB, false, false, EONLY, QUAD>(
+                    s_geo[j], s_par[j],
+                    QUAD ? s_aux[j] : make_float4(0.f, 0.f, 0.f, 0.f), vx, vy, vz, a.rc2, c9,
+                    c12, c18, c24, Fx, Fy, Fz, E);
         }
         __syncthreads();
     }

@@ -97,9 +97,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         const float r = 3.0f + 8.0f * (float)(h & 1023u) / 1024.0f;
         const float th = 3.14159265f * (float)((h >> 10) & 1023u) / 1024.0f;
         const float ph = 6.2831853f * (float)((h >> 20) & 1023u) / 1024.0f;
+        // A = e R^12 and B = 2 e R^6 for e = 0.005 eV, R^2 = 12 A^2
         s_geo[tid] = make_float4(r * sinf(th) * cosf(ph), r * sinf(th) * sinf(ph), r * cosf(th),
-                                 12.0f);
-        s_par[tid] = make_float4(0.005f, 0.06f, 0.2f * ((tid & 1) ? 1.f : -1.f), 0.f);
+                                 14929.92f);
+        s_par[tid] = make_float4(179159.04f, -103.68f, 0.2f * ((tid & 1) ? 1.f : -1.f), -17.28f);
         s_sf[tid] = make_float2(1e-3f, 2e-2f);
     }
     __syncthreads();
@@ -126,18 +127,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 const bool in = !PERIODIC || r2 < rc2;
                 if (PERIODIC) ir = in ? ir : 0.0f;
                 const float ir2 = ir * ir;
-                const float s2 = g.w * ir2;
-                const float s6 = s2 * s2 * s2;
-                const float t12 = fmaf(s6, s6, -s6);
+                const float ir4 = ir2 * ir2;
+                const float ir6 = ir4 * ir2;
                 const float ec = p.z * ir;
-                float e = fmaf(p.x, t12 - s6, E[k]);
+                float e = fmaf(fmaf(g.w, ir6, p.w), ir6, E[k]);
                 if (PERIODIC) {
                     e += fmaf(fmaf(sf.x, r2, p.z), ir, in ? -sf.y : 0.0f);
                 } else {
                     e += ec;
                 }
                 E[k] = e;
-                float f = fmaf(p.y, t12, ec) * ir2;
+                float f = fmaf(fmaf(p.x, ir6, p.y), ir6, ec) * ir2;
                 if (PERIODIC) f = fmaf(-sf.x, ir, f);
                 Fx[k] = fmaf(f, dx, Fx[k]);
                 Fy[k] = fmaf(f, dy, Fy[k]);
