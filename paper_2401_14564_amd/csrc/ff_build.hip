@@ -358,9 +358,12 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
 // At most four waves per SIMD: the register budget (up to 128 VGPRs) lets the
 // compiler put independent work after each v_rsq_f32 instead of its consumer,
 // which on gfx950 costs a wait state per pair (72 VGPRs, seven waves per SIMD:
-// 0.35 ms at 240^3; four: 0.32 ms).
+// 0.35 ms at 240^3; four: 0.32 ms).  Periodic bricks of depth 8 get three
+// (up to 168 VGPRs): within 128 the compiler evaluates their eight voxels one
+// after another, each a dependent chain, instead of interleaving them (large
+// periodic build at depth 8: 5.2 ms with four waves, 4.2 ms with three).
 template <int BX, int BY, int NZB, bool PERIODIC, bool EONLY, bool QUAD>
-__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(1, 4))) void ff_build_kernel(
+__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(1, (PERIODIC && NZB > 6) ? 3 : 4))) void ff_build_kernel(
     const FFArgs a, const double *__restrict__ pos, const double *__restrict__ q,
     const double *__restrict__ R, const double *__restrict__ eps, float4 *__restrict__ ff)
 {
