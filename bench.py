@@ -319,20 +319,21 @@ def _buffers(ppm, torch, w, nbuf):
     return ffs, outs, m
 
 
-def _scan_stats(ppm, torch, w, ff):
+def _scan_stats(ppm, torch, w, ff, tile=16):
     """FIRE evaluations of one scan launch (deterministic: same inputs, same
-    iterations) and the critical path: the scan runs 16 x 16-column blocks of
-    four 64-lane waves (4 rows of 16 columns each); a wave lasts as long as its
-    slowest column."""
+    iterations, the same for every launch shape) and the critical path: a
+    64-lane wave covers 4 rows of 16 columns in 16 x 16-column blocks and
+    8 x 8 columns in 8 x 8 blocks, and lasts as long as its slowest column."""
     res = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=None, fz=False, pp=True)
     it = res["pp"][..., 3]
     n_eq = w.scan.n_eq
     evals = float(it.abs().sum().item()) + n_eq
     per_col = (it.abs().sum(0) + w.scan.nz).cpu().numpy()            # [ny, nx]
     ny, nx = per_col.shape
-    pc = np.zeros(((ny + 3) // 4 * 4, (nx + 15) // 16 * 16))
+    wy, wx = (8, 8) if tile == 8 else (4, 16)
+    pc = np.zeros(((ny + wy - 1) // wy * wy, (nx + wx - 1) // wx * wx))
     pc[:ny, :nx] = per_col
-    wave = pc.reshape(pc.shape[0] // 4, 4, pc.shape[1] // 16, 16).max(axis=(1, 3))
+    wave = pc.reshape(pc.shape[0] // wy, wy, pc.shape[1] // wx, wx).max(axis=(1, 3))
     out = dict(evals=evals, not_converged=int((it < 0).sum().item()),
                mean_steps=float(it.abs().mean().item()), max_steps=int(it.abs().max().item()),
                slowest_wave_evals=float(wave.max()), mean_wave_evals=float(wave.mean()))
@@ -374,7 +375,7 @@ def main():
     ms_per_step, ff_ms, scan_ms = _run_steps(ppm, torch, w, atoms, ffs, outs, a.pipeline,
                                              a.steps, a.warmup, tuning)
     n_eq = w.scan.n_eq
-    st = _scan_stats(ppm, torch, w, ffs[0])
+    st = _scan_stats(ppm, torch, w, ffs[0], tuning.scan_tile)
     pairs = _pairs_within_cutoff(w)
     ff_tflops = pairs * FLOP_PER_PAIR_SF / (ff_ms * 1e-3) / 1e12
     n_df = (w.scan.nz - 2 * m) * w.scan.nx * w.scan.ny
