@@ -11,8 +11,9 @@
 // Design:
 //  * A block of BX x BY threads owns a brick of BX x BY x NZB voxels; each
 //    thread owns NZB voxels of one z-column, so dx, dy and dx^2+dy^2 are shared
-//    by NZB pairs (register blocking along z).  A wave covers 16 x 4 columns,
-//    so its float4 stores are four contiguous 256-byte runs.
+//    by NZB pairs (register blocking along z).  A wave covers 8 x 8 columns
+//    (eight 128-byte runs of float4 stores), the most compact box for the
+//    periodic per-wave atom lists below.
 //  * Atoms are staged through LDS in chunks of BX*BY.  While staging, each atom's
 //    mixing rules are applied once (R_iP = R_i + R_PP, e_iP = sqrt(e_i e_PP),
 //    kq_i = k_e q_i q_PP) and folded, in FP64, into A_i = e_iP R_iP^12 and
@@ -36,11 +37,16 @@
 //    constants fc = -dU/drho(rc), C = U(rc) + rc fc; the radial part of the
 //    d_z2 term folds into the same two constants, its angular part adds
 //    kQ dz^2 (9 rho^-1 rc^-4 - 12 rho^-2 rc^-3) to E.
+#include <type_traits>
+
 #include "ppm.h"
 #include "ppm_kernels.h"
 
 namespace ppm {
 namespace {
+
+// Interior atoms within this distance (A) of a wave's box are summed last.
+constexpr float kCloseA = 3.0f;
 
 template <int BX, int BY, int NZB>
 __device__ __host__ __forceinline__ double ff_brick_half_diagonal_dev(double hx, double hy,
@@ -58,8 +64,10 @@ struct BrickLds {
     float4 aux[NT];   // shifted-force constants fc, C (periodic), kQ_i (quadrupole)
     int wcnt[NT / 64];
     // periodic: per wave, the staged atoms whose cutoff sphere holds the whole
-    // wave box (interior) and those it only cuts (shell), in staging order
-    uint8_t list[NT / 64][2][NT];
+    // wave box (interior: [0] beyond kCloseA of the box, [2] within it) and
+    // those it only cuts (shell, [1]), in staging order, as byte offsets into
+    // geo (the same offsets address par and aux)
+    uint16_t list[NT / 64][3][NT];
 };
 
 // An atom's auxiliary constants: all four with a quadrupolar probe, else
@@ -172,8 +180,12 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         c24 = (float)(24.0 * irc3);
     }
 
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = ty * BX + tx;
+    // each wave owns an 8 x 8 patch of the brick's columns (a compact box for
+    // the periodic cull); tid stages atoms, (tx, ty) is the thread's column
+    const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
+    constexpr int WPX = BX / 8;                                 // waves per brick row
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+    const int tx = 8 * (wv % WPX) + (tid & 7), ty = 8 * (wv / WPX) + ((tid >> 3) & 7);
 
     // brick centre in FP64
     const double hcx = 0.5 * (BX - 1), hcy = 0.5 * (BY - 1), hcz = 0.5 * (NZB - 1);
@@ -187,14 +199,15 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
 #pragma unroll
     for (int k = 0; k < NZB; ++k) vz[k] = (float)((k - hcz) * a.hz);
 
-    float Fx[NZB], Fy[NZB], Fz[NZB], E[NZB];
+    // E_cl: the energy of the close interior atoms (periodic), kept apart so
+    // that the small terms of later chunks are not rounded against it
+    float Fx[NZB], Fy[NZB], Fz[NZB], E[NZB], E_cl[NZB];
 #pragma unroll
-    for (int k = 0; k < NZB; ++k) Fx[k] = Fy[k] = Fz[k] = E[k] = 0.0f;
-    // this wave's box (periodic culling): rows ty in [RW wv, RW wv + RW - 1]
-    constexpr int RW = 64 / BX;
-    const float wex = (float)(hcx * a.hx), wez = (float)(hcz * a.hz);
-    const float wey = (float)(0.5 * (RW - 1) * a.hy);
-    const float wcy = (float)((RW * (tid >> 6) + 0.5 * (RW - 1) - hcy) * a.hy);
+    for (int k = 0; k < NZB; ++k) Fx[k] = Fy[k] = Fz[k] = E[k] = E_cl[k] = 0.0f;
+    // this wave's box (periodic culling): its 8 x 8 columns, all NZB heights
+    const float wex = (float)(3.5 * a.hx), wey = (float)(3.5 * a.hy), wez = (float)(hcz * a.hz);
+    const float wcx = (float)((8 * (wv % WPX) + 3.5 - hcx) * a.hx);
+    const float wcy = (float)((8 * (wv / WPX) + 3.5 - hcy) * a.hy);
     float rc2_in = 0.f, rc2_out = 0.f;
     if (PERIODIC) {
         rc2_in = (float)((a.rc - 1e-3) * (a.rc - 1e-3));
@@ -243,7 +256,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         int cnt, slot;
         if (PERIODIC) {
             // deterministic compaction: wave ballot + per-wave offsets
-            const int lane = tid & 63, wv = tid >> 6;
+            const int lane = tid & 63;
             const unsigned long long m = __ballot(keep);
             const int before = __popcll(m & ((1ull << lane) - 1ull));
             if (lane == 0) s_wcnt[wv] = __popcll(m);
@@ -257,7 +270,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             }
             slot = off + before;
         } else {
-            cnt = min(NT, a.n_atoms - base);
+            cnt = __builtin_amdgcn_readfirstlane(min(NT, a.n_atoms - base));
             slot = tid;
         }
         if (keep) {
@@ -268,69 +281,81 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         __syncthreads();
 
         if (PERIODIC) {
-            // Per-wave lists: the wave's 16 x 4 x NZB voxels span a box (brick-
-            // local, FP32) of centre (0, wcy, 0) and half extents (wex, wey, wez).
+            // Per-wave lists: the wave's 8 x 8 x NZB voxels span a box (brick-
+            // local, FP32) of centre (wcx, wcy, 0) and half extents (wex, wey, wez).
             // An atom enters the shell list if the box comes within rc (+1e-3 A,
-            // so that no pair the FP32 mask would admit is dropped) and the
+            // so that no pair the FP32 mask would admit is dropped) and an
             // interior list if the whole box is within rc - 1e-3 A (every pair
-            // inside the sphere, so no mask is needed).
-            const int lane = tid & 63, wv = tid >> 6;
-            int n_in = 0, n_sh = 0;
+            // inside the sphere, so no mask is needed).  Interior atoms within
+            // kCloseA of the box go to a list of their own, summed last and into
+            // an energy accumulator of their own: their terms reach thousands of
+            // eV at the voxels next to them, and in the common accumulator they
+            // would leave the many small terms of the other atoms (those of later
+            // chunks too) to be rounded against that magnitude.
+            const int lane = tid & 63;
+            int n_in = 0, n_sh = 0, n_cl = 0;
 #pragma unroll
             for (int r = 0; r < NT / 64; ++r) {
                 const int j = r * 64 + lane;
-                bool is_in = false, is_sh = false;
+                bool is_in = false, is_sh = false, is_cl = false;
                 if (j < cnt) {
                     const float4 g = s_geo[j];
-                    const float ax = fabsf(g.x), ay = fabsf(g.y - wcy), az = fabsf(g.z);
+                    const float ax = fabsf(g.x - wcx), ay = fabsf(g.y - wcy), az = fabsf(g.z);
                     const float nx_ = fmaxf(ax - wex, 0.f), ny_ = fmaxf(ay - wey, 0.f),
                                 nz_ = fmaxf(az - wez, 0.f);
                     const float near2 = fmaf(nx_, nx_, fmaf(ny_, ny_, nz_ * nz_));
                     const float fx_ = ax + wex, fy_ = ay + wey, fz_ = az + wez;
                     const float far2 = fmaf(fx_, fx_, fmaf(fy_, fy_, fz_ * fz_));
-                    is_in = far2 < rc2_in;
-                    is_sh = !is_in && near2 < rc2_out;
+                    const bool inner = far2 < rc2_in;
+                    is_cl = inner && near2 < kCloseA * kCloseA;
+                    is_in = inner && !is_cl;
+                    is_sh = !inner && near2 < rc2_out;
                 }
-                const unsigned long long mi = __ballot(is_in), ms = __ballot(is_sh);
+                const unsigned long long mi = __ballot(is_in), ms = __ballot(is_sh),
+                                         mc = __ballot(is_cl);
                 const unsigned long long below = (1ull << lane) - 1ull;
-                if (is_in) lds.list[wv][0][n_in + __popcll(mi & below)] = (uint8_t)j;
-                if (is_sh) lds.list[wv][1][n_sh + __popcll(ms & below)] = (uint8_t)j;
+                if (is_in) lds.list[wv][0][n_in + __popcll(mi & below)] = (uint16_t)(16 * j);
+                if (is_sh) lds.list[wv][1][n_sh + __popcll(ms & below)] = (uint16_t)(16 * j);
+                if (is_cl) lds.list[wv][2][n_cl + __popcll(mc & below)] = (uint16_t)(16 * j);
                 n_in += __popcll(mi);
                 n_sh += __popcll(ms);
+                n_cl += __popcll(mc);
             }
             __syncthreads();
             // the next atom's list entry and data are read before the current
             // atom's pairs, so the LDS latency overlaps them
-            float sumC = 0.0f;
-            if (n_in > 0) {
-                int t = lds.list[wv][0][0];
-                float4 g = s_geo[t], pa = s_par[t], ax = lds_aux<QUAD>(s_aux, t);
-                for (int j = 0; j < n_in; ++j) {
-                    const int tn = lds.list[wv][0][min(j + 1, n_in - 1)];
-                    const float4 gn = s_geo[tn], pn = s_par[tn], xn = lds_aux<QUAD>(s_aux, tn);
-                    ff_pair<NZB, true, false, EONLY, QUAD>(g, pa, ax, vx, vy, vz, a.rc2, c9, c12,
-                                                           c18, c24, Fx, Fy, Fz, E);
-                    sumC += ax.y;
+            auto rec = [&](int off, float4 &g, float4 &p, float4 &x) {
+                g = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_geo) + off);
+                p = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_par) + off);
+                x = lds_aux<QUAD>(
+                    reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_aux) + off), 0);
+            };
+            // the pairs of one list; unmasked (interior) atoms return their -C
+            // for the caller to subtract once per wave
+            auto pairs = [&](auto masked, const uint16_t *L, int n, float(&Eacc)[NZB]) {
+                constexpr bool M = decltype(masked)::value;
+                float sc = 0.0f;
+                if (n == 0) return sc;
+                float4 g, pa, ax;
+                rec(L[0], g, pa, ax);
+                for (int j = 0; j < n; ++j) {
+                    float4 gn, pn, xn;
+                    rec(L[min(j + 1, n - 1)], gn, pn, xn);
+                    ff_pair<NZB, true, M, EONLY, QUAD>(g, pa, ax, vx, vy, vz, a.rc2, c9, c12,
+                                                       c18, c24, Fx, Fy, Fz, Eacc);
+                    if (!M) sc += ax.y;
                     g = gn;
                     pa = pn;
                     ax = xn;
                 }
-            }
+                return sc;
+            };
+            // interior, shell, then the close interior atoms
+            float sumC = pairs(std::false_type{}, lds.list[wv][0], n_in, E);
+            pairs(std::true_type{}, lds.list[wv][1], n_sh, E);
+            sumC += pairs(std::false_type{}, lds.list[wv][2], n_cl, E_cl);
 #pragma unroll
             for (int k = 0; k < NZB; ++k) E[k] -= sumC;
-            if (n_sh > 0) {
-                int t = lds.list[wv][1][0];
-                float4 g = s_geo[t], pa = s_par[t], ax = lds_aux<QUAD>(s_aux, t);
-                for (int j = 0; j < n_sh; ++j) {
-                    const int tn = lds.list[wv][1][min(j + 1, n_sh - 1)];
-                    const float4 gn = s_geo[tn], pn = s_par[tn], xn = lds_aux<QUAD>(s_aux, tn);
-                    ff_pair<NZB, true, true, EONLY, QUAD>(g, pa, ax, vx, vy, vz, a.rc2, c9, c12,
-                                                          c18, c24, Fx, Fy, Fz, E);
-                    g = gn;
-                    pa = pn;
-                    ax = xn;
-                }
-            }
         } else {
             for (int j = 0; j < cnt; ++j)
                 ff_pair<NZB, false, false, EONLY, QUAD>(
@@ -348,8 +373,9 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             const int iz = iz0 + k;
             if (iz < a.nz) {
                 const size_t o = ((size_t)iz * a.ny + iy) * a.nx + ix;
-                if (EONLY) reinterpret_cast<float *>(ff)[o] = E[k];
-                else ff[o] = make_float4(Fx[k], Fy[k], Fz[k], E[k]);
+                const float e = PERIODIC ? E[k] + E_cl[k] : E[k];
+                if (EONLY) reinterpret_cast<float *>(ff)[o] = e;
+                else ff[o] = make_float4(Fx[k], Fy[k], Fz[k], e);
             }
         }
     }
