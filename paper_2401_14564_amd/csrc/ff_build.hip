@@ -169,7 +169,8 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     float4 *s_par = lds.par;
     float4 *s_aux = lds.aux;
     int *s_wcnt = lds.wcnt;
-    static_assert(NT <= 256 && (64 % BX) == 0, "uint8 lists and whole rows per wave");
+    static_assert(BX % 8 == 0 && BY % 8 == 0 && NT <= 256,
+                  "8 x 8-column waves; list offsets 16 * (NT - 1) fit in 16 bits");
     // angular part of the shifted d_z2 term: 9 rc^-4, 12 rc^-3, 18 rc^-4, 24 rc^-3
     float c9 = 0.f, c12 = 0.f, c18 = 0.f, c24 = 0.f;
     if (PERIODIC && QUAD) {
