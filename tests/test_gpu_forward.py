@@ -83,6 +83,24 @@ def test_ff_c2_sampled_voxels():
     print("C2 ff", info, flush=True)
 
 
+def test_ff_c2_voxels_next_to_the_slab():
+    """2,000 seeded voxels 0.9-1.2 A above the slab's top layer, where one or two
+    atoms' repulsion (thousands of eV) meets hundreds of small terms from the
+    atoms within the cutoff: the energy's rounding there depends on the order in
+    which the kernel adds them."""
+    w = W.config2()
+    got = _gpu_ff(w)
+    rng = np.random.default_rng(2003)
+    iz0 = int(round((0.9 - w.grid.origin[2]) / w.grid.step[2]))
+    idx = np.stack([rng.integers(0, w.grid.n[0], 2000), rng.integers(0, w.grid.n[1], 2000),
+                    rng.integers(iz0, iz0 + 4, 2000)], axis=1)
+    ref, sc = orc.ff_voxels(w.grid, w.probe, w.atoms, idx)
+    it = torch.as_tensor(idx, device=got.device)
+    sel = got[it[:, 2], it[:, 1], it[:, 0]].cpu().numpy()
+    info = check_ff(sel, ref, sc, "C2 next to the slab")
+    print("C2 ff next to the slab", info, flush=True)
+
+
 # ------------------------------------------------------------------ relaxed scan
 def _scan_both(w, fire, cols=None, dfp=None):
     """Oracle force field rounded to FP32 feeds both sides; the GPU scans every
