@@ -645,9 +645,9 @@ ppm_status ppm_batch_relaxed_scan(int32_t n_mol, const ppm_batch_mol *mols_host,
     bool wide = false;
     for (int i = 0; i < n_mol; ++i) {
         if ((st = check_grid(&mols_host[i].grid)) != PPM_OK) return st;
-        const double bytes = 16.0 * mols_host[i].grid.n[0] * (double)mols_host[i].grid.n[1] *
-                             mols_host[i].grid.n[2];
-        if (bytes >= 4294967296.0) wide = true;
+        if (scan_grid_wide(mols_host[i].grid.n[0], mols_host[i].grid.n[1], mols_host[i].grid.n[2],
+                           16.0))
+            wide = true;
     }
     long long nfz = 0, ndf = 0, tiles = 0;
     int max_nz = 0;

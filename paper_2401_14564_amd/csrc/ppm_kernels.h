@@ -16,6 +16,15 @@ constexpr double kCoulomb = 14.3996454784;
 constexpr double kEvPerA2InNewtonPerM = 16.02176634;
 // Largest supported frequency-shift half-width (samples on each side).
 constexpr int kMaxDfHalfWidth = 32;
+// Scan kernels take 64-bit grid offsets (WIDE) when the grid holds 4 GiB or
+// more, or when a plane or the z extent reaches 2^24 voxels: below those bounds
+// the 32-bit kernels form voxel indices with 24-bit multiplies.
+inline bool scan_grid_wide(int nx, int ny, int nz, double bytes_per_voxel)
+{
+    return bytes_per_voxel * nx * (double)ny * nz >= 4294967296.0 ||
+           (double)nx * ny >= 16777216.0 || nz >= 16777216;
+}
+
 // Largest scan height count whose per-lane Fz column (one 64-lane block) fits
 // in 64 KiB of LDS; taller scans with a fused frequency shift need the fz output.
 constexpr int kMaxScanLdsHeights = 256;

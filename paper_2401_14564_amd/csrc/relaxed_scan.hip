@@ -509,7 +509,7 @@ __device__ __forceinline__ int clamp_cell_f(float u, int n, float &t)
 {
     const float top =
         __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, (float)(n - 1)) - 1u);
-    const float uc = fminf(fmaxf(u, 0.0f), top);
+    const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, top);   // clamp to [0, top]
     t = __builtin_amdgcn_fractf(uc);
     return (int)uc;
 }
@@ -518,7 +518,7 @@ __device__ __forceinline__ int periodic_cell_f(float u, int n, float &t)
 {
     float f = floorf(u);
     t = u - f;
-    f = fminf(fmaxf(f, -1.0e9f), 1.0e9f);
+    f = __builtin_amdgcn_fmed3f(f, -1.0e9f, 1.0e9f);
     int i = (int)f;
     i += (i < 0) ? n : 0;
     i -= (i >= n) ? n : 0;
@@ -529,7 +529,7 @@ __device__ __forceinline__ int periodic_cell_f(float u, int n, float &t)
     return i;
 }
 
-template <int GEOM>
+template <int GEOM, bool WIDE>
 __device__ __forceinline__ CellF locate_f(const ScanArgs &a, float gx, float gy, float gz)
 {
     CellF c;
@@ -538,8 +538,12 @@ __device__ __forceinline__ CellF locate_f(const ScanArgs &a, float gx, float gy,
     if (periodic) {
         ix = periodic_cell_f(gx, a.gnx, c.tx);
         iy = periodic_cell_f(gy, a.gny, c.ty);
-        c.dx1 = (ix + 1 < a.gnx) ? 1 : 1 - a.gnx;
-        c.dy1 = (iy + 1 < a.gny) ? a.gnx : a.gnx * (1 - a.gny);
+        // the wrapped offsets are wave-uniform; kept opaque so that the
+        // selects stay selects (not a per-lane multiply of a selected factor)
+        int wrap_x = 1 - a.gnx, wrap_y = a.gnx * (1 - a.gny);
+        asm volatile("" : "+s"(wrap_x), "+s"(wrap_y));
+        c.dx1 = (ix + 1 < a.gnx) ? 1 : wrap_x;
+        c.dy1 = (iy + 1 < a.gny) ? a.gnx : wrap_y;
     } else {
         ix = clamp_cell_f(gx, a.gnx, c.tx);
         iy = clamp_cell_f(gy, a.gny, c.ty);
@@ -548,7 +552,9 @@ __device__ __forceinline__ CellF locate_f(const ScanArgs &a, float gx, float gy,
     }
     const int iz = clamp_cell_f(gz, a.gnz, c.tz);
     const int plane = a.gnx * a.gny;
-    c.i000 = (uint32_t)(iz * plane + iy * a.gnx + ix);
+    // 32-bit kernels: planes and z extents below 2^24 voxels (scan_grid_wide)
+    c.i000 = WIDE ? (uint32_t)(iz * plane + iy * a.gnx + ix)
+                  : __umul24(iz, plane) + __umul24(iy, a.gnx) + (uint32_t)ix;
     c.dz1 = plane;
     return c;
 }
@@ -612,7 +618,7 @@ __device__ __forceinline__ void scan_column_f32(const ScanArgs &a, const DfWeigh
             float Sx, Sy, Sz, Tx, Ty;
             // issue the eight gathers, then the springs (independent of them)
             // while they are in flight, then interpolate
-            const CellF c = locate_f<GEOM>(a, fmaf(ux, ihx, gx0), fmaf(uy, ihy, gy0),
+            const CellF c = locate_f<GEOM, WIDE>(a, fmaf(ux, ihx, gx0), fmaf(uy, ihy, gy0),
                                            fmaf(uz, ihz, gz0));
             if (c.i000 != cell) {
                 gather8<WIDE, GEOM == kOpen>(ff, c, cv);
@@ -1057,8 +1063,7 @@ void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
                                float *fz, float4 *pp, float *df, hipStream_t stream, int tile)
 {
-    const double bytes = 16.0 * a.gnx * (double)a.gny * a.gnz;
-    if (bytes >= 4294967296.0)
+    if (scan_grid_wide(a.gnx, a.gny, a.gnz, 16.0))
         launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
     else
         launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
@@ -1069,8 +1074,7 @@ hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w,
                                         const float *En, float *fz, float4 *pp, float *df,
                                         hipStream_t stream)
 {
-    const double bytes = 4.0 * a.gnx * (double)a.gny * a.gnz;
-    if (bytes >= 4294967296.0)
+    if (scan_grid_wide(a.gnx, a.gny, a.gnz, 4.0))
         launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
     else
         launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
