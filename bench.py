@@ -829,6 +829,7 @@ def _bench_next_rows(ppm, W, torch):
     # quadrupolar probe (d_z2, -0.05 e A^2, no monopole): the point-charge force field
     qprobe = dataclasses.replace(w.probe, q_pp=0.0, q_zz=-0.05)
     ffq = ppm.build_ff(w.grid, qprobe, atoms)
+    qtune, qtune_ms = ppm.tune_build_ff(w.grid, qprobe, atoms, out=ffq)
     # grid electrostatics: LJ-only grid + FFT cross-correlation with the tip density
     V = torch.as_tensor(W.hartree_potential(w.atoms, w.grid).astype(np.float32), device="cuda")
     rho = ppm.tip_density(w.grid, 0.0, -0.05, W.TIP_SIGMA)
@@ -840,7 +841,7 @@ def _bench_next_rows(ppm, W, torch):
     tq, tl, th, tsc = [], [], [], []
     for _ in range(4):
         e[0].record()
-        ppm.build_ff(w.grid, qprobe, atoms, out=ffq)
+        ppm.build_ff(w.grid, qprobe, atoms, out=ffq, tuning=qtune)
         e[1].record()
         ppm.build_ff(w.grid, lj_probe, atoms, out=ffh)
         e[2].record()
@@ -858,7 +859,9 @@ def _bench_next_rows(ppm, W, torch):
     return {"workload": "paper-scale (60 atoms, 240^3 grid, 240x240x100 scan)",
             "quadrupole_probe": {"ff_ms": round(q_ms, 3),
                                  "ff_tflops": round(pairs * FLOP_PER_PAIR_QUAD /
-                                                    (q_ms * 1e-3) / 1e12, 2)},
+                                                    (q_ms * 1e-3) / 1e12, 2),
+                                 "ff_voxels_per_thread": qtune.ff_nzb,
+                                 "ff_autotuner_ms": qtune_ms},
             "hartree": {"note": "LJ grid + FFT cross-correlation of the d_z2 tip density "
                                 "(-0.05 e A^2, sigma 0.7 A) with a synthetic periodic potential",
                         "lj_ff_ms": round(l_ms, 3),
