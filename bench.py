@@ -89,9 +89,11 @@ def _ff_kernel(tuning, periodic):
 
 def _scan_kernel(tuning, periodic):
     """Name prefix of the scan kernel of a launch with a fused frequency shift
-    (Fz staged in LDS), the work-group shape of `tuning`."""
+    and an fz output, the work-group shape of `tuning` (Fz staged in LDS, or
+    with 8 x 8 work-groups and scan_fz_direct written straight to fz)."""
     t = getattr(tuning, "scan_tile", 0) or 16
-    return f"relaxed_scan_kernel<{t}, {t}, true, false, 0, {1 if periodic else 0},"
+    stage = "false" if t == 8 and getattr(tuning, "scan_fz_direct", 0) else "true"
+    return f"relaxed_scan_kernel<{t}, {t}, {stage}, false, 0, {1 if periodic else 0},"
 
 
 def kernels_once():
@@ -116,11 +118,11 @@ def kernels_once():
         if tune:
             t, _ = ppm.tune_build_ff(w.grid, w.probe, w.atoms, out=ff)
             t, _, _ = ppm.tune_relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df,
-                                            fz=False, pp=False, tuning=t)
+                                            fz=True, pp=False, tuning=t)
         torch.cuda.synchronize()
         ppm.build_ff(w.grid, w.probe, w.atoms, out=ff, tuning=t)
         torch.cuda.synchronize()
-        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False,
+        ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=True, pp=False,
                          tuning=t)
         torch.cuda.synchronize()
         print(w.name, "shapes", t, flush=True)
@@ -288,7 +290,7 @@ def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup, tuning=
             s_scan.wait_event(ff_done[b])
             if ev is not None:
                 ev[2].record(s_scan)
-            ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+            ppm.relaxed_scan(w.grid, ffs[b], w.probe, w.fire, w.scan, dfp=w.df, fz=True,
                              pp=False, out=outs[b], tuning=tuning)
             if ev is not None:
                 ev[3].record(s_scan)
@@ -315,6 +317,8 @@ def _buffers(ppm, torch, w, nbuf):
     m = ppm.df_half_width(w.df.A, w.scan.dz)
     ffs = [torch.empty((nz, ny, nx, 4), dtype=torch.float32, device=dev) for _ in range(nbuf)]
     outs = [dict(df=torch.empty((w.scan.nz - 2 * m, w.scan.ny, w.scan.nx), dtype=torch.float32,
+                                device=dev),
+                 fz=torch.empty((w.scan.nz, w.scan.ny, w.scan.nx), dtype=torch.float32,
                                 device=dev)) for _ in range(nbuf)]
     return ffs, outs, m
 
@@ -370,7 +374,7 @@ def main():
     # launch shapes from the autotuner, on these inputs, before the timed steps
     tuning, ff_tune_ms = ppm.tune_build_ff(w.grid, w.probe, atoms, out=ffs[0])
     tuning, scan_tune_ms, _ = ppm.tune_relaxed_scan(w.grid, ffs[0], w.probe, w.fire, w.scan,
-                                                    dfp=w.df, fz=False, pp=False, out=outs[0],
+                                                    dfp=w.df, fz=True, pp=False, out=outs[0],
                                                     tuning=tuning)
     ms_per_step, ff_ms, scan_ms = _run_steps(ppm, torch, w, atoms, ffs, outs, a.pipeline,
                                              a.steps, a.warmup, tuning)
@@ -380,8 +384,8 @@ def main():
     ff_tflops = pairs * FLOP_PER_PAIR_SF / (ff_ms * 1e-3) / 1e12
     n_df = (w.scan.nz - 2 * m) * w.scan.nx * w.scan.ny
     # algorithmic bytes of the scan launch as timed: 96 B per force evaluation
-    # plus the frequency-shift output (Fz and probe state are not written)
-    scan_bytes = st["evals"] * BYTES_PER_EVAL + n_df * 4
+    # plus the Fz and frequency-shift outputs (the probe state is not written)
+    scan_bytes = st["evals"] * BYTES_PER_EVAL + (n_eq + n_df) * 4
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
     mb = _microbench(torch)
     ff_name, scan_name = _ff_kernel(tuning, True), _scan_kernel(tuning, True)
@@ -415,9 +419,12 @@ def main():
                    "pipelining": ("step i+1's force-field build overlaps step i's scan on a "
                                   "second stream (double-buffered grid)") if a.pipeline else
                                  "none: build then scan, in order, on one stream",
+                   "outputs": "Fz (the tip-force readout) at every relaxed point and the frequency "
+                              "shift; probe state not written",
                    "relaxations_per_step": n_eq, "voxels": w.grid.nvox, "atoms": w.atoms.n,
                    "launch_shapes": {"ff_voxels_per_thread": tuning.ff_nzb,
                                      "scan_tile": f"{tuning.scan_tile}x{tuning.scan_tile}",
+                                     "scan_fz_direct": tuning.scan_fz_direct,
                                      "autotuner_ms": {"ff_build": ff_tune_ms,
                                                       "relaxed_scan": scan_tune_ms}}},
         "roofline": roof,
@@ -554,7 +561,7 @@ def _bench_paper_scale(ppm, W, torch, a):
     n_eq = w.scan.n_eq
     n_df = (w.scan.nz - 2 * m) * w.scan.nx * w.scan.ny
     pairs = w.grid.nvox * w.atoms.n
-    scan_bytes = st["evals"] * BYTES_PER_EVAL + n_df * 4
+    scan_bytes = st["evals"] * BYTES_PER_EVAL + (n_eq + n_df) * 4
     return {"workload": "paper-scale plain method: 60 atoms, grid 240^3 at 0.1 A (open), scan "
                         "240x240 tips x 100 heights",
             "ms_per_step": round(seq[0], 4), "relaxations_per_s": round(n_eq / (seq[0] * 1e-3), 1),

@@ -224,10 +224,17 @@ ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_pro
  *             four waves where the heights fit the LDS staging, else 8 x 8),
  *             16 (16 x 16 where the requested outputs allow it) or 8 (8 x 8
  *             one-wave blocks).  Every scan shape gives the same bits.
+ *   scan_fz_direct  0 or 1.  With 1, scan_tile 8 and an fz output, the scan
+ *             writes each height's Fz straight to fz and the fused frequency
+ *             shift re-reads it there, instead of staging the column in LDS
+ *             (4 B per height and column): the blocks then need no LDS, and
+ *             large lattices keep all their waves resident at once.  Ignored
+ *             otherwise.  Same bits either way.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t ff_nzb;
     int32_t scan_tile;
+    int32_t scan_fz_direct;
 } ppm_tuning;
 
 /* ppm_build_ff with the brick depth of `tuning` (NULL = defaults).  Errors as
@@ -238,7 +245,8 @@ ppm_status ppm_build_ff_tuned(const ppm_grid *grid, const ppm_probe *probe,
                               void *stream);
 
 /* ppm_relaxed_scan with the work-group shape of `tuning` (NULL = automatic).
- * Errors as ppm_relaxed_scan, and PPM_EINVAL for a tile other than 0, 8, 16. */
+ * Errors as ppm_relaxed_scan, and PPM_EINVAL for a tile other than 0, 8, 16 or
+ * a scan_fz_direct other than 0, 1. */
 ppm_status ppm_relaxed_scan_tuned(const ppm_grid *grid, const float *ff,
                                   const ppm_probe *probe, const ppm_fire *fire,
                                   const ppm_scan *scan, const ppm_tuning *tuning, float *fz,
@@ -263,9 +271,11 @@ ppm_status ppm_tune_build_ff(const ppm_grid *grid, const ppm_probe *probe, int32
 /*
  * ppm_tune_relaxed_scan -- autotuner of the scan's work-group shape: runs the
  * scan (arguments as ppm_relaxed_scan; the outputs are overwritten, with the
- * same bits whatever the shape) with scan_tile 16 and 8, once untimed and
- * three times timed, and sets tuning->scan_tile to the faster (median); ms
- * (may be NULL) receives the two medians.  Blocking, as ppm_tune_build_ff.
+ * same bits whatever the shape) with scan_tile 16, scan_tile 8 and, when fz
+ * is given, scan_tile 8 with scan_fz_direct 1, each once untimed and three
+ * times timed, and sets tuning->scan_tile and tuning->scan_fz_direct to the
+ * fastest (median); ms (may be NULL, else three floats) receives the medians
+ * in that order, 0 for a candidate not run.  Blocking, as ppm_tune_build_ff.
  */
 ppm_status ppm_tune_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
                                  const ppm_fire *fire, const ppm_scan *scan, float *fz,

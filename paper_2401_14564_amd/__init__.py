@@ -38,9 +38,12 @@ __all__ = ["build_ff", "relaxed_scan", "df", "df_half_width", "relaxed_scan_back
 class Tuning:
     """Launch shapes (include/ppm.h, ppm_tuning): ff_nzb = force-field voxels per
     thread along z (0 = 8, or 6), scan_tile = relaxed-scan work-group (0 =
-    automatic, 16 or 8).  Chosen by tune_build_ff / tune_relaxed_scan."""
+    automatic, 16 or 8), scan_fz_direct = 1: with 8 x 8 work-groups and an fz
+    output, Fz goes straight to fz instead of an LDS stage.  Chosen by
+    tune_build_ff / tune_relaxed_scan."""
     ff_nzb: int = 0
     scan_tile: int = 0
+    scan_fz_direct: int = 0
 
 
 def _stream():
@@ -152,7 +155,7 @@ def tune_build_ff(grid, probe, atoms, out: torch.Tensor | None = None,
                              _lib.ptr(pos), _lib.ptr(q), _lib.ptr(R), _lib.ptr(eps),
                              _lib.ptr(out), _stream(), t, ms)
     _lib.check(st, "ppm_tune_build_ff")
-    return Tuning(t.ff_nzb, t.scan_tile), {8: float(ms[0]), 6: float(ms[1])}
+    return Tuning(t.ff_nzb, t.scan_tile, t.scan_fz_direct), {8: float(ms[0]), 6: float(ms[1])}
 
 
 def _scan_outputs(grid, ff, scan, dfp, fz, pp, out):
@@ -192,19 +195,23 @@ def relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: boo
 def tune_relaxed_scan(grid, ff, probe, fire, scan, dfp=None, fz: bool = True, pp: bool = True,
                       out: dict | None = None, tuning: Tuning | None = None):
     """Autotune the scan's work-group shape for these outputs (ppm_tune_relaxed_scan;
-    blocks).  Returns (Tuning, {tile: ms}, outputs)."""
+    blocks).  Returns (Tuning, {candidate: ms}, outputs), candidates "16x16",
+    "8x8" and, with fz, "8x8 fz direct"."""
     import ctypes as ct
     L = _lib.lib()
     out = _scan_outputs(grid, ff, scan, dfp, fz, pp, out)
     t = _lib.tuning_struct(tuning or Tuning())
-    ms = (ct.c_float * 2)()
+    ms = (ct.c_float * 3)()
     st = L.ppm_tune_relaxed_scan(_lib.grid_struct(grid), _lib.ptr(ff), _lib.probe_struct(probe),
                                  _lib.fire_struct(fire), _lib.scan_struct(scan),
                                  _lib.ptr(out.get("fz")), _lib.ptr(out.get("pp")),
                                  None if dfp is None else _lib.df_struct(dfp),
                                  _lib.ptr(out.get("df")), _stream(), t, ms)
     _lib.check(st, "ppm_tune_relaxed_scan")
-    return Tuning(t.ff_nzb, t.scan_tile), {16: float(ms[0]), 8: float(ms[1])}, out
+    cand = {"16x16": float(ms[0]), "8x8": float(ms[1])}
+    if out.get("fz") is not None:
+        cand["8x8 fz direct"] = float(ms[2])
+    return Tuning(t.ff_nzb, t.scan_tile, t.scan_fz_direct), cand, out
 
 
 def build_energy(grid, probe, atoms, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -69,7 +69,8 @@ class DfParams(ct.Structure):
 
 
 class Tuning(ct.Structure):
-    _fields_ = [("ff_nzb", ct.c_int32), ("scan_tile", ct.c_int32)]
+    _fields_ = [("ff_nzb", ct.c_int32), ("scan_tile", ct.c_int32),
+                ("scan_fz_direct", ct.c_int32)]
 
 
 class BatchMol(ct.Structure):
@@ -196,7 +197,8 @@ def tuning_struct(t) -> Tuning | None:
     """ctypes Tuning from anything with ff_nzb / scan_tile attributes (None -> NULL)."""
     if t is None:
         return None
-    return Tuning(int(getattr(t, "ff_nzb", 0)), int(getattr(t, "scan_tile", 0)))
+    return Tuning(int(getattr(t, "ff_nzb", 0)), int(getattr(t, "scan_tile", 0)),
+                  int(getattr(t, "scan_fz_direct", 0)))
 
 
 def ptr(t):

@@ -368,14 +368,15 @@ ppm_status ppm_relaxed_scan_tuned(const ppm_grid *grid, const float *ff,
                                   float *pp, const ppm_df_params *dfp, float *df, void *stream)
 {
     const int tile = tuning ? tuning->scan_tile : 0;
-    if (!valid_tile(tile)) return PPM_EINVAL;
+    const int direct = tuning ? tuning->scan_fz_direct : 0;
+    if (!valid_tile(tile) || (direct != 0 && direct != 1)) return PPM_EINVAL;
     ScanArgs a;
     DfWeights W;
     ppm_status st = scan_setup(grid, ff, probe, fire, scan, fz, pp, dfp, df, &a, &W);
     if (st != PPM_OK) return st;
     return hip_status(launch_relaxed_scan(a, W, reinterpret_cast<const float4 *>(ff), fz,
                                           reinterpret_cast<float4 *>(pp), df,
-                                          (hipStream_t)stream, tile));
+                                          (hipStream_t)stream, tile, direct != 0));
 }
 
 ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_probe *probe,
@@ -395,19 +396,25 @@ ppm_status ppm_tune_relaxed_scan(const ppm_grid *grid, const float *ff, const pp
     DfWeights W;
     ppm_status st = scan_setup(grid, ff, probe, fire, scan, fz, pp, dfp, df, &a, &W);
     if (st != PPM_OK) return st;
-    const int cand[2] = {16, 8};
-    float t[2];
-    for (int c = 0; c < 2; ++c) {
+    // (scan_tile, scan_fz_direct); the direct route only with an fz output
+    const int cand[3][2] = {{16, 0}, {8, 0}, {8, 1}};
+    const int n_cand = fz ? 3 : 2;
+    float t[3] = {0.0f, 0.0f, 0.0f};
+    int best = 0;
+    for (int c = 0; c < n_cand; ++c) {
         ppm_tuning tt = *tuning;
-        tt.scan_tile = cand[c];
+        tt.scan_tile = cand[c][0];
+        tt.scan_fz_direct = cand[c][1];
         t[c] = time_median3((hipStream_t)stream, [&]() {
             return ppm_relaxed_scan_tuned(grid, ff, probe, fire, scan, &tt, fz, pp, dfp, df,
                                           stream);
         }, &st);
         if (st != PPM_OK) return st;
+        if (t[c] < t[best]) best = c;
     }
-    tuning->scan_tile = t[1] < t[0] ? 8 : 16;
-    if (ms) { ms[0] = t[0]; ms[1] = t[1]; }
+    tuning->scan_tile = cand[best][0];
+    tuning->scan_fz_direct = cand[best][1];
+    if (ms) { ms[0] = t[0]; ms[1] = t[1]; ms[2] = t[2]; }
     return PPM_OK;
 }
 

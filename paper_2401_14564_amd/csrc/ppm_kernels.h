@@ -134,8 +134,10 @@ struct DfWeights {
     float w[2 * kMaxDfHalfWidth + 1];
 };
 
+// tile: ppm_tuning.scan_tile; fz_direct: ppm_tuning.scan_fz_direct
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
-                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile);
+                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile,
+                               bool fz_direct);
 
 // Batched scan: one 8x8 column tile per block over all jobs of the batch.
 // `proto` carries the FIRE and frequency-shift fields shared by the batch.

@@ -1002,10 +1002,14 @@ void launch_scan_geom(const ScanArgs &b, bool stage, const DfWeights &w, const f
 // tile (the autotuner's choice, ppm_tuning.scan_tile): 0 = this automatic
 // choice, 16 = 16 x 16 blocks wherever the outputs allow them, 8 = 8 x 8
 // one-wave blocks (Fz staged in 8 KiB-per-32-heights LDS columns, several
-// blocks per CU).  Every route writes the same bits.
+// blocks per CU; with fz_direct and an fz output, Fz goes straight to fz and
+// the frequency shift re-reads it, so the blocks take no LDS and every block
+// of a large lattice can be resident at once).  Every route writes the same
+// bits.
 template <bool WIDE, int INTERP, int GEOM, bool LERP32>
 void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, const float *En,
-                      float *fz, float4 *pp, float *df, hipStream_t stream, int tile)
+                      float *fz, float4 *pp, float *df, hipStream_t stream, int tile,
+                      bool fz_direct)
 {
     const bool want_df = b.m != 0 && df;
     const DfWeights sw = want_df ? sample_weights(w, b.m) : w;
@@ -1014,8 +1018,9 @@ void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, c
     const bool fits16 = (column + sizeof(int)) * 256 <= max_block_lds();
     const bool fits8 = b.snz <= kMaxScanLdsHeights;
     if (tile == 8) {
-        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, (fz || want_df) && fits8, sw,
-                                                               ff, En, fz, pp, dfo, stream);
+        const bool stage = (fz || want_df) && fits8 && !(fz_direct && fz);
+        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, stage, sw, ff, En, fz, pp, dfo,
+                                                               stream);
         return;
     }
     if (!fz && !want_df)
@@ -1038,35 +1043,40 @@ void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, c
 template <bool WIDE, int INTERP>
 void launch_scan_variant(const ScanArgs &b, const DfWeights &w, const float4 *ff,
                          const float *En, float *fz, float4 *pp, float *df, hipStream_t stream,
-                         int tile)
+                         int tile, bool fz_direct)
 {
     if constexpr (INTERP != 0) {
         if (b.lerp32)
             launch_scan_mode<WIDE, INTERP, kRuntimeGeom, true>(b, w, ff, En, fz, pp, df, stream,
-                                                               tile);
+                                                               tile, fz_direct);
         else
             launch_scan_mode<WIDE, INTERP, kRuntimeGeom, false>(b, w, ff, En, fz, pp, df, stream,
-                                                                tile);
+                                                                tile, fz_direct);
     } else if (b.periodic) {
         if (b.lerp32)
-            launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream, tile);
+            launch_scan_mode<WIDE, 0, kPeriodic, true>(b, w, ff, En, fz, pp, df, stream, tile,
+                                                       fz_direct);
         else
-            launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream, tile);
+            launch_scan_mode<WIDE, 0, kPeriodic, false>(b, w, ff, En, fz, pp, df, stream, tile,
+                                                        fz_direct);
     } else {
         if (b.lerp32)
-            launch_scan_mode<WIDE, 0, kOpen, true>(b, w, ff, En, fz, pp, df, stream, tile);
+            launch_scan_mode<WIDE, 0, kOpen, true>(b, w, ff, En, fz, pp, df, stream, tile,
+                                                   fz_direct);
         else
-            launch_scan_mode<WIDE, 0, kOpen, false>(b, w, ff, En, fz, pp, df, stream, tile);
+            launch_scan_mode<WIDE, 0, kOpen, false>(b, w, ff, En, fz, pp, df, stream, tile,
+                                                    fz_direct);
     }
 }
 
 hipError_t launch_relaxed_scan(const ScanArgs &a, const DfWeights &w, const float4 *ff,
-                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile)
+                               float *fz, float4 *pp, float *df, hipStream_t stream, int tile,
+                               bool fz_direct)
 {
     if (scan_grid_wide(a.gnx, a.gny, a.gnz, 16.0))
-        launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
+        launch_scan_variant<true, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile, fz_direct);
     else
-        launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile);
+        launch_scan_variant<false, 0>(a, w, ff, nullptr, fz, pp, df, stream, tile, fz_direct);
     return hipGetLastError();
 }
 
@@ -1075,9 +1085,9 @@ hipError_t launch_relaxed_scan_tricubic(const ScanArgs &a, const DfWeights &w,
                                         hipStream_t stream)
 {
     if (scan_grid_wide(a.gnx, a.gny, a.gnz, 4.0))
-        launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
+        launch_scan_variant<true, 1>(a, w, nullptr, En, fz, pp, df, stream, 0, false);
     else
-        launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream, 0);
+        launch_scan_variant<false, 1>(a, w, nullptr, En, fz, pp, df, stream, 0, false);
     return hipGetLastError();
 }
 

@@ -330,6 +330,9 @@ def test_tuning_arguments_rejected_on_host():
     for bad in (4, 32, -8):
         assert L.ppm_relaxed_scan_tuned(g, FAKE, pr, fi, sc, _lib.Tuning(0, bad), FAKE, None,
                                         None, None, None) == E
+    for bad in (2, -1):     # scan_fz_direct is 0 or 1
+        assert L.ppm_relaxed_scan_tuned(g, FAKE, pr, fi, sc, _lib.Tuning(0, 8, bad), FAKE, None,
+                                        None, None, None) == E
     assert L.ppm_tune_build_ff(g, pr, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, None) == E
     assert L.ppm_tune_relaxed_scan(g, FAKE, pr, fi, sc, FAKE, None, None, None, None, None,
                                    None) == E

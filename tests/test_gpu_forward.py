@@ -238,16 +238,18 @@ def test_scan_output_routes_agree(nz):
     assert torch.equal(full["df"], df_only["df"])
     assert torch.equal(full["pp"], pp_only["pp"])
     assert torch.equal(ppm.df(full["fz"], scan.dz, w.df), full["df"])
-    # the work-group shapes the autotuner chooses between
-    for tile in (16, 8):
-        t = ppm.Tuning(scan_tile=tile)
+    # the work-group shapes the autotuner chooses between (8 x 8 with Fz
+    # written straight to the fz output instead of an LDS stage too)
+    for tile, direct in ((16, 0), (8, 0), (8, 1)):
+        t = ppm.Tuning(scan_tile=tile, scan_fz_direct=direct)
         for kw in (dict(dfp=w.df, fz=True, pp=True), dict(dfp=w.df, fz=False, pp=False),
-                   dict(fz=False, pp=True)):
+                   dict(fz=False, pp=True), dict(dfp=w.df, fz=True, pp=False),
+                   dict(fz=True, pp=False)):
             if nz > 256 and not kw.get("fz") and "dfp" in kw:
                 continue
             r = run(tuning=t, **kw)
             for k in r:
-                assert torch.equal(r[k], full[k]), (tile, k, kw)
+                assert torch.equal(r[k], full[k]), (tile, direct, k, kw)
 
 
 def test_scan_below_and_above_grid_clamps():
@@ -287,6 +289,16 @@ def test_scan_across_xy_edges(periodic):
                       label=f"tricubic edges periodic={periodic}", residual=orc.residual_tricubic)
     print("tricubic edges", periodic, info, flush=True)
     assert info["graded"] > 0.9 * info["points"]
+    # every launch route of the trilinear scan gives these bits on this grid too
+    # (wrapped cells and clamped edges in each), with a fused frequency shift
+    ff32 = torch.as_tensor(ff64.astype(np.float32), device="cuda")
+    ref = ppm.relaxed_scan(grid, ff32, w.probe, fire, scan, dfp=w.df, fz=True, pp=True)
+    for tile, direct in ((16, 0), (8, 0), (8, 1)):
+        t = ppm.Tuning(scan_tile=tile, scan_fz_direct=direct)
+        r = ppm.relaxed_scan(grid, ff32, w.probe, fire, scan, dfp=w.df, fz=True, pp=True,
+                             tuning=t)
+        for k in ref:
+            assert torch.equal(r[k], ref[k]), (periodic, tile, direct, k)
 
 
 # ------------------------------------------------------------------ frequency shift
@@ -565,9 +577,10 @@ def test_autotuner_choices_on_the_large_sample():
     t, ms = ppm.tune_build_ff(w.grid, w.probe, w.atoms)
     assert t.ff_nzb in (6, 8) and all(v > 0 for v in ms.values())
     ff = ppm.build_ff(w.grid, w.probe, w.atoms, tuning=t)
-    t2, ms2, out = ppm.tune_relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False,
+    t2, ms2, out = ppm.tune_relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=True,
                                          pp=False, tuning=t)
-    assert t2.scan_tile in (8, 16) and t2.ff_nzb == t.ff_nzb
-    ref = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=False, pp=False)
-    assert torch.equal(out["df"], ref["df"])
+    assert (t2.scan_tile, t2.scan_fz_direct) in ((16, 0), (8, 0), (8, 1))
+    assert t2.ff_nzb == t.ff_nzb and len(ms2) == 3 and all(v > 0 for v in ms2.values())
+    ref = ppm.relaxed_scan(w.grid, ff, w.probe, w.fire, w.scan, dfp=w.df, fz=True, pp=False)
+    assert torch.equal(out["df"], ref["df"]) and torch.equal(out["fz"], ref["fz"])
     print("large sample tuning:", t2, "build ms", ms, "scan ms", ms2, flush=True)
