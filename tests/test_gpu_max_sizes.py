@@ -3,7 +3,8 @@ voxels, 34 GB) is built and checked voxel by voxel against the FP64 oracle; the
 scans' 64-bit addressing (grids of 4 GiB and more) is checked on an affine sample
 force (trilinear) and a quadratic potential (tricubic), which the interpolants
 reproduce exactly, so every relaxed position is the root of the analytic force
-balance (Eq. 1), found here by an independent Newton iteration."""
+balance (Eq. 1), found here by an independent Newton iteration; so is the switch
+to 64-bit addressing for planes of 2^24 voxels and more."""
 import numpy as np
 import pytest
 import torch
@@ -49,15 +50,13 @@ def _newton(anchor, probe, Amat, b, r0):
     return r
 
 
-def test_scan_on_a_grid_beyond_4_gib():
-    n = (1024, 512, 520)                        # 16 B x 272,629,760 voxels = 4.36 GB
-    h = 0.1
-    grid = W.Grid((0.0, 0.0, 0.0), (h, h, h), n)
-    rng = np.random.default_rng(42)
+def _affine_ff(n, h, centre, seed=42):
+    """float4 grid [nz][ny][nx] holding the affine force A r + b (stable, not
+    symmetric), zero energy; returns (ff, A, b)."""
+    rng = np.random.default_rng(seed)
     M = rng.normal(size=(3, 3)) * 0.004
     Amat = -(M @ M.T) - 0.003 * np.eye(3) + (M - M.T) * 0.5     # stable, not symmetric
-    centre = np.array([80.0, 40.0, 30.0])
-    b = np.array([0.004, -0.003, 0.02]) - Amat @ centre
+    b = np.array([0.004, -0.003, 0.02]) - Amat @ np.asarray(centre)
     dev = torch.device("cuda")
     ff = torch.empty((n[2], n[1], n[0], 4), dtype=torch.float32, device=dev)
     x = torch.arange(n[0], dtype=torch.float64, device=dev) * h
@@ -67,14 +66,12 @@ def test_scan_on_a_grid_beyond_4_gib():
         ff[..., c] = (Amat[c, 0] * x[None, None, :] + Amat[c, 1] * y[None, :, None]
                       + Amat[c, 2] * z[:, None, None] + b[c]).float()
     ff[..., 3] = 0.0
-    probe = W.Probe()
-    fire = W.parity_fire(W.Fire())
-    scan = W.Scan(79.63, 39.71, 0.13, 0.17, 8, 8, 36.4, 0.1, 12)
-    res = ppm.relaxed_scan(grid, ff, probe, fire, scan)
-    pp = res["pp"].cpu().numpy()
-    fz = res["fz"].cpu().numpy()
-    del ff, res
-    torch.cuda.empty_cache()
+    return ff, Amat, b
+
+
+def _check_affine_scan(scan, probe, Amat, b, pp, fz, label):
+    """Every relaxed point against the Newton root of the analytic balance, and
+    the Fz read-out there."""
     assert np.all(pp[..., 3] >= 0)
     worst = 0.0
     for iy in range(scan.ny):
@@ -89,9 +86,50 @@ def test_scan_on_a_grid_beyond_4_gib():
                 d = rN - anchor
                 dn = np.linalg.norm(d)
                 fzN = probe.k_rad * (dn - np.linalg.norm(probe.d0)) * d[2] / dn
-                assert abs(fz[k, iy, ix] - fzN) <= 1e-5, (ix, iy, k)
-    assert worst <= 1e-4, worst
-    print("wide grid scan: worst |dr|", worst, flush=True)
+                assert abs(fz[k, iy, ix] - fzN) <= 1e-5, (label, ix, iy, k)
+    assert worst <= 1e-4, (label, worst)
+    print(label, "worst |dr|", worst, flush=True)
+
+
+def test_scan_on_a_grid_beyond_4_gib():
+    n = (1024, 512, 520)                        # 16 B x 272,629,760 voxels = 4.36 GB
+    h = 0.1
+    grid = W.Grid((0.0, 0.0, 0.0), (h, h, h), n)
+    ff, Amat, b = _affine_ff(n, h, (80.0, 40.0, 30.0))
+    probe = W.Probe()
+    fire = W.parity_fire(W.Fire())
+    scan = W.Scan(79.63, 39.71, 0.13, 0.17, 8, 8, 36.4, 0.1, 12)
+    res = ppm.relaxed_scan(grid, ff, probe, fire, scan)
+    pp = res["pp"].cpu().numpy()
+    fz = res["fz"].cpu().numpy()
+    del ff, res
+    torch.cuda.empty_cache()
+    _check_affine_scan(scan, probe, Amat, b, pp, fz, "wide grid scan")
+
+
+def test_scan_on_a_grid_with_a_plane_of_2_24_voxels():
+    """Below 4 GiB the scans form voxel indices with 24-bit multiplies; a grid
+    whose xy plane holds 2^24 voxels or more (here 4097 x 4097 x 3, 0.8 GB) takes
+    the 64-bit kernels instead.  Columns next to the far corner, both work-group
+    shapes and the Fz-direct route."""
+    n = (4097, 4097, 3)
+    h = 0.1
+    grid = W.Grid((0.0, 0.0, 0.0), (h, h, h), n)
+    ff, Amat, b = _affine_ff(n, h, (405.0, 405.0, 0.1))
+    probe = W.Probe()
+    fire = W.parity_fire(W.Fire())
+    scan = W.Scan(404.63, 404.71, 0.13, 0.17, 9, 7, 4.15, 0.05, 2)   # probe 0.15, 0.10 A
+    outs = []
+    for t in (None, ppm.Tuning(scan_tile=16), ppm.Tuning(scan_tile=8),
+              ppm.Tuning(scan_tile=8, scan_fz_direct=1)):
+        res = ppm.relaxed_scan(grid, ff, probe, fire, scan, tuning=t)
+        outs.append({k: v.cpu().numpy() for k, v in res.items()})
+    del ff, res
+    torch.cuda.empty_cache()
+    for o in outs[1:]:
+        for k in o:
+            assert np.array_equal(o[k], outs[0][k]), k
+    _check_affine_scan(scan, probe, Amat, b, outs[0]["pp"], outs[0]["fz"], "2^24-plane scan")
 
 
 def test_tricubic_scan_on_an_energy_grid_beyond_4_gib():
