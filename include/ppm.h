@@ -225,11 +225,12 @@ ppm_status ppm_relaxed_scan(const ppm_grid *grid, const float *ff, const ppm_pro
  *             16 (16 x 16 where the requested outputs allow it) or 8 (8 x 8
  *             one-wave blocks).  Every scan shape gives the same bits.
  *   scan_fz_direct  0 or 1.  With 1, scan_tile 8 and an fz output, the scan
- *             writes each height's Fz straight to fz and the fused frequency
- *             shift re-reads it there, instead of staging the column in LDS
- *             (4 B per height and column): the blocks then need no LDS, and
- *             large lattices keep all their waves resident at once.  Ignored
- *             otherwise.  Same bits either way.
+ *             writes each height's Fz straight to fz, instead of staging the
+ *             column in LDS (4 B per height and column), and the frequency
+ *             shift (if requested) follows as a second pass over fz, enqueued
+ *             on the same stream by the same call: the scan's blocks then need
+ *             no LDS, and large lattices keep all their waves resident at once.
+ *             Ignored otherwise.  Same bits either way.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t ff_nzb;

@@ -1003,9 +1003,9 @@ void launch_scan_geom(const ScanArgs &b, bool stage, const DfWeights &w, const f
 // choice, 16 = 16 x 16 blocks wherever the outputs allow them, 8 = 8 x 8
 // one-wave blocks (Fz staged in 8 KiB-per-32-heights LDS columns, several
 // blocks per CU; with fz_direct and an fz output, Fz goes straight to fz and
-// the frequency shift re-reads it, so the blocks take no LDS and every block
-// of a large lattice can be resident at once).  Every route writes the same
-// bits.
+// the frequency shift is a second pass over it, so the blocks take no LDS and
+// every block of a large lattice can be resident at once).  Every route
+// writes the same bits.
 template <bool WIDE, int INTERP, int GEOM, bool LERP32>
 void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, const float *En,
                       float *fz, float4 *pp, float *df, hipStream_t stream, int tile,
@@ -1017,10 +1017,19 @@ void launch_scan_mode(const ScanArgs &b, const DfWeights &w, const float4 *ff, c
     const size_t column = (size_t)b.snz * sizeof(float);
     const bool fits16 = (column + sizeof(int)) * 256 <= max_block_lds();
     const bool fits8 = b.snz <= kMaxScanLdsHeights;
+    if (tile == 8 && fz_direct && fz) {
+        // Fz straight to fz; the frequency shift then runs as its own pass over
+        // fz (df_kernel, the same sums): fused, each lane would re-read its
+        // column once per tap at the end of its FIRE chain (0.14 ms on the
+        // large periodic scan against 0.07 ms for the pass)
+        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, false, sw, ff, En, fz, pp,
+                                                               nullptr, stream);
+        if (want_df) launch_df(fz, b.snz, b.sny, b.snx, b.m, w, df, stream);
+        return;
+    }
     if (tile == 8) {
-        const bool stage = (fz || want_df) && fits8 && !(fz_direct && fz);
-        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, stage, sw, ff, En, fz, pp, dfo,
-                                                               stream);
+        launch_scan_geom<kTX, kTY, WIDE, INTERP, GEOM, LERP32>(b, (fz || want_df) && fits8, sw,
+                                                               ff, En, fz, pp, dfo, stream);
         return;
     }
     if (!fz && !want_df)
