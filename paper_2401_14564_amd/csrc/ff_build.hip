@@ -63,6 +63,7 @@ struct BrickLds {
     float4 par[NT];   // 12 A_i, -6 B_i, kq_i, -B_i  (B_i = 2 e_iP R_iP^6)
     float4 aux[NT];   // shifted-force constants fc, C (periodic), kQ_i (quadrupole)
     int wcnt[NT / 64];
+    int idx[NT];      // periodic: atom index of each staged slot
     // periodic: per wave, the staged atoms whose cutoff sphere holds the whole
     // wave box (interior: [0] beyond kCloseA of the box, [2] within it) and
     // those it only cuts (shell, [1]), in staging order, as byte offsets into
@@ -215,48 +216,51 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         rc2_out = (float)((a.rc + 1e-3) * (a.rc + 1e-3));
     }
 
+    // an atom's staged record: mixing (R_iP, e_iP, kq_i) folded into A_i, B_i,
+    // and on periodic samples its shifted-force constants, all in FP64
+    auto atom_record = [&](int ia, float4 &geo, float4 &par, float4 &aux) {
+        const double RiP = R[ia] + a.R_pp;
+        const double eiP = sqrt(eps[ia] * a.eps_pp);
+        const double R6 = RiP * RiP * RiP * RiP * RiP * RiP;
+        const double A = eiP * R6 * R6, B = 2.0 * eiP * R6;
+        geo.w = (float)A;
+        par = make_float4((float)(12.0 * A), (float)(-6.0 * B), (float)(a.kq_pp * q[ia]),
+                          (float)(-B));
+        aux = make_float4(0.f, 0.f, (float)(a.kQ_pp * q[ia]), 0.f);
+        if (PERIODIC) {
+            // U(rc) and fc = -dU/drho(rc) of the LJ + Coulomb pair, in FP64
+            const double rc = a.rc, irc = 1.0 / rc;
+            const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2;
+            const double sc12 = sc6 * sc6, kq = a.kq_pp * q[ia];
+            const double Uc = eiP * (sc12 - 2.0 * sc6) + kq * irc;
+            double fc = 12.0 * eiP * (sc12 - sc6) * irc + kq * irc * irc;
+            double C = Uc + rc * fc;
+            if (QUAD) {    // radial part of the shifted d_z2 term
+                const double kQ = a.kQ_pp * q[ia], irc3 = irc * irc * irc;
+                fc -= 3.0 * kQ * irc3 * irc;
+                C -= 4.0 * kQ * irc3;
+            }
+            aux.x = (float)fc;
+            aux.y = (float)C;
+        }
+    };
+
     for (int base = 0; base < a.n_atoms; base += NT) {
         const int i = base + tid;
-        bool keep = false;
-        float4 geo = make_float4(0.f, 0.f, 0.f, 0.f), par = geo;
-        float4 aux = geo;
-        if (i < a.n_atoms) {
-            double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
-            if (PERIODIC) {
+        int cnt;
+        if (PERIODIC) {
+            // (1) minimum image and cull of atom i; deterministic compaction of
+            // the kept atoms (wave ballot + per-wave offsets) with their
+            // brick-local positions and indices
+            bool keep = false;
+            float4 geo = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < a.n_atoms) {
+                double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
                 dx -= a.Lx * rint(dx / a.Lx);
                 dy -= a.Ly * rint(dy / a.Ly);
                 keep = dx * dx + dy * dy + dz * dz < a.cull2;
-            } else {
-                keep = true;
+                geo = make_float4((float)dx, (float)dy, (float)dz, 0.f);
             }
-            const double RiP = R[i] + a.R_pp;
-            const double eiP = sqrt(eps[i] * a.eps_pp);
-            const double R6 = RiP * RiP * RiP * RiP * RiP * RiP;
-            const double A = eiP * R6 * R6, B = 2.0 * eiP * R6;
-            geo = make_float4((float)dx, (float)dy, (float)dz, (float)A);
-            par = make_float4((float)(12.0 * A), (float)(-6.0 * B), (float)(a.kq_pp * q[i]),
-                              (float)(-B));
-            aux.z = (float)(a.kQ_pp * q[i]);
-            if (PERIODIC) {
-                // U(rc) and fc = -dU/drho(rc) of the LJ + Coulomb pair, in FP64
-                const double rc = a.rc, irc = 1.0 / rc;
-                const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2;
-                const double sc12 = sc6 * sc6, kq = a.kq_pp * q[i];
-                const double Uc = eiP * (sc12 - 2.0 * sc6) + kq * irc;
-                double fc = 12.0 * eiP * (sc12 - sc6) * irc + kq * irc * irc;
-                double C = Uc + rc * fc;
-                if (QUAD) {    // radial part of the shifted d_z2 term
-                    const double kQ = a.kQ_pp * q[i], irc3 = irc * irc * irc;
-                    fc -= 3.0 * kQ * irc3 * irc;
-                    C -= 4.0 * kQ * irc3;
-                }
-                aux.x = (float)fc;
-                aux.y = (float)C;
-            }
-        }
-        int cnt, slot;
-        if (PERIODIC) {
-            // deterministic compaction: wave ballot + per-wave offsets
             const int lane = tid & 63;
             const unsigned long long m = __ballot(keep);
             const int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -269,15 +273,37 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
                 off += (w < wv) ? s_wcnt[w] : 0;
                 cnt += s_wcnt[w];
             }
-            slot = off + before;
+            if (keep) {
+                s_geo[off + before] = geo;
+                lds.idx[off + before] = i;
+            }
+            __syncthreads();
+            // (2) the records of the kept atoms only (about a third of the atoms
+            // on the large sample): one thread per slot
+            if (tid < cnt) {
+                float4 g = s_geo[tid], pr, ax;
+                atom_record(lds.idx[tid], g, pr, ax);
+                s_geo[tid].w = g.w;
+                s_par[tid] = pr;
+                s_aux[tid] = ax;
+            }
         } else {
+            // open samples: every atom of the chunk is staged, in its own slot
+            bool keep = false;
+            float4 geo = make_float4(0.f, 0.f, 0.f, 0.f), par = geo, aux = geo;
+            if (i < a.n_atoms) {
+                const double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy,
+                             dz = pos[3 * i + 2] - cz;
+                keep = true;
+                geo = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                atom_record(i, geo, par, aux);
+            }
             cnt = __builtin_amdgcn_readfirstlane(min(NT, a.n_atoms - base));
-            slot = tid;
-        }
-        if (keep) {
-            s_geo[slot] = geo;
-            s_par[slot] = par;
-            if (PERIODIC || QUAD) s_aux[slot] = aux;
+            if (keep) {
+                s_geo[tid] = geo;
+                s_par[tid] = par;
+                if (QUAD) s_aux[tid] = aux;
+            }
         }
         __syncthreads();
 
