@@ -321,8 +321,9 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             // chunks too) to be rounded against that magnitude.
             const int lane = tid & 63;
             int n_in = 0, n_sh = 0, n_cl = 0;
-#pragma unroll
-            for (int r = 0; r < NT / 64; ++r) {
+            // rounds of 64 staged atoms, as many as the chunk kept (cnt is
+            // wave-uniform)
+            for (int r = 0; r * 64 < cnt; ++r) {
                 const int j = r * 64 + lane;
                 bool is_in = false, is_sh = false, is_cl = false;
                 if (j < cnt) {
