@@ -216,6 +216,11 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         rc2_out = (float)((a.rc + 1e-3) * (a.rc + 1e-3));
     }
 
+    // periods and cutoff as reciprocals, once per brick (the minimum image
+    // rounds dx / Lx to an integer; a product with 1/Lx can round the other
+    // way only at half a period, where both images lie beyond the cull radius)
+    const double iLx = PERIODIC ? 1.0 / a.Lx : 0.0, iLy = PERIODIC ? 1.0 / a.Ly : 0.0;
+    const double irc = PERIODIC ? 1.0 / a.rc : 0.0;
     // an atom's staged record: mixing (R_iP, e_iP, kq_i) folded into A_i, B_i,
     // and on periodic samples its shifted-force constants, all in FP64
     auto atom_record = [&](int ia, float4 &geo, float4 &par, float4 &aux) {
@@ -229,7 +234,7 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
         aux = make_float4(0.f, 0.f, (float)(a.kQ_pp * q[ia]), 0.f);
         if (PERIODIC) {
             // U(rc) and fc = -dU/drho(rc) of the LJ + Coulomb pair, in FP64
-            const double rc = a.rc, irc = 1.0 / rc;
+            const double rc = a.rc;
             const double sc2 = RiP * RiP * irc * irc, sc6 = sc2 * sc2 * sc2;
             const double sc12 = sc6 * sc6, kq = a.kq_pp * q[ia];
             const double Uc = eiP * (sc12 - 2.0 * sc6) + kq * irc;
@@ -256,8 +261,8 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             float4 geo = make_float4(0.f, 0.f, 0.f, 0.f);
             if (i < a.n_atoms) {
                 double dx = pos[3 * i] - cx, dy = pos[3 * i + 1] - cy, dz = pos[3 * i + 2] - cz;
-                dx -= a.Lx * rint(dx / a.Lx);
-                dy -= a.Ly * rint(dy / a.Ly);
+                dx -= a.Lx * rint(dx * iLx);
+                dy -= a.Ly * rint(dy * iLy);
                 keep = dx * dx + dy * dy + dz * dz < a.cull2;
                 geo = make_float4((float)dx, (float)dy, (float)dz, 0.f);
             }
