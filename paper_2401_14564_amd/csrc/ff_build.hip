@@ -27,7 +27,11 @@
 //    brick centre (exact minimum image for every voxel of the brick as long as
 //    cutoff + brick half-diagonal < L/2, which the host checks), atoms beyond
 //    cutoff + half-diagonal of the centre are dropped with a deterministic
-//    ballot compaction, and each pair is masked by rho^2 < cutoff^2.  The
+//    ballot compaction (positions first; the FP64 per-atom constants are then
+//    computed for the kept atoms only, one thread per kept slot), and each wave
+//    sorts the kept atoms against its own 8 x 8 x NZB box into interior atoms
+//    (no mask), shell atoms (each pair masked by rho^2 < cutoff^2) and close
+//    interior atoms (summed last, into an energy accumulator of their own).  The
 //    cutoff is a shifted-force truncation: along every ray from an atom each
 //    pair term Y(direction) g(rho) becomes g - g(rc) - (rho - rc) g'(rc), so
 //    energy and force vanish on the cutoff sphere (a plain truncation leaves a
