@@ -192,6 +192,9 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
     constexpr int WPX = BX / 8;                                 // waves per brick row
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int tx = 8 * (wv % WPX) + (tid & 7), ty = 8 * (wv / WPX) + ((tid >> 3) & 7);
+    // a wave whose columns all lie beyond the grid's x or y edge (bricks of a
+    // ragged grid) stages atoms with the others but computes no pairs
+    const bool live = ix0 + 8 * (wv % WPX) < a.nx && iy0 + 8 * (wv / WPX) < a.ny;
 
     // brick centre in FP64
     const double hcx = 0.5 * (BX - 1), hcy = 0.5 * (BY - 1), hcz = 0.5 * (NZB - 1);
@@ -330,12 +333,13 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
             // chunks too) to be rounded against that magnitude.
             const int lane = tid & 63;
             int n_in = 0, n_sh = 0, n_cl = 0;
-            // rounds of 64 staged atoms, as many as the chunk kept (cnt is
-            // wave-uniform)
-            for (int r = 0; r * 64 < cnt; ++r) {
+            // rounds of 64 staged atoms, as many as the chunk kept (cnt and
+            // live are wave-uniform)
+            const int cnt_w = live ? cnt : 0;
+            for (int r = 0; r * 64 < cnt_w; ++r) {
                 const int j = r * 64 + lane;
                 bool is_in = false, is_sh = false, is_cl = false;
-                if (j < cnt) {
+                if (j < cnt_w) {
                     const float4 g = s_geo[j];
                     const float ax = fabsf(g.x - wcx), ay = fabsf(g.y - wcy), az = fabsf(g.z);
                     const float nx_ = fmaxf(ax - wex, 0.f), ny_ = fmaxf(ay - wey, 0.f),
@@ -394,7 +398,8 @@ __device__ __forceinline__ void ff_brick(const FFArgs &a, int ix0, int iy0, int 
 #pragma unroll
             for (int k = 0; k < NZB; ++k) E[k] -= sumC;
         } else {
-            for (int j = 0; j < cnt; ++j)
+            const int cnt_w = live ? cnt : 0;
+            for (int j = 0; j < cnt_w; ++j)
                 ff_pair<NZB, false, false, EONLY, QUAD>(
                     s_geo[j], s_par[j],
                     QUAD ? s_aux[j] : make_float4(0.f, 0.f, 0.f, 0.f), vx, vy, vz, a.rc2, c9,
