@@ -3,8 +3,8 @@
 One step = one pass of the forward hot path over the large periodic sample
 (400-atom flake on a 1,200-atom two-layer slab, periodic in x and y with a
 12 A shifted-force cutoff, 400x400x300 force-field grid, 400x400 tip columns x
-120 heights): force-field build -> relaxed scan with the fused frequency
-shift.  Inputs are resident in device memory before timing starts.  The
+120 heights): force-field build -> relaxed scan with the Fz readout and the
+frequency shift.  Inputs are resident in device memory before timing starts.  The
 reported value is relaxed probe positions (pixel x height) per second of the
 whole job.  By default the two stages run in order on one stream; --pipeline
 overlaps the force-field build of step i+1 with the scan of step i on a second
@@ -88,8 +88,8 @@ def _ff_kernel(tuning, periodic):
 
 
 def _scan_kernel(tuning, periodic):
-    """Name prefix of the scan kernel of a launch with a fused frequency shift
-    and an fz output, the work-group shape of `tuning` (Fz staged in LDS, or
+    """Name prefix of the scan kernel of a launch with a frequency shift and an
+    fz output, the work-group shape of `tuning` (Fz staged in LDS, or
     with 8 x 8 work-groups and scan_fz_direct written straight to fz)."""
     t = getattr(tuning, "scan_tile", 0) or 16
     stage = "false" if t == 8 and getattr(tuning, "scan_fz_direct", 0) else "true"
@@ -262,8 +262,8 @@ def _traffic(name_prefix, src_key, src):
 
 
 def _run_steps(ppm, torch, w, atoms, ffs, outs, pipeline, steps, warmup, tuning=None):
-    """Time `steps` forward steps (force-field build -> relaxed scan with fused
-    frequency shift) after `warmup` untimed ones.  Returns (ms per step, mean
+    """Time `steps` forward steps (force-field build -> relaxed scan with the Fz
+    readout and the frequency shift) after `warmup` untimed ones.  Returns (ms per step, mean
     build ms, mean scan ms), the kernel times from HIP events on the streams
     the kernels run on."""
     if pipeline:
@@ -400,7 +400,7 @@ def main():
     roof = ff_roof if ff_ms >= scan_ms else scan_roof
 
     result = {
-        "metric": "relaxed-scan PP relaxations/s (force-field build + relaxed scan + fused df)",
+        "metric": "relaxed-scan PP relaxations/s (force-field build + relaxed scan + df)",
         "value": round(n_eq / (ms_per_step * 1e-3), 1),
         "unit": "relaxations/s",
         "n_gpus": 1,
