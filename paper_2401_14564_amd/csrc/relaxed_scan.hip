@@ -881,7 +881,15 @@ __global__ __launch_bounds__(kTX * kTY) void relaxed_scan_batch_kernel(
             a, wts, ix, iy, lane, arena + M.ff_offset, fzo, nullptr, dfo, s_col);
 }
 
-// Standalone frequency shift: one lane per (x, y) column sliding along z.
+// Standalone frequency shift, Eq. 3: one lane per (x, y) column and chunk of
+// kDfChunk consecutive outputs (blockIdx.y), so that a lattice's columns give
+// enough lanes to keep the loads in flight (one lane per column walking all of
+// z left the pass latency-bound).  The lane loads its window of kDfChunk + 2m
+// samples into registers (zero past the stack and up to kDfChunk + 2M); output o sums
+// wts.w[j] * Fz(o + j) for j = 0 .. 2M in sample order, the weights beyond 2m
+// being zero, so every output rounds as the end-of-column evaluation does.
+constexpr int kDfChunk = 16;
+
 template <int M>
 __global__ __launch_bounds__(256) void df_kernel(const float *__restrict__ fz, int nz, int ny,
                                                   int nx, int m, const DfWeights wts,
@@ -890,18 +898,21 @@ __global__ __launch_bounds__(256) void df_kernel(const float *__restrict__ fz, i
     const size_t plane = (size_t)nx * ny;
     const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= plane) return;
-    float ring[2 * M + 1];
+    const int n_out = nz - 2 * m;
+    // chunks blockIdx.y, blockIdx.y + gridDim.y, ... (gridDim.y is capped)
+    for (long long o0 = (long long)blockIdx.y * kDfChunk; o0 < n_out;
+         o0 += (long long)gridDim.y * kDfChunk) {
+        float win[kDfChunk + 2 * M];
 #pragma unroll
-    for (int j = 0; j < 2 * M + 1; ++j) ring[j] = 0.0f;
-    for (int k = 0; k < nz; ++k) {
+        for (int j = 0; j < kDfChunk + 2 * M; ++j)
+            win[j] = (j <= kDfChunk - 1 + 2 * m && o0 + j < nz)
+                         ? fz[(size_t)(o0 + j) * plane + col] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2 * M; ++j) ring[j] = ring[j + 1];
-        ring[2 * M] = fz[(size_t)k * plane + col];
-        if (k >= 2 * m) {
+        for (int c = 0; c < kDfChunk; ++c) {
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j < 2 * M + 1; ++j) s = fmaf(wts.w[j], ring[j], s);
-            df[(size_t)(k - 2 * m) * plane + col] = s;
+            for (int j = 0; j <= 2 * M; ++j) s = fmaf(wts.w[j], win[c + j], s);
+            if (o0 + c < n_out) df[(size_t)(o0 + c) * plane + col] = s;
         }
     }
 }
@@ -913,16 +924,6 @@ DfWeights sample_weights(const DfWeights &w, int m)
     DfWeights o{};
     const int K = kMaxDfHalfWidth;
     for (int j = 0; j <= 2 * m; ++j) o.w[j] = w.w[2 * K - (2 * m - j)];
-    return o;
-}
-
-// Pad the weights of half-width m into the ring layout of capacity M.
-DfWeights repad(const DfWeights &w, int m, int M)
-{
-    DfWeights o{};
-    // w.w[j] is given for capacity kMaxDfHalfWidth: ring index j <-> lag 2K - j
-    const int K = kMaxDfHalfWidth;
-    for (int lag = 0; lag <= 2 * m; ++lag) o.w[2 * M - lag] = w.w[2 * K - lag];
     return o;
 }
 
@@ -1157,17 +1158,18 @@ hipError_t launch_df(const float *fz, int nz, int ny, int nx, int m, const DfWei
                      float *df, hipStream_t stream)
 {
     const size_t plane = (size_t)nx * ny;
+    const int n_out = nz - 2 * m;
+    if (plane == 0 || n_out <= 0) return hipSuccess;
     dim3 block(256, 1, 1);
-    dim3 grid((unsigned)((plane + 255) / 256), 1, 1);
+    const int chunks = (n_out + kDfChunk - 1) / kDfChunk;
+    dim3 grid((unsigned)((plane + 255) / 256), (unsigned)(chunks < 65535 ? chunks : 65535), 1);
+    const DfWeights sw = sample_weights(w, m);   // zero beyond 2m
     if (m <= 8)
-        hipLaunchKernelGGL((df_kernel<8>), grid, block, 0, stream, fz, nz, ny, nx, m,
-                           repad(w, m, 8), df);
+        hipLaunchKernelGGL((df_kernel<8>), grid, block, 0, stream, fz, nz, ny, nx, m, sw, df);
     else if (m <= 16)
-        hipLaunchKernelGGL((df_kernel<16>), grid, block, 0, stream, fz, nz, ny, nx, m,
-                           repad(w, m, 16), df);
+        hipLaunchKernelGGL((df_kernel<16>), grid, block, 0, stream, fz, nz, ny, nx, m, sw, df);
     else
-        hipLaunchKernelGGL((df_kernel<32>), grid, block, 0, stream, fz, nz, ny, nx, m,
-                           repad(w, m, 32), df);
+        hipLaunchKernelGGL((df_kernel<32>), grid, block, 0, stream, fz, nz, ny, nx, m, sw, df);
     return hipGetLastError();
 }
 
