@@ -12,8 +12,8 @@
 // cell corner, recomputed here; the gradient of the grid is never stored.
 //
 // Kernels:
-//  1. adjoint_solve: one lane per tip column walks its heights with a register
-//     ring of grad_df, gathers the eight corners of the relaxed point's cell,
+//  1. adjoint_solve: one lane per relaxed point (tip column and height) forms
+//     its grad_df tap sum, gathers the eight corners of the point's cell,
 //     builds J (trilinear cell Jacobian + spring Jacobian, FP64), solves the
 //     3x3 transposed system and writes mu, the cell and its fractions.
 //  2. atom_scatter: one lane per atom, one block of four waves per chunk of
@@ -52,18 +52,18 @@ __global__ __launch_bounds__(kTX * kTY) void adjoint_solve_kernel(
     const size_t col = (size_t)iy * a.snx + ix;
     const double ax = a.x0 + ix * a.sdx, ay = a.y0 + iy * a.sdy;
 
-    // ring[j] = grad_df of output s - (2M - j); gbar_s = sum_j wts.w[j] ring[j]
-    float ring[2 * M + 1];
-#pragma unroll
-    for (int j = 0; j < 2 * M + 1; ++j) ring[j] = 0.0f;
-
-    for (int s = 0; s < a.snz; ++s) {
-#pragma unroll
-        for (int j = 0; j < 2 * M; ++j) ring[j] = ring[j + 1];
-        ring[2 * M] = (s < a.ndf) ? grad_df[(size_t)s * plane + col] : 0.0f;
+    // one point (column, height s) per lane; heights blockIdx.z, + gridDim.z, ...
+    // gbar_s = sum_j wts.w[j] grad_df(s - (2M - j)) in j order, the terms of
+    // outputs outside 0 .. ndf-1 and of zero weight (j < 2M - 2m) being zero
+    for (int s = (int)blockIdx.z; s < a.snz; s += (int)gridDim.z) {
         float gbar = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2 * M + 1; ++j) gbar = fmaf(wts.w[j], ring[j], gbar);
+        for (int j = 0; j < 2 * M + 1; ++j) {
+            const int so = s - (2 * M - j);
+            const float g = (j >= 2 * M - 2 * a.m && so >= 0 && so < a.ndf)
+                                ? grad_df[(size_t)so * plane + col] : 0.0f;
+            gbar = fmaf(wts.w[j], g, gbar);
+        }
 
         const size_t o = (size_t)s * plane + col;
         const float4 st = pp[o];
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
 DfWeights repad_lag(const DfWeights &w, int m, int M)
 {
     // input: forward layout of capacity K (W[2K - lag] = weight of lag);
-    // output: V[j] = weight of lag 2m - (2M - j) for the grad_df ring.
+    // output: V[j] = weight of lag 2m - (2M - j) for the grad_df taps.
     DfWeights o{};
     const int K = kMaxDfHalfWidth;
     for (int j = 2 * M - 2 * m; j <= 2 * M; ++j) {
@@ -587,7 +587,8 @@ hipError_t launch_backward(const BwdArgs &A, const DfWeights &w, const float4 *f
 {
     EqRecord *rec = reinterpret_cast<EqRecord *>(eq_ws);
     dim3 blk(kTX, kTY, 1);
-    dim3 grd((A.s.snx + kTX - 1) / kTX, (A.s.sny + kTY - 1) / kTY, 1);
+    dim3 grd((A.s.snx + kTX - 1) / kTX, (A.s.sny + kTY - 1) / kTY,
+             (unsigned)(A.s.snz < 65535 ? A.s.snz : 65535));
     const int m = A.s.m;
     if (m <= 8)
         hipLaunchKernelGGL((adjoint_solve_kernel<8>), grd, blk, 0, stream, A, repad_lag(w, m, 8),
