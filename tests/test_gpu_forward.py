@@ -327,6 +327,20 @@ def test_df_standalone_random_stacks(A, dz, nz):
     np.testing.assert_allclose(got, ref, atol=2e-5 * np.abs(ref).max() + 1e-6)
 
 
+def test_df_standalone_stack_beyond_the_chunk_grid():
+    """A stack of more than 65,535 chunks of 16 outputs: the pass caps its grid
+    in y and its blocks take a second chunk."""
+    dz, dfp = 0.1, W.DfParams(A=1.0)
+    m = ppm.df_half_width(dfp.A, dz)
+    nz = 65535 * 16 + 2 * m + 37
+    rng = np.random.default_rng(65535)
+    fz = rng.normal(0, 0.05, size=(nz, 1, 3)).astype(np.float32)
+    got = ppm.df(torch.as_tensor(fz, device="cuda"), dz, dfp).cpu().numpy()
+    ref = orc.df(fz.astype(np.float64), dz, dfp)
+    assert got.shape == ref.shape == (nz - 2 * m, 1, 3)
+    np.testing.assert_allclose(got, ref, atol=2e-5 * np.abs(ref).max() + 1e-6)
+
+
 @pytest.mark.parametrize("nz", [1, 2])
 def test_scan_single_column(nz):
     """A lattice of one column: its block has one active lane beside 255 idle
