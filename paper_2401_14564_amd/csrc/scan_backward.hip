@@ -278,8 +278,15 @@ __global__ __launch_bounds__(64 * kScatterWaves) void atom_scatter_kernel(
 {
     __shared__ float s_m[3][kCellCap];
     __shared__ float4 s_u[kCellCap];          // merged voxels: (m, packed local x, y, z)
-    __shared__ EqRecord s_rec[kChPts];
-    __shared__ int s_tag[kCellCap];           // merge: last lane to hit a voxel
+    // The chunk's records and the merge tags share s_u's storage: wave 0 writes
+    // s_u only after its merge has read them for the last time (a wave's LDS
+    // operations complete in order), and the per-point path, which reads the
+    // records after the barrier, writes no s_u.  (28.7 KB per block: five
+    // blocks per CU instead of four.)
+    EqRecord *const s_rec = reinterpret_cast<EqRecord *>(s_u);                // [kChPts]
+    int *const s_tag = reinterpret_cast<int *>(s_rec + kChPts);               // [kCellCap]
+    static_assert(kChPts * sizeof(EqRecord) + kCellCap * sizeof(int) <= sizeof(s_u),
+                  "records and tags fit in s_u");
     __shared__ int s_box[8];                  // lo[3], bx, by, bz, n, flags
     const ScanArgs &a = A.s;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
